@@ -1,0 +1,255 @@
+/*
+ * gosurf.h - C ABI of the GO-Surf optimisation hot path for MI355X (gfx950).
+ *
+ * One optimisation iteration of GO-Surf (Wang, Bleja, Agapito 2022) over a
+ * dense multi-level feature grid is four asynchronous calls on one HIP stream:
+ *
+ *   gosurf_sample_rays  rays from all pixels of all frames and the points along
+ *                       them (Sec. 3.2 "Depth and Color Rendering", Sec. 3.5),
+ *                       plus the smoothness points and perturbations (Sec. 3.4)
+ *   gosurf_forward      grid interpolation (Sec. 3.1, Eq. SDF_MLP), decoders,
+ *                       volume rendering (Eqs. volume_rendering,
+ *                       volume_rendering_alpha) and the six loss terms with
+ *                       their weighted total (Sec. 3.3-3.5)
+ *   gosurf_backward     exact gradients of that total with respect to every
+ *                       grid feature and decoder parameter, including the
+ *                       second-order grid-sampler blocks that the Eikonal and
+ *                       smoothness terms need (supplementary "Second-order Grid
+ *                       Sampler", Eqs. second_sdf_grad_theta, second_sdf_grad_omega)
+ *   gosurf_adam_step    Adam over all parameters (implementation details)
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All array pointers are DEVICE pointers to caller-owned memory, contiguous,
+ *   row-major, float32 unless stated.  The library allocates nothing on these
+ *   paths; scratch memory is a caller-supplied workspace sized by
+ *   gosurf_workspace_bytes().
+ * - Every call only validates its arguments on the host and enqueues kernels
+ *   on `stream` (a hipStream_t; NULL = the default stream).  It returns
+ *   GOSURF_OK or an error status and never blocks.  Device faults surface at
+ *   the caller's next synchronisation.  On error nothing has been enqueued
+ *   and gosurf_last_error() (thread-local) describes the problem.
+ * - No C++ exception crosses this interface.  Calls are re-entrant; calls that
+ *   share output or workspace buffers must be ordered by the caller.
+ *
+ * Grid layout (Sec. 3.1; readings stated where the paper is silent)
+ * -----------------------------------------------------------------
+ * GOSURF_LEVELS = 4 levels, coarsest first (z = [V^0 .. V^3]), 4 features per
+ * vertex (h_g = 4).  All levels share the box [p0, p1].  Level l has voxel
+ * edge voxel[l] and dims[l] = (nx, ny, nz) vertices; vertex (i, j, k) of level
+ * l is row offset[l] + (k*ny + j)*nx + i of the concatenated float32 table
+ * grid[n_vertices][4] (16-byte aligned).  Interpolation uses the eight
+ * vertices of the cell with origin clamp(floor((x - p0)/voxel), 0, n - 2) and
+ * the supplementary's coefficient vector (bit order theta_xyz).  A point
+ * outside [p0, p1] (decided in float32 on o + t*r, product and sum rounded
+ * separately) is masked: it has no SDF, the opacities of both intervals that
+ * touch it are 0 and it receives no loss and no gradient.
+ *
+ * Decoder parameters: one float32 vector of GOSURF_MLP_NUMEL entries, each
+ * matrix row-major [out][in]:
+ *   W1[32][16] b1[32] W2[32][32] b2[32] W3[16][32] b3[16]    geometry 16-32-32-16
+ *   U1[32][15] c1[32] U2[3][32] c2[3]                        colour   15-32-3
+ *   v[1]                                                     sharpness s = exp(10 v)
+ * Hidden layers use ReLU (derivative 0 at 0); output 0 of the geometry decoder
+ * is the SDF, outputs 1..15 feed the colour decoder, whose output is a sigmoid.
+ */
+#ifndef GOSURF_H
+#define GOSURF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GOSURF_LEVELS 4
+#define GOSURF_FEAT 4
+#define GOSURF_MLP_NUMEL 2740
+#define GOSURF_MAX_SAMPLES_PER_RAY 256
+#define GOSURF_N_LOSSES 8
+
+typedef enum {
+  GOSURF_OK = 0,
+  GOSURF_ERR_NULL = 1,       /* a required pointer is NULL */
+  GOSURF_ERR_SHAPE = 2,      /* a size is out of range or inconsistent */
+  GOSURF_ERR_ALIGN = 3,      /* a pointer is not suitably aligned */
+  GOSURF_ERR_VALUE = 4,      /* a scalar argument is invalid (NaN, <= 0, ...) */
+  GOSURF_ERR_WORKSPACE = 5,  /* workspace missing or smaller than required */
+  GOSURF_ERR_HIP = 6         /* a kernel launch failed */
+} gosurf_status;
+
+typedef enum { GOSURF_FP32 = 0, GOSURF_BF16 = 1 } gosurf_precision;
+typedef enum { GOSURF_SPAN_FIXED = 0, GOSURF_SPAN_BOX = 1 } gosurf_span_mode;
+
+/* Geometry of the grid (see "Grid layout" above). */
+typedef struct {
+  float p0[3];                        /* box minimum (world units, metres) */
+  float p1[3];                        /* box maximum */
+  float voxel[GOSURF_LEVELS];         /* voxel edge per level, coarsest first */
+  int32_t dims[GOSURF_LEVELS][3];     /* (nx, ny, nz) per level, each >= 2 */
+  int64_t offset[GOSURF_LEVELS];      /* first vertex row of each level */
+  int64_t n_vertices;                 /* rows of the concatenated table */
+  int32_t precision;                  /* gosurf_precision of decoders and grid reads */
+} gosurf_model;
+
+/* Parameters read by forward/backward. */
+typedef struct {
+  const float* grid;          /* [n_vertices][4] float32 master features */
+  const uint16_t* grid_bf16;  /* [n_vertices][4] bfloat16 mirror; required for GOSURF_BF16 */
+  const float* mlp;           /* [GOSURF_MLP_NUMEL] decoder parameters and v */
+} gosurf_params;
+
+/* An RGB-D sequence {I_t, D_t} with camera-to-world poses (Sec. 3, first para.). */
+typedef struct {
+  const uint8_t* rgb;   /* [T][H][W][3] */
+  const float* depth;   /* [T][H][W], z-depth in metres, <= 0 means missing */
+  const float* c2w;     /* [T][4][4] camera-to-world, OpenCV camera axes */
+  int32_t T, H, W;
+  float fx, fy, cx, cy; /* pinhole intrinsics; pixel (u, v) looks along
+                           R [(u + .5 - cx)/fx, (v + .5 - cy)/fy, 1] */
+} gosurf_frames;
+
+/* How a batch is drawn.  Every random number is Philox4x32-10 keyed by `seed`
+   with counter (index, step, stream, block): stream 0 picks the pixel
+   (floor(u32 * T*H*W / 2^32)), 1 the stratified jitter, 2 the near-depth
+   jitter, 3 the smoothness points; u = (u32 >> 8) * 2^-24. */
+typedef struct {
+  int32_t M;            /* rays, >= 1 */
+  int32_t n_strat;      /* stratified samples per ray over the span, >= 1 */
+  int32_t n_near;       /* extra samples on [D - trunc, D + trunc] for rays with depth */
+  int32_t span_mode;    /* GOSURF_SPAN_FIXED: [near, far]; GOSURF_SPAN_BOX: the
+                           ray's passage through the grid box, clipped to [near, far] */
+  float near_t, far_t;  /* span limits (ray parameter = camera z-depth) */
+  float trunc;          /* truncation t of the SDF terms (metres) */
+  int32_t S;            /* smoothness pairs, >= 0 */
+  float delta_s;        /* perturbation length (metres) */
+  uint64_t seed;
+  uint32_t step;
+} gosurf_sample_cfg;
+
+/* A ray batch.  Written by gosurf_sample_rays, read by forward/backward.
+   Samples are stored ray-major: the samples of ray m are
+   t[seg[m] .. seg[m+1]-1], sorted ascending, at most
+   GOSURF_MAX_SAMPLES_PER_RAY per ray; ray_of[s] is the ray of sample s. */
+typedef struct {
+  int32_t M;            /* rays */
+  int32_t total;        /* samples, = seg[M] */
+  int32_t S;            /* smoothness pairs */
+  float* o;             /* [M][3] ray origin (camera centre) */
+  float* r;             /* [M][3] ray direction (camera-z component 1) */
+  float* rgb;           /* [M][3] observed colour in [0, 1] */
+  float* depth;         /* [M] observed depth, 0 = missing */
+  float* t;             /* [total] sample depths along the ray */
+  int32_t* seg;         /* [M + 1] CSR offsets */
+  int32_t* ray_of;      /* [total] */
+  float* xs;            /* [S][3] smoothness points */
+  float* eps;           /* [S][3] perturbations; the pair is (x, x + eps rounded to float32) */
+  int64_t* pixel;       /* [M] flat pixel index of each ray (output only; may be NULL) */
+} gosurf_ray_batch;
+
+/* Loss configuration (Sec. 3.3-3.5 and implementation details). */
+typedef struct {
+  float lambda[6];      /* weights of rgb, depth, sdf, free-space, Eikonal, smoothness */
+  float trunc;          /* truncation t: S_tr = {|D - d| <= t}, S_fs = {D - d > t} */
+  float alpha_fs;       /* exponent of the free-space term (5) */
+} gosurf_loss_cfg;
+
+/* Forward outputs.  losses[] = {L_rgb, L_d, L_sdf, L_fs, L_eik, L_smooth,
+   weighted total, number of rays with valid depth}.  `saved` holds what the
+   backward needs and must be passed to it unchanged. */
+typedef struct {
+  float* rgb_hat;       /* [M][3] rendered colour */
+  float* depth_hat;     /* [M] rendered depth */
+  float* wsum;          /* [M] sum of the ray's weights */
+  float* losses;        /* [GOSURF_N_LOSSES] */
+  float* saved;         /* [total][4]: phi, colour per sample; then [total] eik residual */
+  float* weights;       /* [total] per-sample weights w_i, or NULL */
+} gosurf_fwd_out;
+
+/* Gradient accumulators (caller zeroes them once; Adam re-zeroes them). */
+typedef struct {
+  float* grid;          /* [n_vertices][4] */
+  float* mlp;           /* [GOSURF_MLP_NUMEL] */
+} gosurf_grads;
+
+typedef struct {
+  float lr_grid;        /* 1e-2 in the paper */
+  float lr_mlp;         /* 1e-3 in the paper (decoders and v) */
+  float beta1, beta2, eps;
+  int32_t step;         /* 1-based Adam step */
+  float inv_loss_scale; /* gradients are multiplied by this before use */
+} gosurf_adam_cfg;
+
+/* Parameters, gradients and Adam moments of both groups. */
+typedef struct {
+  float* grid; float* grid_grad; float* grid_m; float* grid_v;
+  uint16_t* grid_bf16;  /* refreshed bfloat16 mirror of grid, or NULL */
+  int64_t grid_numel;   /* multiple of 4 */
+  float* mlp; float* mlp_grad; float* mlp_m; float* mlp_v;
+  int32_t mlp_numel;    /* multiple of 4 */
+} gosurf_adam_state;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* gosurf_last_error(void);
+
+/* Number of samples one ray batch drawn with `cfg` holds (M * (n_strat + n_near)). */
+int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg);
+
+/* Draw a ray batch (Sec. 3.2, 3.4, 3.5).  `out` arrays must be sized for
+   cfg->M rays, gosurf_batch_samples(cfg) samples and cfg->S pairs; out->M,
+   out->total and out->S are set by the caller to those sizes.  Pixels are
+   drawn uniformly from all pixels of all frames, including those without
+   depth.  Rays with depth get n_strat stratified samples over the span and
+   n_near stratified samples on [D - trunc, D + trunc], merged in order
+   (stratified first on ties); rays without depth get n_strat + n_near
+   stratified samples.  A smoothness point tries up to 8 pixels and keeps the
+   first with depth, at depth D + (2u - 1) trunc along its ray; eps is delta_s
+   times a uniform unit vector; with no valid pixel the point is the box
+   centre with eps = 0.  Errors: NULL, SHAPE (sizes, T*H*W >= 2^32), VALUE. */
+gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames* frames,
+                                 const gosurf_sample_cfg* cfg, gosurf_ray_batch* out,
+                                 void* stream);
+
+/* Workspace bytes needed by forward/backward for a batch of these sizes. */
+size_t gosurf_workspace_bytes(const gosurf_model* model, int32_t M, int32_t total, int32_t S);
+
+/* Forward pass and loss (Sec. 3.1-3.5).  Per-ray opacities
+   alpha_i = max(1 - Phi_s(phi_{i+1}) / Phi_s(phi_i), 0), alpha_last = 0,
+   w_i = T_i alpha_i; colour/depth = sum w_i c_i / sum w_i t_i.  Loss terms:
+   L_rgb = mean over rays of the channel-mean |I - c_hat|; L_d = mean over rays
+   with depth of |D - d_hat|; L_sdf, L_fs, L_eik = (1/M) sum over rays of the
+   per-ray mean over S_tr / S_fs (empty: 0) of |phi - b|,
+   max(0, e^{-alpha phi} - 1, phi - b), (1 - |grad phi|)^2 with b = D - t; only
+   rays with depth have S_tr and S_fs, and membership is decided in float32;
+   L_smooth = (1/S) sum over pairs of |grad phi(x) - grad phi(x + eps)|^2
+   (a pair leaving the box contributes 0).  A term whose weight lambda is 0 is
+   not evaluated and reported as 0.  Errors: NULL, SHAPE, VALUE, WORKSPACE,
+   HIP. */
+gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* params,
+                             const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
+                             gosurf_fwd_out* out, void* workspace, size_t workspace_bytes,
+                             void* stream);
+
+/* Backward pass: ADDS loss_scale * d(total)/d(params) into grads.  Must follow
+   the gosurf_forward call that produced `fwd` with the same params, batch,
+   loss config and workspace.  Grid gradients are accumulated with float32
+   atomics (summation order varies between runs); decoder gradients are
+   reduced in a fixed order.  Errors: NULL, SHAPE, VALUE, WORKSPACE, HIP. */
+gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* params,
+                              const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
+                              const gosurf_fwd_out* fwd, float loss_scale, gosurf_grads* grads,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Adam (Kingma & Ba) with bias correction over both groups, dense: every
+   entry is updated, touched or not.  g = grad * inv_loss_scale;
+   m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+   p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+   Gradients are zeroed and the bfloat16 mirror (if any) refreshed in the same
+   pass.  Errors: NULL, SHAPE, ALIGN, VALUE, HIP. */
+gosurf_status gosurf_adam_step(const gosurf_adam_cfg* cfg, gosurf_adam_state* state, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GOSURF_H */

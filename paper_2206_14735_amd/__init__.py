@@ -1,0 +1,8 @@
+"""GO-Surf optimisation hot path for MI355X (gfx950).
+
+``gosurf``  - ctypes binding of the C ABI in include/gosurf.h (libgosurf.so)
+``train``   - a driver that owns parameters, gradients, Adam state and
+              workspace on the device and runs sample -> forward -> backward
+              -> Adam steps through the library
+``build``   - compiles libgosurf.so in-tree with hipcc for gfx950
+"""

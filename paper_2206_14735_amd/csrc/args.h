@@ -1,0 +1,88 @@
+// Kernel argument blocks (passed by value to the kernels).
+#pragma once
+#include "device.h"
+
+namespace gs {
+
+constexpr int kChunks = GOSURF_MAX_SAMPLES_PER_RAY / 64;
+
+struct FieldArgs {
+  Grid g;
+  const float* grid;
+  const float* mlp;
+  // ray samples
+  const float* o;
+  const float* r;
+  const float* t;
+  const int* ray_of;
+  int total;
+  // smoothness pairs
+  const float* xs;
+  const float* eps;
+  int S;
+  // forward outputs
+  float* out4;            // [total][4] phi, c
+  float* eik;             // [total] (1 - |grad phi|)^2
+  float* smooth_partial;  // [gridDim.x]
+  // backward
+  const float* seed4;     // [total][4] dL/dphi, dL/dc (scaled)
+  const float* eikw;      // [total] Eikonal weight (scaled), 0 outside S_fs
+  float smooth_coef;      // 2 * lambda_smooth * loss_scale / S
+  float* grad_grid;       // [V][4]
+  float* mlp_partial;     // [gridDim.x][kMlpNumel]
+  int need_gx;            // ray mode: compute grad phi for the Eikonal term
+};
+
+struct RenderArgs {
+  Grid g;
+  const float* o;
+  const float* r;
+  const float* rgb;
+  const float* depth;
+  const float* t;
+  const int* seg;
+  int M;
+  const float* mlp;
+  const float* out4;    // [total][4]
+  const float* eik;     // [total] or null
+  float trunc, alpha_fs;
+  float lam[6];
+  // forward outputs
+  float* rgb_hat;
+  float* depth_hat;
+  float* wsum;
+  float* weights;       // or null
+  float* ray_partial;   // [M][8]
+  // backward
+  const float* n_depth_rays;  // device scalar (losses[7])
+  float loss_scale;
+  float* seed4;         // [total][4]
+  float* eikw;          // [total]
+  float* ray_dv;        // [M]
+};
+
+struct SampleArgs {
+  Grid g;
+  const uint8_t* rgb;
+  const float* depth;
+  const float* c2w;
+  int T, H, W;
+  float fx, fy, cx, cy;
+  int M, n_strat, n_near, span_mode;
+  float near_t, far_t, trunc;
+  int S;
+  float delta_s;
+  uint32_t k0, k1, step;
+  float* o;
+  float* r;
+  float* rgb_out;
+  float* depth_out;
+  float* t;
+  int* seg;
+  int* ray_of;
+  float* xs;
+  float* eps;
+  long long* pixel;
+};
+
+}  // namespace gs

@@ -1,0 +1,336 @@
+// C ABI of the GO-Surf hot path: host-side validation, workspace layout and
+// kernel launches.  Every entry point validates on the host, enqueues on the
+// caller's stream and returns without synchronising.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "device.h"
+
+#include "args.h"
+
+namespace gs {
+
+hipError_t launch_field(const FieldArgs& a, int mode, bool bwd, int blocks, hipStream_t st);
+int field_blocks(int n_items, int per_tile);
+hipError_t launch_render(const RenderArgs& a, bool bwd, hipStream_t st);
+hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smooth_partial, int n_sp, int S,
+                              const float lam[6], float* losses, hipStream_t st);
+hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
+                              hipStream_t st);
+hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st);
+hipError_t launch_sample(const SampleArgs& a, hipStream_t st);
+
+}  // namespace gs
+
+namespace {
+
+thread_local std::string g_err;
+
+gosurf_status fail(gosurf_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+gosurf_status fail(gosurf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+gosurf_status ok() {
+  g_err.clear();
+  return GOSURF_OK;
+}
+
+gosurf_status hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(GOSURF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  return GOSURF_OK;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+gosurf_status check_model(const gosurf_model* m) {
+  if (!m) return fail(GOSURF_ERR_NULL, "model is NULL");
+  if (m->precision != GOSURF_FP32 && m->precision != GOSURF_BF16)
+    return fail(GOSURF_ERR_VALUE, "precision %d is not GOSURF_FP32 or GOSURF_BF16", m->precision);
+  long long rows = 0;
+  for (int l = 0; l < GOSURF_LEVELS; ++l) {
+    if (!(m->voxel[l] > 0.f) || !std::isfinite(m->voxel[l]))
+      return fail(GOSURF_ERR_VALUE, "voxel[%d] must be positive and finite", l);
+    for (int a = 0; a < 3; ++a)
+      if (m->dims[l][a] < 2) return fail(GOSURF_ERR_SHAPE, "dims[%d][%d] = %d < 2", l, a, m->dims[l][a]);
+    const long long n = (long long)m->dims[l][0] * m->dims[l][1] * m->dims[l][2];
+    if (m->offset[l] < 0 || m->offset[l] + n > m->n_vertices)
+      return fail(GOSURF_ERR_SHAPE, "level %d rows [%lld, %lld) exceed n_vertices %lld", l,
+                  (long long)m->offset[l], (long long)(m->offset[l] + n), (long long)m->n_vertices);
+    rows += n;
+  }
+  if (m->n_vertices * 4 >= (1LL << 40)) return fail(GOSURF_ERR_SHAPE, "grid too large");
+  for (int a = 0; a < 3; ++a)
+    if (!(m->p1[a] > m->p0[a])) return fail(GOSURF_ERR_VALUE, "box is empty along axis %d", a);
+  (void)rows;
+  return GOSURF_OK;
+}
+
+gs::Grid to_grid(const gosurf_model* m) {
+  gs::Grid g;
+  for (int a = 0; a < 3; ++a) { g.p0[a] = m->p0[a]; g.p1[a] = m->p1[a]; }
+  for (int l = 0; l < 4; ++l) {
+    g.voxel[l] = m->voxel[l];
+    g.nx[l] = m->dims[l][0];
+    g.ny[l] = m->dims[l][1];
+    g.nz[l] = m->dims[l][2];
+    g.off[l] = m->offset[l];
+  }
+  return g;
+}
+
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Workspace {
+  float* ray_partial;     // [M][8]
+  float* smooth_partial;  // [1024]
+  float* seed4;           // [total][4]
+  float* eikw;            // [total]
+  float* ray_dv;          // [M]
+  float* mlp_partial;     // [2048][kMlpNumel]
+  size_t bytes;
+};
+
+Workspace layout(char* base, int M, int total, int S) {
+  (void)S;
+  Workspace w{};
+  size_t off = 0;
+  auto take = [&](size_t n) { char* p = base ? base + off : nullptr; off += up(n); return p; };
+  w.ray_partial = reinterpret_cast<float*>(take(sizeof(float) * 8 * (size_t)M));
+  w.smooth_partial = reinterpret_cast<float*>(take(sizeof(float) * 1024));
+  w.seed4 = reinterpret_cast<float*>(take(sizeof(float) * 4 * (size_t)total));
+  w.eikw = reinterpret_cast<float*>(take(sizeof(float) * (size_t)total));
+  w.ray_dv = reinterpret_cast<float*>(take(sizeof(float) * (size_t)M));
+  w.mlp_partial = reinterpret_cast<float*>(take(sizeof(float) * 2048 * (size_t)gs::kMlpNumel));
+  w.bytes = off;
+  return w;
+}
+
+gosurf_status check_batch(const gosurf_ray_batch* b, bool need_outputs) {
+  if (!b) return fail(GOSURF_ERR_NULL, "batch is NULL");
+  if (b->M < 1) return fail(GOSURF_ERR_SHAPE, "batch M = %d < 1", b->M);
+  if (b->total < b->M) return fail(GOSURF_ERR_SHAPE, "batch total = %d < M", b->total);
+  if ((long long)b->total * 4 >= (1LL << 31)) return fail(GOSURF_ERR_SHAPE, "too many samples (%d)", b->total);
+  if (b->S < 0) return fail(GOSURF_ERR_SHAPE, "S = %d < 0", b->S);
+  if (!b->o || !b->r || !b->rgb || !b->depth || !b->t || !b->seg || !b->ray_of)
+    return fail(GOSURF_ERR_NULL, "a ray-batch array is NULL");
+  if (b->S > 0 && (!b->xs || !b->eps)) return fail(GOSURF_ERR_NULL, "smoothness arrays are NULL");
+  (void)need_outputs;
+  return GOSURF_OK;
+}
+
+gosurf_status check_loss(const gosurf_loss_cfg* l) {
+  if (!l) return fail(GOSURF_ERR_NULL, "loss config is NULL");
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(l->lambda[k]) || l->lambda[k] < 0.f)
+      return fail(GOSURF_ERR_VALUE, "lambda[%d] must be finite and >= 0", k);
+  if (!(l->trunc > 0.f) || !std::isfinite(l->trunc)) return fail(GOSURF_ERR_VALUE, "trunc must be > 0");
+  if (!std::isfinite(l->alpha_fs)) return fail(GOSURF_ERR_VALUE, "alpha_fs must be finite");
+  return GOSURF_OK;
+}
+
+gosurf_status check_params(const gosurf_model* m, const gosurf_params* p) {
+  if (!p) return fail(GOSURF_ERR_NULL, "params is NULL");
+  if (!p->grid || !p->mlp) return fail(GOSURF_ERR_NULL, "params.grid / params.mlp is NULL");
+  if (!aligned(p->grid, 16)) return fail(GOSURF_ERR_ALIGN, "params.grid must be 16-byte aligned");
+  if (m->precision == GOSURF_BF16) {
+    if (!p->grid_bf16) return fail(GOSURF_ERR_NULL, "params.grid_bf16 is required for GOSURF_BF16");
+    if (!aligned(p->grid_bf16, 8)) return fail(GOSURF_ERR_ALIGN, "params.grid_bf16 must be 8-byte aligned");
+  }
+  return GOSURF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gosurf_last_error(void) { return g_err.c_str(); }
+
+int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg) {
+  if (!cfg) return -1;
+  return (int64_t)cfg->M * (int64_t)(cfg->n_strat + cfg->n_near);
+}
+
+size_t gosurf_workspace_bytes(const gosurf_model* model, int32_t M, int32_t total, int32_t S) {
+  (void)model;
+  if (M < 0 || total < 0 || S < 0) return 0;
+  return layout(nullptr, M, total, S).bytes;
+}
+
+gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames* fr, const gosurf_sample_cfg* c,
+                                 gosurf_ray_batch* out, void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if (!fr || !c || !out) return fail(GOSURF_ERR_NULL, "frames, cfg and out must not be NULL");
+  if (!fr->rgb || !fr->depth || !fr->c2w) return fail(GOSURF_ERR_NULL, "frame arrays must not be NULL");
+  if (fr->T < 1 || fr->H < 1 || fr->W < 1) return fail(GOSURF_ERR_SHAPE, "frames must be non-empty");
+  const unsigned long long thw = (unsigned long long)fr->T * fr->H * fr->W;
+  if (thw >= (1ULL << 32)) return fail(GOSURF_ERR_SHAPE, "T*H*W = %llu must be < 2^32", thw);
+  if (!(fr->fx > 0.f) || !(fr->fy > 0.f)) return fail(GOSURF_ERR_VALUE, "focal lengths must be > 0");
+  if (c->M < 1 || c->n_strat < 1 || c->n_near < 0 || c->S < 0)
+    return fail(GOSURF_ERR_SHAPE, "need M >= 1, n_strat >= 1, n_near >= 0, S >= 0");
+  if (c->n_strat + c->n_near > GOSURF_MAX_SAMPLES_PER_RAY)
+    return fail(GOSURF_ERR_SHAPE, "n_strat + n_near = %d exceeds %d", c->n_strat + c->n_near,
+                GOSURF_MAX_SAMPLES_PER_RAY);
+  const long long total = (long long)c->M * (c->n_strat + c->n_near);
+  if (total * 4 >= (1LL << 31)) return fail(GOSURF_ERR_SHAPE, "too many samples (%lld)", total);
+  if (out->M != c->M || out->total != total || out->S != c->S)
+    return fail(GOSURF_ERR_SHAPE, "out sizes (M=%d total=%d S=%d) do not match cfg (M=%d total=%lld S=%d)",
+                out->M, out->total, out->S, c->M, total, c->S);
+  if (c->span_mode != GOSURF_SPAN_FIXED && c->span_mode != GOSURF_SPAN_BOX)
+    return fail(GOSURF_ERR_VALUE, "unknown span_mode %d", c->span_mode);
+  if (!(c->far_t >= c->near_t) || !std::isfinite(c->near_t))
+    return fail(GOSURF_ERR_VALUE, "need finite near <= far");
+  if (!(c->trunc > 0.f) || c->delta_s < 0.f) return fail(GOSURF_ERR_VALUE, "need trunc > 0, delta_s >= 0");
+  if (!out->o || !out->r || !out->rgb || !out->depth || !out->t || !out->seg || !out->ray_of)
+    return fail(GOSURF_ERR_NULL, "an output array is NULL");
+  if (c->S > 0 && (!out->xs || !out->eps)) return fail(GOSURF_ERR_NULL, "smoothness outputs are NULL");
+  gs::SampleArgs a{};
+  a.g = to_grid(model);
+  a.rgb = fr->rgb; a.depth = fr->depth; a.c2w = fr->c2w;
+  a.T = fr->T; a.H = fr->H; a.W = fr->W;
+  a.fx = fr->fx; a.fy = fr->fy; a.cx = fr->cx; a.cy = fr->cy;
+  a.M = c->M; a.n_strat = c->n_strat; a.n_near = c->n_near; a.span_mode = c->span_mode;
+  a.near_t = c->near_t; a.far_t = c->far_t; a.trunc = c->trunc; a.S = c->S; a.delta_s = c->delta_s;
+  a.k0 = (uint32_t)(c->seed & 0xffffffffu); a.k1 = (uint32_t)(c->seed >> 32); a.step = c->step;
+  a.o = out->o; a.r = out->r; a.rgb_out = out->rgb; a.depth_out = out->depth; a.t = out->t;
+  a.seg = out->seg; a.ray_of = out->ray_of; a.xs = out->xs; a.eps = out->eps;
+  a.pixel = reinterpret_cast<long long*>(out->pixel);
+  if ((st = hip_check(gs::launch_sample(a, (hipStream_t)stream), "sample_kernel")) != GOSURF_OK) return st;
+  return ok();
+}
+
+gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* params, const gosurf_ray_batch* b,
+                             const gosurf_loss_cfg* loss, gosurf_fwd_out* out, void* ws, size_t ws_bytes,
+                             void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if ((st = check_params(model, params)) != GOSURF_OK) return st;
+  if ((st = check_batch(b, false)) != GOSURF_OK) return st;
+  if ((st = check_loss(loss)) != GOSURF_OK) return st;
+  if (!out || !out->rgb_hat || !out->depth_hat || !out->wsum || !out->losses || !out->saved)
+    return fail(GOSURF_ERR_NULL, "a forward output array is NULL");
+  if (!aligned(out->saved, 16)) return fail(GOSURF_ERR_ALIGN, "out.saved must be 16-byte aligned");
+  if (model->precision != GOSURF_FP32)
+    return fail(GOSURF_ERR_VALUE, "this build implements the GOSURF_FP32 decoders only");
+  const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
+  if (!ws || ws_bytes < w.bytes)
+    return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                w.bytes);
+  hipStream_t s = (hipStream_t)stream;
+  const gs::Grid g = to_grid(model);
+  const bool need_gx = loss->lambda[4] != 0.f;
+  float* eik = out->saved + 4 * (size_t)b->total;
+
+  gs::FieldArgs fa{};
+  fa.g = g; fa.grid = params->grid; fa.mlp = params->mlp;
+  fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
+  fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S;
+  fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
+  if ((st = hip_check(gs::launch_field(fa, 0, false, gs::field_blocks(b->total, 16), s), "field fwd")) != GOSURF_OK)
+    return st;
+  int n_sp = 0;
+  if (b->S > 0 && loss->lambda[5] != 0.f) {
+    n_sp = gs::field_blocks(2 * b->S, 16);
+    if ((st = hip_check(gs::launch_field(fa, 1, false, n_sp, s), "smoothness fwd")) != GOSURF_OK) return st;
+  }
+  gs::RenderArgs ra{};
+  ra.g = g; ra.o = b->o; ra.r = b->r; ra.rgb = b->rgb; ra.depth = b->depth; ra.t = b->t; ra.seg = b->seg;
+  ra.M = b->M; ra.mlp = params->mlp; ra.out4 = out->saved; ra.eik = need_gx ? eik : nullptr;
+  ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs;
+  for (int k = 0; k < 6; ++k) ra.lam[k] = loss->lambda[k];
+  ra.rgb_hat = out->rgb_hat; ra.depth_hat = out->depth_hat; ra.wsum = out->wsum; ra.weights = out->weights;
+  ra.ray_partial = w.ray_partial;
+  if ((st = hip_check(gs::launch_render(ra, false, s), "render fwd")) != GOSURF_OK) return st;
+  if ((st = hip_check(gs::launch_loss_reduce(w.ray_partial, b->M, w.smooth_partial, n_sp, b->S, loss->lambda,
+                                             out->losses, s),
+                      "loss reduce")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
+gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* params, const gosurf_ray_batch* b,
+                              const gosurf_loss_cfg* loss, const gosurf_fwd_out* fwd, float loss_scale,
+                              gosurf_grads* grads, void* ws, size_t ws_bytes, void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if ((st = check_params(model, params)) != GOSURF_OK) return st;
+  if ((st = check_batch(b, false)) != GOSURF_OK) return st;
+  if ((st = check_loss(loss)) != GOSURF_OK) return st;
+  if (!fwd || !fwd->saved || !fwd->losses) return fail(GOSURF_ERR_NULL, "forward outputs are NULL");
+  if (!grads || !grads->grid || !grads->mlp) return fail(GOSURF_ERR_NULL, "gradient buffers are NULL");
+  if (!aligned(grads->grid, 16)) return fail(GOSURF_ERR_ALIGN, "grads.grid must be 16-byte aligned");
+  if (!(loss_scale > 0.f) || !std::isfinite(loss_scale)) return fail(GOSURF_ERR_VALUE, "loss_scale must be > 0");
+  if (model->precision != GOSURF_FP32)
+    return fail(GOSURF_ERR_VALUE, "this build implements the GOSURF_FP32 decoders only");
+  const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
+  if (!ws || ws_bytes < w.bytes)
+    return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                w.bytes);
+  hipStream_t s = (hipStream_t)stream;
+  const gs::Grid g = to_grid(model);
+  const bool need_gx = loss->lambda[4] != 0.f;
+
+  gs::RenderArgs ra{};
+  ra.g = g; ra.o = b->o; ra.r = b->r; ra.rgb = b->rgb; ra.depth = b->depth; ra.t = b->t; ra.seg = b->seg;
+  ra.M = b->M; ra.mlp = params->mlp; ra.out4 = fwd->saved; ra.eik = nullptr;
+  ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs;
+  for (int k = 0; k < 6; ++k) ra.lam[k] = loss->lambda[k];
+  ra.n_depth_rays = fwd->losses + 7;
+  ra.loss_scale = loss_scale; ra.seed4 = w.seed4; ra.eikw = w.eikw; ra.ray_dv = w.ray_dv;
+  if ((st = hip_check(gs::launch_render(ra, true, s), "render bwd")) != GOSURF_OK) return st;
+
+  gs::FieldArgs fa{};
+  fa.g = g; fa.grid = params->grid; fa.mlp = params->mlp;
+  fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
+  fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S;
+  fa.seed4 = w.seed4; fa.eikw = w.eikw; fa.need_gx = need_gx;
+  fa.grad_grid = grads->grid; fa.mlp_partial = w.mlp_partial;
+  fa.smooth_coef = b->S > 0 ? 2.f * loss->lambda[5] * loss_scale / (float)b->S : 0.f;
+  const int nbr = gs::field_blocks(b->total, 16);
+  if ((st = hip_check(gs::launch_field(fa, 0, true, nbr, s), "field bwd")) != GOSURF_OK) return st;
+  int nbs = 0;
+  if (b->S > 0 && loss->lambda[5] != 0.f) {
+    nbs = gs::field_blocks(2 * b->S, 16);
+    fa.mlp_partial = w.mlp_partial + (size_t)nbr * gs::kMlpNumel;
+    if ((st = hip_check(gs::launch_field(fa, 1, true, nbs, s), "smoothness bwd")) != GOSURF_OK) return st;
+  }
+  if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nbr + nbs, w.ray_dv, b->M, grads->mlp, s),
+                      "grad reduce")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
+gosurf_status gosurf_adam_step(const gosurf_adam_cfg* c, gosurf_adam_state* s, void* stream) {
+  if (!c || !s) return fail(GOSURF_ERR_NULL, "cfg and state must not be NULL");
+  if (!s->grid || !s->grid_grad || !s->grid_m || !s->grid_v || !s->mlp || !s->mlp_grad || !s->mlp_m || !s->mlp_v)
+    return fail(GOSURF_ERR_NULL, "an Adam array is NULL");
+  if (s->grid_numel < 0 || s->grid_numel % 4 || s->mlp_numel < 0 || s->mlp_numel % 4)
+    return fail(GOSURF_ERR_SHAPE, "group sizes must be non-negative multiples of 4");
+  const void* ptrs[] = {s->grid, s->grid_grad, s->grid_m, s->grid_v, s->mlp, s->mlp_grad, s->mlp_m, s->mlp_v};
+  for (const void* p : ptrs)
+    if (!aligned(p, 16)) return fail(GOSURF_ERR_ALIGN, "Adam arrays must be 16-byte aligned");
+  if (s->grid_bf16 && !aligned(s->grid_bf16, 8)) return fail(GOSURF_ERR_ALIGN, "grid_bf16 must be 8-byte aligned");
+  if (c->step < 1) return fail(GOSURF_ERR_VALUE, "step must be >= 1");
+  if (!(c->beta1 >= 0.f && c->beta1 < 1.f && c->beta2 >= 0.f && c->beta2 < 1.f))
+    return fail(GOSURF_ERR_VALUE, "betas must lie in [0, 1)");
+  if (!(c->eps > 0.f) || !std::isfinite(c->lr_grid) || !std::isfinite(c->lr_mlp) ||
+      !std::isfinite(c->inv_loss_scale))
+    return fail(GOSURF_ERR_VALUE, "eps must be > 0 and rates finite");
+  gosurf_status st;
+  gosurf_adam_state copy = *s;
+  if ((st = hip_check(gs::launch_adam(*c, copy, (hipStream_t)stream), "adam")) != GOSURF_OK) return st;
+  return ok();
+}
+
+}  // extern "C"

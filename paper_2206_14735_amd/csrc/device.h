@@ -1,0 +1,103 @@
+// Device helpers shared by the gfx950 kernels of the GO-Surf hot path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gosurf.h"
+
+namespace gs {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+constexpr int kTile = 16;          // samples per wave-tile (one 16-wide MFMA column block)
+constexpr int kBlock = 256;        // threads per block of the field kernels (4 waves)
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// ---------------------------------------------------------------- packed decoder offsets
+// W1[32][16] b1[32] W2[32][32] b2[32] W3[16][32] b3[16] U1[32][15] c1[32] U2[3][32] c2[3] v[1]
+constexpr int oW1 = 0, oB1 = 512, oW2 = 544, oB2 = 1568, oW3 = 1600, oB3 = 2112;
+constexpr int oU1 = 2128, oC1 = 2608, oU2 = 2640, oC2 = 2736, oV = 2739, kMlpNumel = 2740;
+static_assert(kMlpNumel == GOSURF_MLP_NUMEL, "decoder layout");
+
+// ---------------------------------------------------------------- grid description (by value)
+struct Grid {
+  float p0[3], p1[3];
+  float voxel[4];
+  int nx[4], ny[4], nz[4];
+  long long off[4];   // first vertex row of each level
+};
+
+// ---------------------------------------------------------------- Philox4x32-10 (Salmon et al. SC'11)
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+// ---------------------------------------------------------------- exact-rounding helpers
+// o + t*r with the product and the sum rounded separately (no contraction),
+// so that the box test takes the same decision as a plain float32 evaluation.
+__device__ __forceinline__ float mad_norm(float t, float r, float o) {
+  return __fadd_rn(__fmul_rn(t, r), o);
+}
+
+__device__ __forceinline__ bool inside_box(const Grid& g, float x, float y, float z) {
+  return x >= g.p0[0] && x <= g.p1[0] && y >= g.p0[1] && y <= g.p1[1] && z >= g.p0[2] &&
+         z <= g.p1[2];
+}
+
+// ---------------------------------------------------------------- numerics
+__device__ __forceinline__ float log_sigmoid(float x) {
+  // log(1 / (1 + e^-x)) = -softplus(-x), evaluated without overflow
+  return x >= 0.f ? -log1pf(__expf(-x)) : x - log1pf(__expf(x));
+}
+__device__ __forceinline__ float sigmoidf_(float x) {
+  return x >= 0.f ? 1.f / (1.f + __expf(-x)) : __expf(x) / (1.f + __expf(x));
+}
+__device__ __forceinline__ float signf_(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ---------------------------------------------------------------- MFMA (CDNA3/4 16x16x4 fp32)
+// D[16x16] += A[16x4] B[4x16].  Lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// the result holds D[4*(l/16) + r][l%16] in component r.
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// bf16 16x16x16: lane l supplies A[l%16][4(l/16)+0..3] and B[4(l/16)+0..3][l%16].
+__device__ __forceinline__ v4f mfma16_bf16(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace gs

@@ -1,0 +1,574 @@
+// Fused per-sample field kernels: multi-level trilinear gather, geometry and
+// colour decoders on MFMA, d(phi)/dx, and (backward) decoder weight gradients,
+// the double backward of the gradient terms and the grid scatter.
+//
+// Work decomposition (one wave = 64 lanes):
+//   a wave-tile is 16 consecutive samples; lane l serves sample l % 16 and
+//   grid level q = l / 16.  Each lane gathers only its level's 8 corners, and
+//   the 16-d feature z lands directly in the B-operand layout of the
+//   16x16x4 MFMA (lane q holds rows 4q..4q+3 = level q's four features).
+//   Decoder activations stay in MFMA accumulator layout between layers
+//   ([neuron][sample], lane (q, j) holds rows 16b + 4q + r of sample j), so
+//   layers chain in registers; weights are pre-arranged per lane in LDS.
+//   Weight gradients (sums over samples) are MFMAs with the sample axis as K;
+//   their operands are transposed through a small per-wave LDS scratch.
+#include "args.h"
+
+namespace gs {
+
+// ---------------------------------------------------------------- A-operand tables in LDS
+// slot = table base + out_block * (4 * in_blocks) + step; 64 floats per slot.
+enum : int {
+  T_L1 = 0,    // W1       out 32 (2 blk), in 16 (1 blk)
+  T_L2 = 8,    // W2       out 32, in 32
+  T_L3 = 24,   // W3       out 16, in 32
+  T_C1 = 32,   // U1       out 32, in o-index 16 (row 0 = phi -> 0)
+  T_C2 = 40,   // U2       out 16 (rows 0..2), in 32
+  T_C2T = 48,  // U2^T     out 32, in 16 (rows 0..2)
+  T_C1T = 56,  // U1^T     out o-index 16, in 32
+  T_L3T = 64,  // W3^T     out 32, in 16
+  T_L2T = 72,  // W2^T     out 32, in 32
+  T_L1T = 88,  // W1^T     out 16, in 32
+  T_END = 96
+};
+
+__device__ float table_value(const float* __restrict__ P, int slot, int l) {
+  int tb, nbi;
+  if (slot < T_L2) { tb = T_L1; nbi = 1; }
+  else if (slot < T_L3) { tb = T_L2; nbi = 2; }
+  else if (slot < T_C1) { tb = T_L3; nbi = 2; }
+  else if (slot < T_C2) { tb = T_C1; nbi = 1; }
+  else if (slot < T_C2T) { tb = T_C2; nbi = 2; }
+  else if (slot < T_C1T) { tb = T_C2T; nbi = 1; }
+  else if (slot < T_L3T) { tb = T_C1T; nbi = 2; }
+  else if (slot < T_L2T) { tb = T_L3T; nbi = 1; }
+  else if (slot < T_L1T) { tb = T_L2T; nbi = 2; }
+  else { tb = T_L1T; nbi = 2; }
+  int rel = slot - tb;
+  int bo = rel / (4 * nbi), s = rel % (4 * nbi);
+  int i = 16 * bo + (l & 15);                       // output row
+  int k = 16 * (s >> 2) + 4 * (l >> 4) + (s & 3);   // input row
+  switch (tb) {
+    case T_L1: return P[oW1 + i * 16 + k];
+    case T_L2: return P[oW2 + i * 32 + k];
+    case T_L3: return P[oW3 + i * 32 + k];
+    case T_C1: return k >= 1 ? P[oU1 + i * 15 + (k - 1)] : 0.f;
+    case T_C2: return i < 3 ? P[oU2 + i * 32 + k] : 0.f;
+    case T_C2T: return k < 3 ? P[oU2 + k * 32 + i] : 0.f;
+    case T_C1T: return i >= 1 ? P[oU1 + k * 15 + (i - 1)] : 0.f;
+    case T_L3T: return P[oW3 + k * 32 + i];
+    case T_L2T: return P[oW2 + k * 32 + i];
+    default: return P[oW1 + k * 16 + i];
+  }
+}
+
+// out[bo] = sum over input blocks/steps of A(slot) * in   (NBO output blocks of 16 rows)
+template <int NBO, int NBI>
+__device__ __forceinline__ void layer(const float* __restrict__ tab, int base, const v4f* in, v4f* out,
+                                      int lane) {
+#pragma unroll
+  for (int bo = 0; bo < NBO; ++bo) out[bo] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int bo = 0; bo < NBO; ++bo)
+        out[bo] = mfma4(tab[(base + bo * 4 * NBI + bi * 4 + r) * 64 + lane], in[bi][r], out[bo]);
+}
+
+// LDS scratch row stride for transposed [sample][row] tiles
+constexpr int RS = 36;
+
+template <int NB>
+__device__ __forceinline__ void store_T(float* scr, const v4f* X, int q, int j) {
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) scr[j * RS + 16 * b + 4 * q + r] = X[b][r];
+}
+
+// acc[ba][bb] += sum over the tile's 16 samples of A[16ba + i][s] * B[16bb + j][s]
+template <int NA, int NB>
+__device__ __forceinline__ void outer_acc(float* scrA, float* scrB, const v4f* A, const v4f* B, v4f* acc,
+                                          int q, int j) {
+  store_T<NA>(scrA, A, q, j);
+  store_T<NB>(scrB, B, q, j);
+  wave_lds_fence();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    float av[NA], bv[NB];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) av[a] = scrA[(4 * m + q) * RS + 16 * a + j];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bv[b] = scrB[(4 * m + q) * RS + 16 * b + j];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[a * NB + b] = mfma4(av[a], bv[b], acc[a * NB + b]);
+  }
+  wave_lds_fence();
+}
+
+
+// per-lane gather state of one level
+struct LevelSample {
+  float f[3];
+  long long row;   // corner 000
+  int sy, sz;      // row strides of +y, +z corners
+  float inv_v;
+};
+
+__device__ __forceinline__ void locate(const Grid& g, int q, float x, float y, float z, LevelSample& ls) {
+  const float xyz[3] = {x, y, z};
+  const int n[3] = {g.nx[q], g.ny[q], g.nz[q]};
+  const float v = g.voxel[q];
+  int i0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float u = (xyz[a] - g.p0[a]) / v;
+    int c = (int)floorf(u);
+    c = c < 0 ? 0 : (c > n[a] - 2 ? n[a] - 2 : c);
+    i0[a] = c;
+    ls.f[a] = u - (float)c;
+  }
+  ls.sy = n[0];
+  ls.sz = n[0] * n[1];
+  ls.row = g.off[q] + ((long long)i0[2] * n[1] + i0[1]) * n[0] + i0[0];
+  ls.inv_v = 1.f / v;
+}
+
+// trilinear value (z) and, optionally, dz/dx (G[k][axis]) of one level
+template <bool NEED_G>
+__device__ __forceinline__ void interp(const float* __restrict__ grid, const LevelSample& ls, bool valid,
+                                       float z[4], float G[4][3]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) { z[k] = 0.f; G[k][0] = G[k][1] = G[k][2] = 0.f; }
+  if (!valid) return;
+  const float fx = ls.f[0], fy = ls.f[1], fz = ls.f[2];
+  float4 th[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+    const long long row = ls.row + bx + (long long)by * ls.sy + (long long)bz * ls.sz;
+    th[c] = *reinterpret_cast<const float4*>(grid + row * 4);
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+    const float wx = bx ? fx : 1.f - fx, wy = by ? fy : 1.f - fy, wz = bz ? fz : 1.f - fz;
+    const float w = wx * wy * wz;
+    const float tv[4] = {th[c].x, th[c].y, th[c].z, th[c].w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z[k] += w * tv[k];
+    if (NEED_G) {
+      const float jx = (bx ? 1.f : -1.f) * wy * wz, jy = (by ? 1.f : -1.f) * wx * wz,
+                  jz = (bz ? 1.f : -1.f) * wx * wy;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        G[k][0] += jx * tv[k];
+        G[k][1] += jy * tv[k];
+        G[k][2] += jz * tv[k];
+      }
+    }
+  }
+  if (NEED_G) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { G[k][0] *= ls.inv_v; G[k][1] *= ls.inv_v; G[k][2] *= ls.inv_v; }
+  }
+}
+
+// grid scatter: dL/dtheta_c,k = w_c dz_k + a_k (J_c . gvec) / v
+template <bool HAS_DZ, bool HAS_GV>
+__device__ __forceinline__ void scatter(float* __restrict__ grad, const LevelSample& ls, const float dz[4],
+                                        const float a[4], const float gv[3]) {
+  const float fx = ls.f[0], fy = ls.f[1], fz = ls.f[2];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+    const float wx = bx ? fx : 1.f - fx, wy = by ? fy : 1.f - fy, wz = bz ? fz : 1.f - fz;
+    float jg = 0.f;
+    if (HAS_GV) {
+      const float jx = (bx ? 1.f : -1.f) * wy * wz, jy = (by ? 1.f : -1.f) * wx * wz,
+                  jz = (bz ? 1.f : -1.f) * wx * wy;
+      jg = (jx * gv[0] + jy * gv[1] + jz * gv[2]) * ls.inv_v;
+    }
+    const float w = wx * wy * wz;
+    const long long row = ls.row + bx + (long long)by * ls.sy + (long long)bz * ls.sz;
+    float* p = grad + row * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float val = 0.f;
+      if (HAS_DZ) val += w * dz[k];
+      if (HAS_GV) val += a[k] * jg;
+      atomicAdd(p + k, val);
+    }
+  }
+}
+
+__device__ __forceinline__ v4f relu_mask(v4f x, v4f h) {
+  return v4f{h[0] > 0.f ? x[0] : 0.f, h[1] > 0.f ? x[1] : 0.f, h[2] > 0.f ? x[2] : 0.f,
+             h[3] > 0.f ? x[3] : 0.f};
+}
+
+__device__ __forceinline__ float sum16(float v) {   // over the 16 lanes of one level group
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  v += __shfl_xor(v, 8, 64);
+  return v;
+}
+
+// LDS footprint of one block
+struct FieldSmem {
+  float tab[T_END * 64];
+  float bias[32 + 32 + 16 + 32 + 16];   // b1, b2, b3, c1, c2(pad 16)
+  float w3row0[32];
+  float scr[kWavesPerBlock][2][16 * RS];
+};
+constexpr int kRedFloats = kWavesPerBlock * kMlpNumel;
+constexpr int kSmemBytes = (sizeof(FieldSmem) > kRedFloats * 4) ? sizeof(FieldSmem) : kRedFloats * 4;
+
+// MODE 0: ray samples; MODE 1: smoothness pairs (16-lane tile = 8 pairs: lanes
+// j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).
+template <int MODE, bool BWD>
+__global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  FieldSmem& sm = *reinterpret_cast<FieldSmem*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
+
+  for (int e = tid; e < T_END * 64; e += kBlock) sm.tab[e] = table_value(A.mlp, e >> 6, e & 63);
+  if (tid < 32) {
+    sm.bias[tid] = A.mlp[oB1 + tid];
+    sm.bias[32 + tid] = A.mlp[oB2 + tid];
+    sm.bias[80 + tid] = A.mlp[oC1 + tid];
+    sm.w3row0[tid] = A.mlp[oW3 + tid];
+  }
+  if (tid < 16) {
+    sm.bias[64 + tid] = A.mlp[oB3 + tid];
+    sm.bias[112 + tid] = tid < 3 ? A.mlp[oC2 + tid] : 0.f;
+  }
+  __syncthreads();
+  const float* tab = sm.tab;
+  float* scrA = sm.scr[wave][0];
+  float* scrB = sm.scr[wave][1];
+
+  const bool need_g = (MODE == 1) || A.need_gx;
+  const int n_items = MODE == 0 ? A.total : 2 * A.S;   // lanes of work
+  const int per_tile = MODE == 0 ? 16 : 16;
+  const int n_tiles = (n_items + per_tile - 1) / per_tile;
+
+  // accumulators (backward)
+  v4f aW1[2], aW2[4], aW3[2], aU1[2], aU2[2];
+  v4f gB1[2], gB2[2], gB3, gC1[2], gC2, gW3r0[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    aW1[b] = aW3[b] = aU1[b] = aU2[b] = gB1[b] = gB2[b] = gC1[b] = gW3r0[b] = v4f{0, 0, 0, 0};
+    aW2[b] = aW2[b + 2] = v4f{0, 0, 0, 0};
+  }
+  gB3 = gC2 = v4f{0, 0, 0, 0};
+  float smooth_acc = 0.f;
+
+  for (int tile = blockIdx.x * kWavesPerBlock + wave; tile < n_tiles; tile += gridDim.x * kWavesPerBlock) {
+    // ---------------- sample position
+    int item;
+    float px, py, pz;
+    bool live;
+    if (MODE == 0) {
+      item = tile * 16 + j;
+      live = item < A.total;
+      px = py = pz = 0.f;
+      if (live) {
+        const int ray = A.ray_of[item];
+        const float tt = A.t[item];
+        px = mad_norm(tt, A.r[3 * ray + 0], A.o[3 * ray + 0]);
+        py = mad_norm(tt, A.r[3 * ray + 1], A.o[3 * ray + 1]);
+        pz = mad_norm(tt, A.r[3 * ray + 2], A.o[3 * ray + 2]);
+      }
+    } else {
+      const int pair = tile * 8 + (j & 7);
+      item = pair;
+      live = pair < A.S;
+      px = py = pz = 0.f;
+      if (live) {
+        px = A.xs[3 * pair + 0];
+        py = A.xs[3 * pair + 1];
+        pz = A.xs[3 * pair + 2];
+        if (j >= 8) {
+          px = __fadd_rn(px, A.eps[3 * pair + 0]);
+          py = __fadd_rn(py, A.eps[3 * pair + 1]);
+          pz = __fadd_rn(pz, A.eps[3 * pair + 2]);
+        }
+      }
+    }
+    const bool valid = live && inside_box(A.g, px, py, pz);
+    LevelSample ls;
+    locate(A.g, q, px, py, pz, ls);
+    float zl[4], G[4][3];
+    if (need_g) interp<true>(A.grid, ls, valid, zl, G);
+    else interp<false>(A.grid, ls, valid, zl, G);
+
+    // ---------------- geometry decoder
+    v4f zb = v4f{zl[0], zl[1], zl[2], zl[3]};
+    v4f h1[2], h2[2], ob, hc[2], cb;
+    layer<2, 1>(tab, T_L1, &zb, h1, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h1[b][r] = fmaxf(h1[b][r] + sm.bias[16 * b + 4 * q + r], 0.f);
+    layer<2, 2>(tab, T_L2, h1, h2, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h2[b][r] = fmaxf(h2[b][r] + sm.bias[32 + 16 * b + 4 * q + r], 0.f);
+    layer<1, 2>(tab, T_L3, h2, &ob, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ob[r] += sm.bias[64 + 4 * q + r];
+
+    // ---------------- colour decoder (ray mode)
+    if (MODE == 0) {
+      layer<2, 1>(tab, T_C1, &ob, hc, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) hc[b][r] = fmaxf(hc[b][r] + sm.bias[80 + 16 * b + 4 * q + r], 0.f);
+      layer<1, 2>(tab, T_C2, hc, &cb, lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cb[r] = sigmoidf_(cb[r] + sm.bias[112 + 4 * q + r]);
+    }
+
+    // ---------------- d phi / d x
+    v4f e2[2], e1[2], ab;
+    float gx[3] = {0.f, 0.f, 0.f};
+    if (need_g) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) e2[b][r] = h2[b][r] > 0.f ? sm.w3row0[16 * b + 4 * q + r] : 0.f;
+      layer<2, 2>(tab, T_L2T, e2, e1, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) e1[b] = relu_mask(e1[b], h1[b]);
+      layer<1, 2>(tab, T_L1T, e1, &ab, lane);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float v = ab[0] * G[0][a] + ab[1] * G[1][a] + ab[2] * G[2][a] + ab[3] * G[3][a];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        gx[a] = v;
+      }
+    }
+
+    if (!BWD) {
+      if (MODE == 0) {
+        if (q == 0 && live) {
+          *reinterpret_cast<float4*>(A.out4 + 4 * (size_t)item) = make_float4(ob[0], cb[0], cb[1], cb[2]);
+          if (A.need_gx) {
+            const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
+            A.eik[item] = (1.f - n) * (1.f - n);
+          }
+        }
+      } else {
+        // pair partner is lane j ^ 8 of the same level group
+        float d0 = gx[0] - __shfl_xor(gx[0], 8, 64);
+        float d1 = gx[1] - __shfl_xor(gx[1], 8, 64);
+        float d2 = gx[2] - __shfl_xor(gx[2], 8, 64);
+        const bool pv = valid && __shfl_xor((int)valid, 8, 64);
+        if (q == 0 && j < 8 && pv) smooth_acc += d0 * d0 + d1 * d1 + d2 * d2;
+      }
+      continue;
+    }
+
+    // ================================================================ backward
+    float gv[3] = {0.f, 0.f, 0.f};   // dL / d(grad phi)
+    if (MODE == 0) {
+      float4 sd = make_float4(0.f, 0.f, 0.f, 0.f);
+      float ew = 0.f;
+      if (live && valid) {
+        sd = *reinterpret_cast<const float4*>(A.seed4 + 4 * (size_t)item);
+        if (A.need_gx) ew = A.eikw[item];
+      }
+      if (A.need_gx && ew != 0.f) {
+        const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
+        const float c = n > 0.f ? ew * 2.f * (n - 1.f) / n : 0.f;
+        gv[0] = c * gx[0]; gv[1] = c * gx[1]; gv[2] = c * gx[2];
+      }
+      // colour: dL/d(pre-sigmoid) for rows 0..2 held by level-group 0
+      v4f dc2 = v4f{0, 0, 0, 0};
+      if (q == 0) {
+        dc2[0] = sd.y * cb[0] * (1.f - cb[0]);
+        dc2[1] = sd.z * cb[1] * (1.f - cb[1]);
+        dc2[2] = sd.w * cb[2] * (1.f - cb[2]);
+      }
+      v4f dhc[2], dob;
+      layer<2, 1>(tab, T_C2T, &dc2, dhc, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) dhc[b] = relu_mask(dhc[b], hc[b]);
+      layer<1, 2>(tab, T_C1T, dhc, &dob, lane);
+      if (q == 0) dob[0] += sd.x;
+      v4f dh2[2], dh1[2], dz;
+      layer<2, 1>(tab, T_L3T, &dob, dh2, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) dh2[b] = relu_mask(dh2[b], h2[b]);
+      layer<2, 2>(tab, T_L2T, dh2, dh1, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) dh1[b] = relu_mask(dh1[b], h1[b]);
+      layer<1, 2>(tab, T_L1T, dh1, &dz, lane);
+
+      // weight gradients (sum over the tile's samples)
+      outer_acc<1, 2>(scrA, scrB, &dc2, hc, aU2, q, j);
+      outer_acc<2, 1>(scrA, scrB, dhc, &ob, aU1, q, j);
+      outer_acc<1, 2>(scrA, scrB, &dob, h2, aW3, q, j);
+      outer_acc<2, 2>(scrA, scrB, dh2, h1, aW2, q, j);
+      outer_acc<2, 1>(scrA, scrB, dh1, &zb, aW1, q, j);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        gB1[b] += dh1[b];
+        gB2[b] += dh2[b];
+        gC1[b] += dhc[b];
+      }
+      gB3 += dob;
+      gC2 += dc2;
+
+      const float dzl[4] = {dz[0], dz[1], dz[2], dz[3]};
+      if (A.need_gx) {
+        // second-order terms of the Eikonal residual
+        v4f qv;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) qv[k] = gv[0] * G[k][0] + gv[1] * G[k][1] + gv[2] * G[k][2];
+        v4f r1[2], w2r1[2];
+        layer<2, 1>(tab, T_L1, &qv, r1, lane);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
+        layer<2, 2>(tab, T_L2, r1, w2r1, lane);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) gW3r0[b] += relu_mask(w2r1[b], h2[b]);
+        outer_acc<2, 2>(scrA, scrB, e2, r1, aW2, q, j);
+        outer_acc<2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
+        const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
+        if (valid) scatter<true, true>(A.grad_grid, ls, dzl, al, gv);
+      } else {
+        const float al[4] = {0, 0, 0, 0};
+        if (valid) scatter<true, false>(A.grad_grid, ls, dzl, al, gv);
+      }
+    } else {
+      // smoothness pair: d|g(x) - g(x+eps)|^2 / dg at either point is
+      // 2 (own gradient - partner's gradient); smooth_coef carries the 2.
+      const bool pv = valid && __shfl_xor((int)valid, 8, 64);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float d = gx[a] - __shfl_xor(gx[a], 8, 64);
+        gv[a] = pv ? A.smooth_coef * d : 0.f;
+      }
+      v4f qv;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) qv[k] = gv[0] * G[k][0] + gv[1] * G[k][1] + gv[2] * G[k][2];
+      v4f r1[2], w2r1[2];
+      layer<2, 1>(tab, T_L1, &qv, r1, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
+      layer<2, 2>(tab, T_L2, r1, w2r1, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) gW3r0[b] += relu_mask(w2r1[b], h2[b]);
+      outer_acc<2, 2>(scrA, scrB, e2, r1, aW2, q, j);
+      outer_acc<2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
+      const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
+      const float dzl[4] = {0, 0, 0, 0};
+      if (pv) scatter<false, true>(A.grad_grid, ls, dzl, al, gv);
+    }
+  }
+
+  if (!BWD) {
+    if (MODE == 1) {
+      // block partial of the smoothness sum (fixed order: lanes, then waves)
+      float v = wave_sum(smooth_acc);
+      __syncthreads();
+      float* red = reinterpret_cast<float*>(smem_raw);
+      if (lane == 0) red[wave] = v;
+      __syncthreads();
+      if (tid == 0) {
+        float s = 0.f;
+        for (int w = 0; w < kWavesPerBlock; ++w) s += red[w];
+        A.smooth_partial[blockIdx.x] = s;
+      }
+    }
+    return;
+  }
+
+  // ---------------- block partial of the decoder gradients (deterministic)
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(smem_raw) + wave * kMlpNumel;
+  for (int e = lane; e < kMlpNumel; e += 64) red[e] = 0.f;
+  wave_lds_fence();
+#pragma unroll
+  for (int ba = 0; ba < 2; ++ba)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * ba + 4 * q + r;
+      red[oW1 + row * 16 + j] = aW1[ba][r];
+      red[oW2 + row * 32 + j] = aW2[ba * 2 + 0][r];
+      red[oW2 + row * 32 + 16 + j] = aW2[ba * 2 + 1][r];
+      if (j >= 1) red[oU1 + row * 15 + j - 1] = aU1[ba][r];
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 4 * q + r;
+    float w3a = aW3[0][r], w3b = aW3[1][r];
+    red[oW3 + row * 32 + j] = w3a;
+    red[oW3 + row * 32 + 16 + j] = w3b;
+    if (row < 3) {
+      red[oU2 + row * 32 + j] = aU2[0][r];
+      red[oU2 + row * 32 + 16 + j] = aU2[1][r];
+    }
+  }
+  wave_lds_fence();
+  // bias gradients and the W3 row-0 term: sums over the 16 sample lanes
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * b + 4 * q + r;
+      const float s1 = sum16(gB1[b][r]), s2 = sum16(gB2[b][r]), s3 = sum16(gC1[b][r]), s4 = sum16(gW3r0[b][r]);
+      if (j == 0) {
+        red[oB1 + row] = s1;
+        red[oB2 + row] = s2;
+        red[oC1 + row] = s3;
+        red[oW3 + row] += s4;
+      }
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float s1 = sum16(gB3[r]), s2 = sum16(gC2[r]);
+    const int row = 4 * q + r;
+    if (j == 0) {
+      red[oB3 + row] = s1;
+      if (row < 3) red[oC2 + row] = s2;
+    }
+  }
+  __syncthreads();
+  const float* red0 = reinterpret_cast<const float*>(smem_raw);
+  float* out = A.mlp_partial + (size_t)blockIdx.x * kMlpNumel;
+  for (int e = tid; e < kMlpNumel; e += kBlock) {
+    float s = 0.f;
+    for (int w = 0; w < kWavesPerBlock; ++w) s += red0[w * kMlpNumel + e];
+    out[e] = s;
+  }
+}
+
+int field_blocks(int n_items, int per_tile) {
+  const int tiles = (n_items + per_tile - 1) / per_tile;
+  int blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > 1024) blocks = 1024;
+  return blocks < 1 ? 1 : blocks;
+}
+
+hipError_t launch_field(const FieldArgs& a, int mode, bool bwd, int blocks, hipStream_t st) {
+  const size_t smem = kSmemBytes;
+  if (mode == 0 && !bwd) hipLaunchKernelGGL((field_kernel<0, false>), dim3(blocks), dim3(kBlock), smem, st, a);
+  else if (mode == 0) hipLaunchKernelGGL((field_kernel<0, true>), dim3(blocks), dim3(kBlock), smem, st, a);
+  else if (!bwd) hipLaunchKernelGGL((field_kernel<1, false>), dim3(blocks), dim3(kBlock), smem, st, a);
+  else hipLaunchKernelGGL((field_kernel<1, true>), dim3(blocks), dim3(kBlock), smem, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,408 @@
+// Per-ray volume rendering, loss terms and their backward seeds.
+//
+// One wave owns one ray: lane k holds samples k, k+64, k+128, k+192, so every
+// per-sample array is read coalesced.  The transmittance is an exclusive
+// product scan over the ray and the backward recurrence of the opacities is a
+// suffix scan of affine maps, both with cross-lane shuffles.
+#include "args.h"
+
+namespace gs {
+
+
+
+struct RayState {
+  int n, s0;
+  float s;              // sharpness
+  float D, I[3];
+  float phi[kChunks], tt[kChunks], col[kChunks][3];
+  bool valid[kChunks];
+  float alpha[kChunks], T[kChunks], w[kChunks];
+  float c_hat[3], d_hat, wsum;
+};
+
+__device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane, RayState& R) {
+  R.s0 = A.seg[m];
+  R.n = A.seg[m + 1] - R.s0;
+  R.s = __expf(10.f * A.mlp[oV]);
+  const float ox = A.o[3 * m], oy = A.o[3 * m + 1], oz = A.o[3 * m + 2];
+  const float rx = A.r[3 * m], ry = A.r[3 * m + 1], rz = A.r[3 * m + 2];
+  R.D = A.depth[m];
+  R.I[0] = A.rgb[3 * m]; R.I[1] = A.rgb[3 * m + 1]; R.I[2] = A.rgb[3 * m + 2];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const int k = 64 * c + lane;
+    R.valid[c] = false;
+    R.phi[c] = 0.f; R.tt[c] = 0.f;
+    R.col[c][0] = R.col[c][1] = R.col[c][2] = 0.f;
+    if (k < R.n) {
+      const int sidx = R.s0 + k;
+      const float tt = A.t[sidx];
+      R.tt[c] = tt;
+      const float px = mad_norm(tt, rx, ox), py = mad_norm(tt, ry, oy), pz = mad_norm(tt, rz, oz);
+      R.valid[c] = inside_box(A.g, px, py, pz);
+      if (R.valid[c]) {
+        const float4 v = *reinterpret_cast<const float4*>(A.out4 + 4 * (size_t)sidx);
+        R.phi[c] = v.x; R.col[c][0] = v.y; R.col[c][1] = v.z; R.col[c][2] = v.w;
+      }
+    }
+  }
+  // opacities: alpha_k uses sample k+1 (next lane, or lane 0 of the next chunk).
+  // 1 - Phi(b)/Phi(a) = Phi(-b) * (1 - e^{-(a - b)}) with a = s phi_k, b = s phi_{k+1}:
+  // no difference of nearly equal logarithms, so small opacities keep their
+  // relative accuracy.
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    float nphi = __shfl_down(R.phi[c], 1, 64);
+    int nval = __shfl_down((int)R.valid[c], 1, 64);
+    if (c + 1 < kChunks) {
+      const float p0 = __shfl(R.phi[c + 1], 0, 64);
+      const int v0 = __shfl((int)R.valid[c + 1], 0, 64);
+      if (lane == 63) { nphi = p0; nval = v0; }
+    } else if (lane == 63) {
+      nval = 0;
+    }
+    const int k = 64 * c + lane;
+    float a = 0.f;
+    if (R.valid[c] && nval && k + 1 < R.n && nphi < R.phi[c]) {
+      a = sigmoidf_(-R.s * nphi) * -expm1f(R.s * (nphi - R.phi[c]));
+    }
+    R.alpha[c] = a;
+  }
+  // transmittance: exclusive product of (1 - alpha)
+  float carry = 1.f;
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    float v = 1.f - R.alpha[c];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const float u = __shfl_up(v, d, 64);
+      if (lane >= d) v *= u;
+    }
+    float ex = __shfl_up(v, 1, 64);
+    if (lane == 0) ex = 1.f;
+    R.T[c] = carry * ex;
+    carry *= __shfl(v, 63, 64);
+    R.w[c] = R.T[c] * R.alpha[c];
+  }
+  float cr = 0.f, cg = 0.f, cbl = 0.f, dd = 0.f, ws = 0.f;
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    cr += R.w[c] * R.col[c][0];
+    cg += R.w[c] * R.col[c][1];
+    cbl += R.w[c] * R.col[c][2];
+    dd += R.w[c] * R.tt[c];
+    ws += R.w[c];
+  }
+  R.c_hat[0] = wave_sum(cr);
+  R.c_hat[1] = wave_sum(cg);
+  R.c_hat[2] = wave_sum(cbl);
+  R.d_hat = wave_sum(dd);
+  R.wsum = wave_sum(ws);
+}
+
+__global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= A.M) return;
+  RayState R;
+  ray_forward(A, m, lane, R);
+  const bool has_d = R.D > 0.f;
+  float sdf = 0.f, fs = 0.f, ek = 0.f, ntr = 0.f, nfs = 0.f;
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const int k = 64 * c + lane;
+    if (A.weights && k < R.n) A.weights[R.s0 + k] = R.w[c];
+    if (!(R.valid[c] && has_d)) continue;
+    const float b = R.D - R.tt[c];
+    if (fabsf(b) <= A.trunc) {
+      sdf += fabsf(R.phi[c] - b);
+      ntr += 1.f;
+    } else if (b > A.trunc) {
+      const float e = __expf(-A.alpha_fs * R.phi[c]) - 1.f;
+      fs += fmaxf(fmaxf(0.f, e), R.phi[c] - b);
+      if (A.eik) ek += A.eik[R.s0 + k];
+      nfs += 1.f;
+    }
+  }
+  sdf = wave_sum(sdf); fs = wave_sum(fs); ek = wave_sum(ek);
+  ntr = wave_sum(ntr); nfs = wave_sum(nfs);
+  if (lane == 0) {
+    A.rgb_hat[3 * m] = R.c_hat[0];
+    A.rgb_hat[3 * m + 1] = R.c_hat[1];
+    A.rgb_hat[3 * m + 2] = R.c_hat[2];
+    A.depth_hat[m] = R.d_hat;
+    A.wsum[m] = R.wsum;
+    float* p = A.ray_partial + 8 * (size_t)m;
+    p[0] = (fabsf(R.I[0] - R.c_hat[0]) + fabsf(R.I[1] - R.c_hat[1]) + fabsf(R.I[2] - R.c_hat[2])) / 3.f;
+    p[1] = has_d ? fabsf(R.D - R.d_hat) : 0.f;
+    p[2] = ntr > 0.f ? sdf / ntr : 0.f;
+    p[3] = nfs > 0.f ? fs / nfs : 0.f;
+    p[4] = nfs > 0.f ? ek / nfs : 0.f;
+    p[5] = has_d ? 1.f : 0.f;
+    p[6] = 0.f;
+    p[7] = 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= A.M) return;
+  RayState R;
+  ray_forward(A, m, lane, R);
+  const bool has_d = R.D > 0.f;
+  const float invM = 1.f / (float)A.M;
+  const float nd = *A.n_depth_rays;
+  const float sc = A.loss_scale;
+  float gc[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) gc[ch] = -signf_(R.I[ch] - R.c_hat[ch]) * A.lam[0] * invM * (1.f / 3.f);
+  const float gd = (has_d && nd > 0.f) ? -signf_(R.D - R.d_hat) * A.lam[1] / nd : 0.f;
+
+  // subset sizes
+  float ntr = 0.f, nfs = 0.f;
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    if (!(R.valid[c] && has_d)) continue;
+    const float b = R.D - R.tt[c];
+    if (fabsf(b) <= A.trunc) ntr += 1.f;
+    else if (b > A.trunc) nfs += 1.f;
+  }
+  ntr = wave_sum(ntr);
+  nfs = wave_sum(nfs);
+
+  // dL/dw_k and the suffix recurrence Q_i = g_i alpha_i + (1 - alpha_i) Q_{i+1}
+  float g[kChunks], Q[kChunks];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c)
+    g[c] = gc[0] * R.col[c][0] + gc[1] * R.col[c][1] + gc[2] * R.col[c][2] + gd * R.tt[c];
+  float carry = 0.f;   // Q just past the current chunk
+#pragma unroll
+  for (int c = kChunks - 1; c >= 0; --c) {
+    float a = 1.f - R.alpha[c], b = g[c] * R.alpha[c];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const float a2 = __shfl_down(a, d, 64), b2 = __shfl_down(b, d, 64);
+      if (lane + d < 64) { b = b + a * b2; a = a * a2; }
+    }
+    Q[c] = b + a * carry;
+    carry = __shfl(Q[c], 0, 64);
+  }
+  float dv_acc = 0.f;
+  float dalpha[kChunks], act_next[kChunks];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    // R_k = Q_{k+1}
+    float Rk = __shfl_down(Q[c], 1, 64);
+    if (c + 1 < kChunks) {
+      const float q0 = __shfl(Q[c + 1], 0, 64);
+      if (lane == 63) Rk = q0;
+    } else if (lane == 63) {
+      Rk = 0.f;
+    }
+    dalpha[c] = R.alpha[c] > 0.f ? R.T[c] * (g[c] - Rk) : 0.f;
+  }
+  const float s = R.s;
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const int k = 64 * c + lane;
+    // this interval's derivative factors (active only when alpha > 0)
+    const float om = 1.f - R.alpha[c];
+    const float q_here = sigmoidf_(-s * R.phi[c]);           // 1 - Phi_s(phi_k)
+    float nphi = __shfl_down(R.phi[c], 1, 64);
+    if (c + 1 < kChunks) {
+      const float p0 = __shfl(R.phi[c + 1], 0, 64);
+      if (lane == 63) nphi = p0;
+    }
+    const float q_next = sigmoidf_(-s * nphi);
+    // 1 - alpha = Phi(phi_{k+1}) / Phi(phi_k) exactly when alpha > 0
+    const float ratio = R.alpha[c] > 0.f ? om : 0.f;
+    const float d_self = dalpha[c] * s * ratio * q_here;      // d alpha_k / d phi_k
+    const float d_next = -dalpha[c] * s * ratio * q_next;     // d alpha_k / d phi_{k+1}
+    dv_acc += dalpha[c] * ratio * (R.phi[c] * q_here - nphi * q_next);
+    // contribution of interval k-1 to phi_k
+    float from_prev = __shfl_up(d_next, 1, 64);
+    if (c > 0) {
+      const float p63 = __shfl(act_next[c - 1], 63, 64);
+      if (lane == 0) from_prev = p63;
+    } else if (lane == 0) {
+      from_prev = 0.f;
+    }
+    act_next[c] = d_next;
+    float dphi = d_self + from_prev;
+    float ew = 0.f;
+    if (R.valid[c] && has_d) {
+      const float b = R.D - R.tt[c];
+      if (fabsf(b) <= A.trunc) {
+        dphi += A.lam[2] * invM / ntr * signf_(R.phi[c] - b);
+      } else if (b > A.trunc) {
+        const float ex = __expf(-A.alpha_fs * R.phi[c]);
+        const float e = ex - 1.f, lin = R.phi[c] - b;
+        const float inner = fmaxf(0.f, e);
+        float dl = 0.f;
+        if (lin > inner) dl = 1.f;
+        else if (e > 0.f) dl = -A.alpha_fs * ex;
+        dphi += A.lam[3] * invM / nfs * dl;
+        ew = A.lam[4] * invM / nfs;
+      }
+    }
+    if (k < R.n) {
+      const size_t sidx = R.s0 + k;
+      const float wk = R.w[c];
+      float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (R.valid[c]) out = make_float4(dphi * sc, gc[0] * wk * sc, gc[1] * wk * sc, gc[2] * wk * sc);
+      *reinterpret_cast<float4*>(A.seed4 + 4 * sidx) = out;
+      A.eikw[sidx] = R.valid[c] ? ew * sc : 0.f;
+    }
+  }
+  dv_acc = wave_sum(dv_acc);
+  // d s / d v = 10 s
+  if (lane == 0) A.ray_dv[m] = dv_acc * 10.f * s * sc;
+}
+
+// ---------------------------------------------------------------- reductions (fixed order)
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const float* __restrict__ ray_partial, int M,
+                                                          const float* __restrict__ smooth_partial, int n_sp,
+                                                          int S, float l0, float l1, float l2, float l3,
+                                                          float l4, float l5, float* __restrict__ losses) {
+  __shared__ float red[6][256];
+  float acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int m = threadIdx.x; m < M; m += 256) {
+    const float* p = ray_partial + 8 * (size_t)m;
+    acc[0] += p[0]; acc[1] += p[1]; acc[2] += p[2]; acc[3] += p[3]; acc[4] += p[4]; acc[5] += p[5];
+  }
+  float sm = 0.f;
+  for (int i = threadIdx.x; i < n_sp; i += 256) sm += smooth_partial[i];
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  __shared__ float sred[256];
+  sred[threadIdx.x] = sm;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float invM = 1.f / (float)M;
+    const float nd = red[5][0];
+    const float L[6] = {red[0][0] * invM, nd > 0.f ? red[1][0] / nd : 0.f, red[2][0] * invM,
+                        red[3][0] * invM, red[4][0] * invM, S > 0 ? sred[0] / (float)S : 0.f};
+    const float lam[6] = {l0, l1, l2, l3, l4, l5};
+    float tot = 0.f;
+    for (int k = 0; k < 6; ++k) { losses[k] = L[k]; tot += lam[k] * L[k]; }
+    losses[6] = tot;
+    losses[7] = nd;
+  }
+}
+
+// grads.mlp += sum over block partials (+ per-ray dv terms), fixed order per entry
+__global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ partial, int n_part,
+                                                          const float* __restrict__ ray_dv, int M,
+                                                          float* __restrict__ grad_mlp) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == gridDim.x - 1) {
+    // last block: the v entry from the per-ray terms
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int m = threadIdx.x; m < M; m += 256) s += ray_dv[m];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) grad_mlp[oV] += red[0];
+    return;
+  }
+  if (e >= kMlpNumel || e == oV) return;
+  float s = 0.f;
+  for (int b = 0; b < n_part; ++b) s += partial[(size_t)b * kMlpNumel + e];
+  grad_mlp[e] += s;
+}
+
+// ---------------------------------------------------------------- Adam
+__global__ __launch_bounds__(256) void adam_kernel(float4* __restrict__ gp, float4* __restrict__ gg,
+                                                   float4* __restrict__ gm, float4* __restrict__ gv,
+                                                   uint2* __restrict__ gbf, long long n4g,
+                                                   float4* __restrict__ mp, float4* __restrict__ mg,
+                                                   float4* __restrict__ mm, float4* __restrict__ mv,
+                                                   int n4m, float lr_g, float lr_m, float b1, float b2,
+                                                   float eps, float inv_bc1, float inv_sqrt_bc2,
+                                                   float inv_scale) {
+  const long long n4 = n4g + n4m;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
+    const bool isg = i < n4g;
+    const long long k = isg ? i : i - n4g;
+    float4* P = isg ? gp : mp;
+    float4* Gr = isg ? gg : mg;
+    float4* Mo = isg ? gm : mm;
+    float4* Vo = isg ? gv : mv;
+    const float lr = isg ? lr_g : lr_m;
+    float4 p = P[k], g = Gr[k], m = Mo[k], v = Vo[k];
+    float pa[4] = {p.x, p.y, p.z, p.w}, ga[4] = {g.x, g.y, g.z, g.w};
+    float ma[4] = {m.x, m.y, m.z, m.w}, va[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float gg_ = ga[c] * inv_scale;
+      ma[c] = b1 * ma[c] + (1.f - b1) * gg_;
+      va[c] = b2 * va[c] + (1.f - b2) * gg_ * gg_;
+      const float den = sqrtf(va[c]) * inv_sqrt_bc2 + eps;
+      pa[c] -= lr * (ma[c] * inv_bc1) / den;
+    }
+    P[k] = make_float4(pa[0], pa[1], pa[2], pa[3]);
+    Mo[k] = make_float4(ma[0], ma[1], ma[2], ma[3]);
+    Vo[k] = make_float4(va[0], va[1], va[2], va[3]);
+    Gr[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (isg && gbf) {
+      const uint32_t lo = (uint32_t)f2bf(pa[0]) | ((uint32_t)f2bf(pa[1]) << 16);
+      const uint32_t hi = (uint32_t)f2bf(pa[2]) | ((uint32_t)f2bf(pa[3]) << 16);
+      gbf[k] = make_uint2(lo, hi);
+    }
+  }
+}
+
+hipError_t launch_render(const RenderArgs& a, bool bwd, hipStream_t st) {
+  const int blocks = (a.M + 3) / 4;
+  if (bwd) hipLaunchKernelGGL(render_bwd_kernel, dim3(blocks), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(render_fwd_kernel, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smooth_partial, int n_sp, int S,
+                              const float lam[6], float* losses, hipStream_t st) {
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, ray_partial, M, smooth_partial, n_sp, S,
+                     lam[0], lam[1], lam[2], lam[3], lam[4], lam[5], losses);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
+                              hipStream_t st) {
+  const int blocks = (kMlpNumel + 255) / 256 + 1;
+  hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks), dim3(256), 0, st, partial, n_part, ray_dv, M, grad_mlp);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st) {
+  const long long n4g = s.grid_numel / 4;
+  const int n4m = s.mlp_numel / 4;
+  const double bc1 = 1.0 - pow((double)c.beta1, (double)c.step);
+  const double bc2 = 1.0 - pow((double)c.beta2, (double)c.step);
+  long long blocks = (n4g + n4m + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<float4*>(s.grid),
+                     reinterpret_cast<float4*>(s.grid_grad), reinterpret_cast<float4*>(s.grid_m),
+                     reinterpret_cast<float4*>(s.grid_v), reinterpret_cast<uint2*>(s.grid_bf16), n4g,
+                     reinterpret_cast<float4*>(s.mlp), reinterpret_cast<float4*>(s.mlp_grad),
+                     reinterpret_cast<float4*>(s.mlp_m), reinterpret_cast<float4*>(s.mlp_v), n4m, c.lr_grid,
+                     c.lr_mlp, c.beta1, c.beta2, c.eps, (float)(1.0 / bc1), (float)(1.0 / sqrt(bc2)),
+                     c.inv_loss_scale);
+  return hipGetLastError();
+}
+
+}  // namespace gs

@@ -1,0 +1,324 @@
+"""Python binding of libgosurf.so (argument marshalling only).
+
+Each function has the name of the C entry point it calls and takes torch
+tensors that live on the GPU; torch provides device memory and the stream,
+every step of the computation runs in the library's HIP kernels.  There is
+no fallback: if the library is missing or a call fails, an exception is
+raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgosurf.so")
+
+LEVELS = 4
+MLP_NUMEL = 2740
+N_LOSSES = 8
+MAX_SAMPLES_PER_RAY = 256
+FP32, BF16 = 0, 1
+SPAN_FIXED, SPAN_BOX = 0, 1
+STATUS = {0: "OK", 1: "ERR_NULL", 2: "ERR_SHAPE", 3: "ERR_ALIGN", 4: "ERR_VALUE",
+          5: "ERR_WORKSPACE", 6: "ERR_HIP"}
+LOSS_NAMES = ("rgb", "depth", "sdf", "fs", "eik", "smooth", "total", "n_depth_rays")
+
+
+class GosurfError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Model(C.Structure):
+    _fields_ = [("p0", C.c_float * 3), ("p1", C.c_float * 3), ("voxel", C.c_float * LEVELS),
+                ("dims", (C.c_int32 * 3) * LEVELS), ("offset", C.c_int64 * LEVELS),
+                ("n_vertices", C.c_int64), ("precision", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("grid_bf16", C.c_void_p), ("mlp", C.c_void_p)]
+
+
+class FramesC(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("c2w", C.c_void_p),
+                ("T", C.c_int32), ("H", C.c_int32), ("W", C.c_int32),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class SampleCfg(C.Structure):
+    _fields_ = [("M", C.c_int32), ("n_strat", C.c_int32), ("n_near", C.c_int32), ("span_mode", C.c_int32),
+                ("near_t", C.c_float), ("far_t", C.c_float), ("trunc", C.c_float), ("S", C.c_int32),
+                ("delta_s", C.c_float), ("seed", C.c_uint64), ("step", C.c_uint32)]
+
+
+class RayBatchC(C.Structure):
+    _fields_ = [("M", C.c_int32), ("total", C.c_int32), ("S", C.c_int32),
+                ("o", C.c_void_p), ("r", C.c_void_p), ("rgb", C.c_void_p), ("depth", C.c_void_p),
+                ("t", C.c_void_p), ("seg", C.c_void_p), ("ray_of", C.c_void_p),
+                ("xs", C.c_void_p), ("eps", C.c_void_p), ("pixel", C.c_void_p)]
+
+
+class LossCfg(C.Structure):
+    _fields_ = [("lambda_", C.c_float * 6), ("trunc", C.c_float), ("alpha_fs", C.c_float)]
+
+
+class FwdOutC(C.Structure):
+    _fields_ = [("rgb_hat", C.c_void_p), ("depth_hat", C.c_void_p), ("wsum", C.c_void_p),
+                ("losses", C.c_void_p), ("saved", C.c_void_p), ("weights", C.c_void_p)]
+
+
+class GradsC(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("mlp", C.c_void_p)]
+
+
+class AdamCfg(C.Structure):
+    _fields_ = [("lr_grid", C.c_float), ("lr_mlp", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("step", C.c_int32), ("inv_loss_scale", C.c_float)]
+
+
+class AdamState(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("grid_grad", C.c_void_p), ("grid_m", C.c_void_p),
+                ("grid_v", C.c_void_p), ("grid_bf16", C.c_void_p), ("grid_numel", C.c_int64),
+                ("mlp", C.c_void_p), ("mlp_grad", C.c_void_p), ("mlp_m", C.c_void_p),
+                ("mlp_v", C.c_void_p), ("mlp_numel", C.c_int32)]
+
+
+EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "gosurf_workspace_bytes",
+           "gosurf_forward", "gosurf_backward", "gosurf_adam_step")
+
+_lib = None
+
+
+def lib():
+    """Load libgosurf.so (built in-tree by ``build()``); raises if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2206_14735_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.gosurf_last_error.restype = C.c_char_p
+        L.gosurf_batch_samples.restype = C.c_int64
+        L.gosurf_batch_samples.argtypes = [C.POINTER(SampleCfg)]
+        L.gosurf_workspace_bytes.restype = C.c_size_t
+        L.gosurf_workspace_bytes.argtypes = [C.POINTER(Model), C.c_int32, C.c_int32, C.c_int32]
+        L.gosurf_sample_rays.argtypes = [C.POINTER(Model), C.POINTER(FramesC), C.POINTER(SampleCfg),
+                                         C.POINTER(RayBatchC), C.c_void_p]
+        L.gosurf_forward.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
+                                     C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_void_p, C.c_size_t, C.c_void_p]
+        L.gosurf_backward.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
+                                      C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_float, C.POINTER(GradsC),
+                                      C.c_void_p, C.c_size_t, C.c_void_p]
+        L.gosurf_adam_step.argtypes = [C.POINTER(AdamCfg), C.POINTER(AdamState), C.c_void_p]
+        for f in ("gosurf_sample_rays", "gosurf_forward", "gosurf_backward", "gosurf_adam_step"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(fn, status):
+    if status != 0:
+        raise GosurfError(fn, status, lib().gosurf_last_error().decode())
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libgosurf must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected a {dtype} tensor, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError("tensors passed to libgosurf must live on the GPU")
+    return C.c_void_p(t.data_ptr())
+
+
+F32 = torch.float32
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- descriptors
+def make_model(layout, precision=FP32):
+    """gosurf_model from a synth.GridLayout (levels coarsest first)."""
+    if layout.n_levels != LEVELS:
+        raise ValueError(f"the library implements {LEVELS}-level grids")
+    m = Model()
+    for a in range(3):
+        m.p0[a] = layout.p0[a]
+        m.p1[a] = layout.p1[a]
+    for l in range(LEVELS):
+        m.voxel[l] = layout.voxels[l]
+        for a in range(3):
+            m.dims[l][a] = layout.dims[l][a]
+        m.offset[l] = layout.offsets[l]
+    m.n_vertices = layout.n_vertices
+    m.precision = precision
+    return m
+
+
+def make_loss_cfg(lambdas=(10.0, 1.0, 10.0, 1.0, 1.0, 1.0), trunc=0.1, alpha_fs=5.0):
+    c = LossCfg()
+    for k in range(6):
+        c.lambda_[k] = lambdas[k]
+    c.trunc = trunc
+    c.alpha_fs = alpha_fs
+    return c
+
+
+@dataclass
+class RayBatch:
+    o: torch.Tensor
+    r: torch.Tensor
+    rgb: torch.Tensor
+    depth: torch.Tensor
+    t: torch.Tensor
+    seg: torch.Tensor
+    ray_of: torch.Tensor
+    xs: torch.Tensor
+    eps: torch.Tensor
+    pixel: torch.Tensor | None = None
+
+    @property
+    def M(self):
+        return self.o.shape[0]
+
+    @property
+    def total(self):
+        return self.t.shape[0]
+
+    @property
+    def S(self):
+        return self.xs.shape[0]
+
+    def c(self):
+        b = RayBatchC()
+        b.M, b.total, b.S = self.M, self.total, self.S
+        types = dict(seg=torch.int32, ray_of=torch.int32, pixel=torch.int64)
+        for f in ("o", "r", "rgb", "depth", "t", "seg", "ray_of", "xs", "eps", "pixel"):
+            setattr(b, f, _ptr(getattr(self, f), types.get(f, F32)))
+        return b
+
+    @staticmethod
+    def empty(M, total, S, device="cuda"):
+        f = dict(device=device, dtype=torch.float32)
+        return RayBatch(torch.empty(M, 3, **f), torch.empty(M, 3, **f), torch.empty(M, 3, **f),
+                        torch.empty(M, **f), torch.empty(total, **f),
+                        torch.empty(M + 1, device=device, dtype=torch.int32),
+                        torch.empty(total, device=device, dtype=torch.int32),
+                        torch.empty(S, 3, **f), torch.empty(S, 3, **f),
+                        torch.empty(M, device=device, dtype=torch.int64))
+
+    @staticmethod
+    def from_host(b, device="cuda"):
+        """Upload an oracle-format batch (numpy arrays) to the device."""
+        import numpy as np
+        seg = np.asarray(b.seg, dtype=np.int64)
+        ray_of = np.repeat(np.arange(len(seg) - 1), seg[1:] - seg[:-1]).astype(np.int32)
+        t = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)  # noqa
+        return RayBatch(t(b.o), t(b.r), t(b.rgb), t(b.depth), t(b.t), t(seg, torch.int32),
+                        t(ray_of, torch.int32), t(np.asarray(b.xs).reshape(-1, 3)),
+                        t(np.asarray(b.eps).reshape(-1, 3)))
+
+
+@dataclass
+class FwdOut:
+    rgb_hat: torch.Tensor
+    depth_hat: torch.Tensor
+    wsum: torch.Tensor
+    losses: torch.Tensor
+    saved: torch.Tensor
+    weights: torch.Tensor | None = None
+
+    def c(self):
+        o = FwdOutC()
+        for f in ("rgb_hat", "depth_hat", "wsum", "losses", "saved", "weights"):
+            setattr(o, f, _ptr(getattr(self, f), F32))
+        return o
+
+    @staticmethod
+    def empty(M, total, device="cuda", weights=False):
+        f = dict(device=device, dtype=torch.float32)
+        return FwdOut(torch.empty(M, 3, **f), torch.empty(M, **f), torch.empty(M, **f),
+                      torch.empty(N_LOSSES, **f), torch.empty(5 * total, **f),
+                      torch.empty(total, **f) if weights else None)
+
+    def sample_values(self, total):
+        """(phi [total], colour [total, 3]) views of the saved per-sample values."""
+        v = self.saved[: 4 * total].view(total, 4)
+        return v[:, 0], v[:, 1:]
+
+
+def frames_c(frames):
+    f = FramesC()
+    f.rgb, f.depth, f.c2w = _ptr(frames.rgb, torch.uint8), _ptr(frames.depth, F32), _ptr(frames.c2w, F32)
+    f.T, f.H, f.W = frames.depth.shape
+    f.fx, f.fy, f.cx, f.cy = frames.fx, frames.fy, frames.cx, frames.cy
+    return f
+
+
+# ---------------------------------------------------------------- entry points
+def gosurf_batch_samples(cfg):
+    return int(lib().gosurf_batch_samples(C.byref(cfg)))
+
+
+def gosurf_workspace_bytes(model, M, total, S):
+    return int(lib().gosurf_workspace_bytes(C.byref(model), M, total, S))
+
+
+def gosurf_sample_rays(model, frames, cfg, out=None, stream=None):
+    """frames: synth.Frames on the device.  Returns a RayBatch on the device."""
+    total = gosurf_batch_samples(cfg)
+    dev = frames.depth.device
+    if out is None:
+        out = RayBatch.empty(cfg.M, total, cfg.S, dev)
+    fc = frames_c(frames)
+    bc = out.c()
+    _check("gosurf_sample_rays", lib().gosurf_sample_rays(C.byref(model), C.byref(fc), C.byref(cfg),
+                                                          C.byref(bc), _stream(stream)))
+    return out
+
+
+def gosurf_forward(model, grid, mlp, batch, loss_cfg, workspace, out=None, grid_bf16=None, weights=False,
+                   stream=None):
+    if out is None:
+        out = FwdOut.empty(batch.M, batch.total, grid.device, weights)
+    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
+    bc, oc = batch.c(), out.c()
+    _check("gosurf_forward", lib().gosurf_forward(C.byref(model), C.byref(p), C.byref(bc), C.byref(loss_cfg),
+                                                  C.byref(oc), _ptr(workspace), workspace.numel(),
+                                                  _stream(stream)))
+    return out
+
+
+def gosurf_backward(model, grid, mlp, batch, loss_cfg, fwd, loss_scale, grad_grid, grad_mlp, workspace,
+                    grid_bf16=None, stream=None):
+    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
+    g = GradsC(_ptr(grad_grid, F32), _ptr(grad_mlp, F32))
+    bc, oc = batch.c(), fwd.c()
+    _check("gosurf_backward", lib().gosurf_backward(C.byref(model), C.byref(p), C.byref(bc), C.byref(loss_cfg),
+                                                    C.byref(oc), float(loss_scale), C.byref(g),
+                                                    _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def gosurf_adam_step(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_grad, mlp_m, mlp_v, lr_grid=1e-2,
+                     lr_mlp=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, inv_loss_scale=1.0, grid_bf16=None,
+                     stream=None):
+    c = AdamCfg(lr_grid, lr_mlp, beta1, beta2, eps, int(step), inv_loss_scale)
+    s = AdamState(_ptr(grid, F32), _ptr(grid_grad, F32), _ptr(grid_m, F32), _ptr(grid_v, F32), _ptr(grid_bf16),
+                  grid.numel(), _ptr(mlp, F32), _ptr(mlp_grad, F32), _ptr(mlp_m, F32), _ptr(mlp_v, F32),
+                  mlp.numel())
+    _check("gosurf_adam_step", lib().gosurf_adam_step(C.byref(c), C.byref(s), _stream(stream)))
+
+
+def workspace_for(model, M, total, S, device="cuda"):
+    n = gosurf_workspace_bytes(model, M, total, S)
+    return torch.empty(n, dtype=torch.uint8, device=device)

@@ -1,0 +1,79 @@
+"""Device-resident optimisation driver over the C ABI.
+
+Owns the grid and decoder parameters, their gradients, the Adam moments, a
+ray batch, the forward outputs and the workspace, all allocated once on the
+GPU; ``step()`` enqueues gosurf_sample_rays, gosurf_forward, gosurf_backward
+and gosurf_adam_step on the current stream without synchronising.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import gosurf as G
+
+
+class Reconstruction:
+    def __init__(self, layout, frames, n_strat, n_near, M, S, span_mode, near, far, trunc=0.1,
+                 delta_s=0.004, lambdas=(10.0, 1.0, 10.0, 1.0, 1.0, 1.0), alpha_fs=5.0,
+                 lr_grid=1e-2, lr_mlp=1e-3, seed=0, precision=G.FP32, loss_scale=1.0,
+                 grid=None, mlp=None, device="cuda"):
+        import synth
+        self.device = torch.device(device)
+        self.layout = layout
+        self.model = G.make_model(layout, precision)
+        if grid is None or mlp is None:
+            grid, mlp = synth.init_params(layout, seed=seed)
+        self.grid = grid.to(self.device, torch.float32).contiguous()
+        self.mlp = mlp.to(self.device, torch.float32).contiguous()
+        self.grid_grad = torch.zeros_like(self.grid)
+        self.mlp_grad = torch.zeros_like(self.mlp)
+        self.grid_m = torch.zeros_like(self.grid)
+        self.grid_v = torch.zeros_like(self.grid)
+        self.mlp_m = torch.zeros_like(self.mlp)
+        self.mlp_v = torch.zeros_like(self.mlp)
+        self.grid_bf16 = None
+        self.frames = frames.to(self.device)
+        self.cfg = G.SampleCfg(M, n_strat, n_near, span_mode, near, far, trunc, S, delta_s, seed, 0)
+        self.loss_cfg = G.make_loss_cfg(lambdas, trunc, alpha_fs)
+        self.total = G.gosurf_batch_samples(self.cfg)
+        self.batch = G.RayBatch.empty(M, self.total, S, self.device)
+        self.fwd = G.FwdOut.empty(M, self.total, self.device)
+        self.ws = G.workspace_for(self.model, M, self.total, S, self.device)
+        self.lr_grid, self.lr_mlp = lr_grid, lr_mlp
+        self.loss_scale = loss_scale
+        self.it = 0
+
+    @classmethod
+    def from_workload(cls, w, frames, seed=0, **kw):
+        span = G.SPAN_FIXED if w.span == "fixed" else G.SPAN_BOX
+        prec = G.BF16 if w.precision == "bf16" else G.FP32
+        return cls(w.layout(), frames, w.n_strat, w.n_near, w.M, w.S, span, w.near, w.far, w.trunc,
+                   w.delta_s, w.lambdas, w.alpha_fs, w.lr_grid, w.lr_mlp, seed, prec, w.loss_scale, **kw)
+
+    def sample(self):
+        self.cfg.step = self.it
+        G.gosurf_sample_rays(self.model, self.frames, self.cfg, out=self.batch)
+
+    def forward(self):
+        return G.gosurf_forward(self.model, self.grid, self.mlp, self.batch, self.loss_cfg, self.ws,
+                                out=self.fwd, grid_bf16=self.grid_bf16)
+
+    def backward(self):
+        G.gosurf_backward(self.model, self.grid, self.mlp, self.batch, self.loss_cfg, self.fwd,
+                          self.loss_scale, self.grid_grad, self.mlp_grad, self.ws, grid_bf16=self.grid_bf16)
+
+    def adam(self):
+        G.gosurf_adam_step(self.it + 1, self.grid, self.grid_grad, self.grid_m, self.grid_v, self.mlp,
+                           self.mlp_grad, self.mlp_m, self.mlp_v, self.lr_grid, self.lr_mlp,
+                           inv_loss_scale=1.0 / self.loss_scale, grid_bf16=self.grid_bf16)
+
+    def step(self):
+        self.sample()
+        self.forward()
+        self.backward()
+        self.adam()
+        self.it += 1
+
+    def losses(self):
+        v = self.fwd.losses.tolist()
+        return dict(zip(G.LOSS_NAMES, v))

@@ -1,0 +1,146 @@
+"""The C ABI library loads, exports every declared symbol, agrees with the
+header's struct layout, and rejects invalid arguments on the host (no GPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gosurf.h")
+
+from paper_2206_14735_amd import gosurf as G  # noqa: E402
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(gosurf_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(G.LIB_PATH):
+        pytest.fail("libgosurf.so is not built (run __graft_entry__.build())")
+    return G.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert set(G.EXPORTS) <= set(names)
+    for n in names:
+        assert hasattr(lib, n), f"missing export {n}"
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "sizes.c"
+    structs = ["gosurf_model", "gosurf_params", "gosurf_frames", "gosurf_sample_cfg", "gosurf_ray_batch",
+               "gosurf_loss_cfg", "gosurf_fwd_out", "gosurf_grads", "gosurf_adam_cfg", "gosurf_adam_state"]
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gosurf.h"\nint main(void){\n' +
+                    "".join(f'printf("%zu\\n", sizeof({s}));\n' for s in structs) +
+                    'printf("%zu %zu %zu\\n", offsetof(gosurf_model, n_vertices), offsetof(gosurf_sample_cfg, seed),'
+                    ' offsetof(gosurf_adam_state, mlp_numel));\nreturn 0;}\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    py = [G.Model, G.Params, G.FramesC, G.SampleCfg, G.RayBatchC, G.LossCfg, G.FwdOutC, G.GradsC, G.AdamCfg,
+          G.AdamState]
+    for name, cls, n in zip(structs, py, out[:10]):
+        assert C.sizeof(cls) == int(n), f"{name}: ctypes {C.sizeof(cls)} vs C {n}"
+    assert int(out[10]) == G.Model.n_vertices.offset
+    assert int(out[11]) == G.SampleCfg.seed.offset
+    assert int(out[12]) == G.AdamState.mlp_numel.offset
+
+
+def test_constants_match_header():
+    src = open(HEADER).read()
+    vals = dict(re.findall(r"#define (GOSURF_[A-Z_]+) (\d+)", src))
+    assert int(vals["GOSURF_MLP_NUMEL"]) == G.MLP_NUMEL
+    assert int(vals["GOSURF_LEVELS"]) == G.LEVELS
+    assert int(vals["GOSURF_N_LOSSES"]) == G.N_LOSSES
+    assert int(vals["GOSURF_MAX_SAMPLES_PER_RAY"]) == G.MAX_SAMPLES_PER_RAY
+    import synth
+    assert synth.MLP_NUMEL == G.MLP_NUMEL
+
+
+def _model():
+    import synth
+    return G.make_model(synth.configs.SPHERE.layout())
+
+
+def test_workspace_bytes_grows_with_batch(lib):
+    m = _model()
+    a = G.gosurf_workspace_bytes(m, 1024, 65536, 4096)
+    b = G.gosurf_workspace_bytes(m, 2048, 131072, 4096)
+    assert 0 < a < b
+    assert a % 256 == 0
+
+
+def test_batch_samples(lib):
+    c = G.SampleCfg(6144, 64, 32, 1, 0.1, 1e9, 0.1, 16384, 0.004, 0, 0)
+    assert G.gosurf_batch_samples(c) == 6144 * 96
+
+
+def test_forward_rejects_null_arguments(lib):
+    st = lib.gosurf_forward(None, None, None, None, None, None, 0, None)
+    assert st == 1 and b"model" in lib.gosurf_last_error()
+
+
+def test_forward_rejects_bad_model(lib):
+    m = _model()
+    m.voxel[2] = -1.0
+    p = G.Params(8, None, 8)
+    st = lib.gosurf_forward(C.byref(m), C.byref(p), None, None, None, None, 0, None)
+    assert st == 4
+    m = _model()
+    m.dims[1][0] = 1
+    st = lib.gosurf_forward(C.byref(m), C.byref(p), None, None, None, None, 0, None)
+    assert st == 2
+
+
+def test_forward_rejects_small_workspace_and_misalignment(lib):
+    m = _model()
+    p = G.Params(16, None, 16)
+    b = G.RayBatchC()
+    b.M, b.total, b.S = 4, 64, 0
+    for f in ("o", "r", "rgb", "depth", "t", "seg", "ray_of"):
+        setattr(b, f, 64)
+    lc = G.make_loss_cfg()
+    out = G.FwdOutC(16, 16, 16, 16, 16, None)
+    st = lib.gosurf_forward(C.byref(m), C.byref(p), C.byref(b), C.byref(lc), C.byref(out), 256, 10, None)
+    assert st == 5 and b"workspace" in lib.gosurf_last_error()
+    p2 = G.Params(18, None, 16)   # grid not 16-byte aligned
+    st = lib.gosurf_forward(C.byref(m), C.byref(p2), C.byref(b), C.byref(lc), C.byref(out), 256, 1 << 30, None)
+    assert st == 3
+
+
+def test_forward_rejects_bad_loss_config(lib):
+    m = _model()
+    p = G.Params(16, None, 16)
+    b = G.RayBatchC()
+    b.M, b.total, b.S = 4, 64, 0
+    for f in ("o", "r", "rgb", "depth", "t", "seg", "ray_of"):
+        setattr(b, f, 64)
+    lc = G.make_loss_cfg(trunc=0.0)
+    out = G.FwdOutC(16, 16, 16, 16, 16, None)
+    st = lib.gosurf_forward(C.byref(m), C.byref(p), C.byref(b), C.byref(lc), C.byref(out), 256, 1 << 30, None)
+    assert st == 4 and b"trunc" in lib.gosurf_last_error()
+
+
+def test_sample_rays_rejects_oversized_rays(lib):
+    m = _model()
+    fr = G.FramesC(16, 16, 16, 1, 60, 80, 60.0, 60.0, 40.0, 30.0)
+    c = G.SampleCfg(8, 200, 100, 0, 0.1, 3.0, 0.1, 0, 0.004, 0, 0)
+    out = G.RayBatchC()
+    out.M, out.total, out.S = 8, 8 * 300, 0
+    st = lib.gosurf_sample_rays(C.byref(m), C.byref(fr), C.byref(c), C.byref(out), None)
+    assert st == 2 and b"256" in lib.gosurf_last_error()
+
+
+def test_adam_rejects_bad_step_and_sizes(lib):
+    c = G.AdamCfg(1e-2, 1e-3, 0.9, 0.999, 1e-8, 0, 1.0)
+    s = G.AdamState(16, 16, 16, 16, None, 8, 16, 16, 16, 16, 4)
+    assert lib.gosurf_adam_step(C.byref(c), C.byref(s), None) == 4
+    c.step = 1
+    s.grid_numel = 6
+    assert lib.gosurf_adam_step(C.byref(c), C.byref(s), None) == 2

@@ -16,7 +16,15 @@ from oracle import decoder, grid as G, objective as O, render as R, step as S, s
 from oracle.philox import philox4x32_10, uniform01
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
-torch.set_default_dtype(torch.float64)
+
+
+@pytest.fixture(autouse=True)
+def _float64_default():
+    """Plain tensors in this module are float64; restored after each test."""
+    old = torch.get_default_dtype()
+    torch.set_default_dtype(torch.float64)
+    yield
+    torch.set_default_dtype(old)
 
 
 # ---------------------------------------------------------------- Philox
