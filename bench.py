@@ -1,0 +1,170 @@
+"""Throughput of the GO-Surf optimisation step on one MI355X.
+
+One step = gosurf_sample_rays + gosurf_forward + gosurf_backward +
+gosurf_adam_step over one batch of the room workload (8 x 6 x 3 m room,
+1000 synthetic RGB-D frames of 640 x 480, 6144 rays x (64 stratified + 32
+near-depth) samples, 16384 smoothness pairs, 4-level grid at
+0.03/0.06/0.24/0.96 m = 37.9 M parameters, FP32).  Inputs are generated on the
+device before timing; the timed region contains only library calls.
+
+Prints one JSON line: ray-samples/s (rays x samples per ray / step time),
+the roofline of the dominant kernel measured with HIP events on the launch
+stream, and the FP64 oracle timed on a bounded sample on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="room")
+    ap.add_argument("--frames", type=int, default=None, help="override the number of frames")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=512)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, frames_cpu, grid, mlp, n_rays):
+    """FP64 oracle on a bounded sample of the same workload: one step's
+    forward+backward on `n_rays` rays (with the proportional share of
+    smoothness pairs) over the full grid, plus one dense Adam update of all
+    parameters; scaled to the full batch."""
+    import numpy as np
+    import torch
+
+    from oracle import sampler, step as ostep
+    from tests.helpers import f32_layout
+    L = f32_layout(w.layout())
+    S = max(1, round(w.S * n_rays / w.M))
+    b, _, _ = sampler.sample_batch(frames_cpu, L, n_rays, w.n_strat, w.n_near, w.span, w.near, w.far, w.trunc,
+                                   S, w.delta_s, seed=0, step=0)
+    g64 = grid.double().numpy()
+    m64 = mlp.double().numpy()
+    t0 = time.perf_counter()
+    res = ostep.evaluate(g64, m64, L, b, ostep.LossCfg(w.lambdas, w.trunc, w.alpha_fs))
+    t_fb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ostep.adam(g64, res["grad_grid"].numpy(), np.zeros_like(g64), np.zeros_like(g64), 1, w.lr_grid)
+    ostep.adam(m64, res["grad_mlp"].numpy(), np.zeros_like(m64), np.zeros_like(m64), 1, w.lr_mlp)
+    t_adam = time.perf_counter() - t0
+    t_step = t_fb * (w.M / n_rays) + t_adam
+    return {"value": w.M * w.n_samples / t_step, "unit": "ray-samples/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{n_rays} rays x {w.n_samples} samples + {S} smoothness pairs fwd+bwd over the full "
+                      f"grid ({t_fb:.1f} s), scaled by {w.M}/{n_rays}, plus one dense Adam step over all "
+                      f"{grid.numel() + mlp.numel()} parameters ({t_adam:.1f} s)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the multi-GPU sharding is a design "
+              f"described in DESIGN.md and is not run here.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2206_14735_amd import gosurf as G
+    from paper_2206_14735_amd.train import Reconstruction
+
+    G.lib()
+    w = synth.configs.ALL[a.workload]
+    n_frames = a.frames or w.n_frames
+    t0 = time.time()
+    frames, scene = synth.room_frames(n_frames, H=w.H, W=w.W, f=w.f, seed=0, device="cuda") \
+        if w.scene == "room" else (synth.sphere_frames().to("cuda"), None)
+    torch.cuda.synchronize()
+    print(f"# frames ready: {n_frames} x {w.H}x{w.W} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    grid, mlp = synth.init_params(w.layout(), seed=0)
+    rec = Reconstruction.from_workload(w, frames, seed=0, grid=grid.clone(), mlp=mlp.clone())
+
+    t0 = time.time()
+    for _ in range(a.warmup):
+        rec.step()
+    torch.cuda.synchronize()
+    print(f"# warmup done ({a.warmup} steps, {time.time() - t0:.2f} s), losses {rec.losses()}", file=sys.stderr,
+          flush=True)
+
+    # timed region: K whole steps
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        rec.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / a.steps
+    print(f"# timed {a.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # per-call breakdown with HIP events on the launch stream (separate pass)
+    st = torch.cuda.current_stream()
+    names = ["sample_rays", "forward", "backward", "adam_step"]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(a.steps)]
+    for k in range(a.steps):
+        e = evs[k]
+        e[0].record(st)
+        rec.sample()
+        e[1].record(st)
+        rec.forward()
+        e[2].record(st)
+        rec.backward()
+        e[3].record(st)
+        rec.adam()
+        e[4].record(st)
+        rec.it += 1
+    torch.cuda.synchronize()
+    per = {n: sum(evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(a.steps)) / a.steps
+           for i, n in enumerate(names)}
+    print(f"# per call (ms): {per}", file=sys.stderr, flush=True)
+
+    # roofline of the dense Adam kernel (one kernel per call): 32 B per parameter
+    n_par = rec.grid.numel() + rec.mlp.numel()
+    adam_bytes = 32.0 * n_par
+    adam_gbs = adam_bytes / (per["adam_step"] * 1e-3) / 1e9
+    dominant = max(per, key=per.get)
+    roof = {"kernel": "adam_kernel (gosurf_adam_step)", "bound": "hbm", "achieved": round(adam_gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(adam_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None, "algorithmic_bytes": adam_bytes}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        fr_cpu = synth.Frames(frames.rgb.cpu(), frames.depth.cpu(), frames.c2w.cpu(), frames.fx, frames.fy,
+                              frames.cx, frames.cy)
+        print(f"# oracle baseline on {a.cpu_rays} rays ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, fr_cpu, grid, mlp, a.cpu_rays)
+        print(f"# oracle baseline: {cpu['sample']}", file=sys.stderr, flush=True)
+
+    samples = w.M * w.n_samples
+    out = {
+        "metric": "ray-samples/s per fwd+bwd step, plain FP32 vs BF16+proposal at equal depth L1",
+        "value": samples / (ms * 1e-3), "unit": "ray-samples/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "iterations_per_s": 1e3 / ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if w.precision == "fp32" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.M} rays x ({w.n_strat}+{w.n_near}) samples, {w.S} smoothness "
+                               f"pairs, grid {'/'.join(str(v) for v in sorted(w.voxels))} m "
+                               f"({n_par / 1e6:.2f} M params), {n_frames} frames {w.W}x{w.H}, {w.precision}",
+                   "rays": w.M, "samples_per_ray": w.n_samples, "smoothness_pairs": w.S,
+                   "grid_params": rec.grid.numel(), "frames": n_frames},
+        "per_call_ms": {k: round(v, 4) for k, v in per.items()},
+        "dominant_call": dominant,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "losses": rec.losses(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

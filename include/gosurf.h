@@ -223,9 +223,9 @@ size_t gosurf_workspace_bytes(const gosurf_model* model, int32_t M, int32_t tota
    max(0, e^{-alpha phi} - 1, phi - b), (1 - |grad phi|)^2 with b = D - t; only
    rays with depth have S_tr and S_fs, and membership is decided in float32;
    L_smooth = (1/S) sum over pairs of |grad phi(x) - grad phi(x + eps)|^2
-   (a pair leaving the box contributes 0).  A term whose weight lambda is 0 is
-   not evaluated and reported as 0.  Errors: NULL, SHAPE, VALUE, WORKSPACE,
-   HIP. */
+   (a pair leaving the box contributes 0).  The Eikonal and smoothness terms
+   are not evaluated, and reported as 0, when their weight lambda is 0.
+   Errors: NULL, SHAPE, VALUE, WORKSPACE, HIP. */
 gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* params,
                              const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
                              gosurf_fwd_out* out, void* workspace, size_t workspace_bytes,

@@ -31,6 +31,12 @@ struct FieldArgs {
   float* grad_grid;       // [V][4]
   float* mlp_partial;     // [gridDim.x][kMlpNumel]
   int need_gx;            // ray mode: compute grad phi for the Eikonal term
+  // levels whose gradient is accumulated in LDS per block (bit l) and the
+  // float offset of each such level inside the block's LDS area
+  int priv_mask;
+  int priv_off[4];
+  int priv_floats;        // floats of the LDS area
+  float* priv_partial;    // [gridDim.x][priv_floats] block partials
 };
 
 struct RenderArgs {

@@ -14,12 +14,15 @@
 namespace gs {
 
 hipError_t launch_field(const FieldArgs& a, int mode, bool bwd, int blocks, hipStream_t st);
+hipError_t launch_priv_reduce(const FieldArgs& a, int n_part, const int counts[4], float* tmp, hipStream_t st);
+void plan_privatised_levels(FieldArgs& a, int counts[4]);
+int priv_max_floats();
 int field_blocks(int n_items, int per_tile);
 hipError_t launch_render(const RenderArgs& a, bool bwd, hipStream_t st);
 hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smooth_partial, int n_sp, int S,
                               const float lam[6], float* losses, hipStream_t st);
 hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
-                              hipStream_t st);
+                              float* tmp, hipStream_t st);
 hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st);
 hipError_t launch_sample(const SampleArgs& a, hipStream_t st);
 
@@ -68,7 +71,7 @@ gosurf_status check_model(const gosurf_model* m) {
                   (long long)m->offset[l], (long long)(m->offset[l] + n), (long long)m->n_vertices);
     rows += n;
   }
-  if (m->n_vertices * 4 >= (1LL << 40)) return fail(GOSURF_ERR_SHAPE, "grid too large");
+  if (m->n_vertices >= (1LL << 31) - 1) return fail(GOSURF_ERR_SHAPE, "grid has more than 2^31 vertices");
   for (int a = 0; a < 3; ++a)
     if (!(m->p1[a] > m->p0[a])) return fail(GOSURF_ERR_VALUE, "box is empty along axis %d", a);
   (void)rows;
@@ -98,6 +101,8 @@ struct Workspace {
   float* eikw;            // [total]
   float* ray_dv;          // [M]
   float* mlp_partial;     // [2048][kMlpNumel]
+  float* priv_partial;    // [2048][priv_max_floats]
+  float* colsum_tmp;      // [64][max(kMlpNumel, priv_max_floats)]
   size_t bytes;
 };
 
@@ -112,6 +117,9 @@ Workspace layout(char* base, int M, int total, int S) {
   w.eikw = reinterpret_cast<float*>(take(sizeof(float) * (size_t)total));
   w.ray_dv = reinterpret_cast<float*>(take(sizeof(float) * (size_t)M));
   w.mlp_partial = reinterpret_cast<float*>(take(sizeof(float) * 2048 * (size_t)gs::kMlpNumel));
+  w.priv_partial = reinterpret_cast<float*>(take(sizeof(float) * 2048 * (size_t)gs::priv_max_floats()));
+  w.colsum_tmp = reinterpret_cast<float*>(
+      take(sizeof(float) * 64 * (size_t)(gs::priv_max_floats() > gs::kMlpNumel ? gs::priv_max_floats() : gs::kMlpNumel)));
   w.bytes = off;
   return w;
 }
@@ -297,15 +305,22 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   fa.seed4 = w.seed4; fa.eikw = w.eikw; fa.need_gx = need_gx;
   fa.grad_grid = grads->grid; fa.mlp_partial = w.mlp_partial;
   fa.smooth_coef = b->S > 0 ? 2.f * loss->lambda[5] * loss_scale / (float)b->S : 0.f;
+  int counts[4];
+  gs::plan_privatised_levels(fa, counts);
+  fa.priv_partial = w.priv_partial;
   const int nbr = gs::field_blocks(b->total, 16);
   if ((st = hip_check(gs::launch_field(fa, 0, true, nbr, s), "field bwd")) != GOSURF_OK) return st;
   int nbs = 0;
   if (b->S > 0 && loss->lambda[5] != 0.f) {
     nbs = gs::field_blocks(2 * b->S, 16);
     fa.mlp_partial = w.mlp_partial + (size_t)nbr * gs::kMlpNumel;
+    fa.priv_partial = w.priv_partial + (size_t)nbr * fa.priv_floats;
     if ((st = hip_check(gs::launch_field(fa, 1, true, nbs, s), "smoothness bwd")) != GOSURF_OK) return st;
   }
-  if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nbr + nbs, w.ray_dv, b->M, grads->mlp, s),
+  fa.priv_partial = w.priv_partial;
+  if ((st = hip_check(gs::launch_priv_reduce(fa, nbr + nbs, counts, w.colsum_tmp, s), "level reduce")) != GOSURF_OK)
+    return st;
+  if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nbr + nbs, w.ray_dv, b->M, grads->mlp, w.colsum_tmp, s),
                       "grad reduce")) != GOSURF_OK)
     return st;
   return ok();

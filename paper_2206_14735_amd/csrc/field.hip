@@ -178,11 +178,31 @@ __device__ __forceinline__ void interp(const float* __restrict__ grid, const Lev
   }
 }
 
-// grid scatter: dL/dtheta_c,k = w_c dz_k + a_k (J_c . gvec) / v
+// One step of the segmented sum inside a 16-lane level group: lanes of the
+// same run (equal cell) add their right neighbour's partial at distance D.
+template <int CTRL, int D>
+__device__ __forceinline__ void run_step(float (&val)[8][4], int segid, int j) {
+  const int so = dpp_i<CTRL>(segid);
+  const bool take = (j + D < 16) && so == segid;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float o = dpp_f<CTRL>(val[c][k]);
+      val[c][k] += take ? o : 0.f;
+    }
+}
+
+// grid scatter: dL/dtheta_c,k = w_c dz_k + a_k (J_c . gvec) / v.
+// The 16 lanes of a level group hold 16 consecutive samples, so runs of
+// samples in the same cell sit in neighbouring lanes: a segmented sum merges
+// each run into its first lane, which alone updates the 32 features, either
+// in the block's LDS copy of a small level or with float atomics in HBM.
 template <bool HAS_DZ, bool HAS_GV>
-__device__ __forceinline__ void scatter(float* __restrict__ grad, const LevelSample& ls, const float dz[4],
-                                        const float a[4], const float gv[3]) {
+__device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, int q, int j, const LevelSample& ls,
+                                        bool valid, const float dz[4], const float a[4], const float gv[3]) {
   const float fx = ls.f[0], fy = ls.f[1], fz = ls.f[2];
+  float val[8][4];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
@@ -194,14 +214,39 @@ __device__ __forceinline__ void scatter(float* __restrict__ grad, const LevelSam
       jg = (jx * gv[0] + jy * gv[1] + jz * gv[2]) * ls.inv_v;
     }
     const float w = wx * wy * wz;
-    const long long row = ls.row + bx + (long long)by * ls.sy + (long long)bz * ls.sz;
-    float* p = grad + row * 4;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      float val = 0.f;
-      if (HAS_DZ) val += w * dz[k];
-      if (HAS_GV) val += a[k] * jg;
-      atomicAdd(p + k, val);
+      float v = 0.f;
+      if (HAS_DZ) v += w * dz[k];
+      if (HAS_GV) v += a[k] * jg;
+      val[c][k] = valid ? v : 0.f;
+    }
+  }
+  // runs of equal cells (invalid lanes form runs of their own and never write)
+  const int key = valid ? (int)ls.row : -1 - j;
+  const int kprev = dpp_i<kRowShr1>(key);
+  const bool head = (j == 0) || key != kprev;
+  const unsigned long long hm = __ballot(head);
+  const unsigned g = (unsigned)(hm >> (16 * q)) & 0xffffu;
+  const int segid = __popc(g & ((2u << j) - 1u));
+  run_step<kRowShl1, 1>(val, segid, j);
+  run_step<kRowShl2, 2>(val, segid, j);
+  run_step<kRowShl4, 4>(val, segid, j);
+  run_step<kRowShl8, 8>(val, segid, j);
+  if (!(head && valid)) return;
+  const bool in_lds = (A.priv_mask >> q) & 1;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+    const long long row = ls.row + bx + (long long)by * ls.sy + (long long)bz * ls.sz;
+    if (in_lds) {
+      float* p = priv + A.priv_off[q] + (int)(row - A.g.off[q]) * 4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) atomicAdd(p + k, val[c][k]);
+    } else {
+      float* p = A.grad_grid + row * 4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) atomicAdd(p + k, val[c][k]);
     }
   }
 }
@@ -228,6 +273,7 @@ struct FieldSmem {
 };
 constexpr int kRedFloats = kWavesPerBlock * kMlpNumel;
 constexpr int kSmemBytes = (sizeof(FieldSmem) > kRedFloats * 4) ? sizeof(FieldSmem) : kRedFloats * 4;
+constexpr int kPrivMaxFloats = 4096;   // LDS budget for privatised levels (1024 vertices)
 
 // MODE 0: ray samples; MODE 1: smoothness pairs (16-lane tile = 8 pairs: lanes
 // j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).
@@ -253,6 +299,10 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
   const float* tab = sm.tab;
   float* scrA = sm.scr[wave][0];
   float* scrB = sm.scr[wave][1];
+  float* priv = reinterpret_cast<float*>(smem_raw + kSmemBytes);
+  if (BWD)
+    for (int e = tid; e < A.priv_floats; e += kBlock) priv[e] = 0.f;
+  __syncthreads();
 
   const bool need_g = (MODE == 1) || A.need_gx;
   const int n_items = MODE == 0 ? A.total : 2 * A.S;   // lanes of work
@@ -446,10 +496,10 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
         outer_acc<2, 2>(scrA, scrB, e2, r1, aW2, q, j);
         outer_acc<2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
         const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
-        if (valid) scatter<true, true>(A.grad_grid, ls, dzl, al, gv);
+        scatter<true, true>(A, priv, q, j, ls, valid, dzl, al, gv);
       } else {
         const float al[4] = {0, 0, 0, 0};
-        if (valid) scatter<true, false>(A.grad_grid, ls, dzl, al, gv);
+        scatter<true, false>(A, priv, q, j, ls, valid, dzl, al, gv);
       }
     } else {
       // smoothness pair: d|g(x) - g(x+eps)|^2 / dg at either point is
@@ -474,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
       outer_acc<2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
       const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
       const float dzl[4] = {0, 0, 0, 0};
-      if (pv) scatter<false, true>(A.grad_grid, ls, dzl, al, gv);
+      scatter<false, true>(A, priv, q, j, ls, pv, dzl, al, gv);
     }
   }
 
@@ -495,6 +545,12 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
     return;
   }
 
+  // ---------------- block partial of the privatised levels' gradients
+  __syncthreads();
+  if (A.priv_floats > 0) {
+    float* dst = A.priv_partial + (size_t)blockIdx.x * A.priv_floats;
+    for (int e = tid; e < A.priv_floats; e += kBlock) dst[e] = priv[e];
+  }
   // ---------------- block partial of the decoder gradients (deterministic)
   __syncthreads();
   float* red = reinterpret_cast<float*>(smem_raw) + wave * kMlpNumel;
@@ -562,8 +618,65 @@ int field_blocks(int n_items, int per_tile) {
   return blocks < 1 ? 1 : blocks;
 }
 
+// sum of the block partials of the privatised levels into the grid gradient
+// (one writer per entry, fixed block order)
+struct PrivMap {
+  int mask;
+  int po[4], pc[4];
+  long long go[4];
+};
+
+__global__ __launch_bounds__(256) void priv_stage2_kernel(const float* __restrict__ tmp, int floats, PrivMap pm,
+                                                          float* __restrict__ grad) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= floats) return;
+  float s = 0.f;
+#pragma unroll 8
+  for (int y = 0; y < 64; ++y) s += tmp[(size_t)y * floats + e];
+  for (int l = 0; l < 4; ++l)
+    if (((pm.mask >> l) & 1) && e >= pm.po[l] && e < pm.po[l] + pm.pc[l]) grad[pm.go[l] * 4 + (e - pm.po[l])] += s;
+}
+
+hipError_t launch_colsum_stage1(const float* part, int rows, int cols, float* tmp, hipStream_t st);
+int colsum_rows();
+
+hipError_t launch_priv_reduce(const FieldArgs& a, int n_part, const int counts[4], float* tmp, hipStream_t st) {
+  if (a.priv_floats <= 0) return hipSuccess;
+  if (colsum_rows() != 64) return hipErrorInvalidValue;
+  PrivMap pm;
+  pm.mask = a.priv_mask;
+  for (int l = 0; l < 4; ++l) {
+    pm.po[l] = a.priv_off[l];
+    pm.pc[l] = counts[l];
+    pm.go[l] = a.g.off[l];
+  }
+  hipError_t e = launch_colsum_stage1(a.priv_partial, n_part, a.priv_floats, tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(priv_stage2_kernel, dim3((a.priv_floats + 255) / 256), dim3(256), 0, st, tmp, a.priv_floats,
+                     pm, a.grad_grid);
+  return hipGetLastError();
+}
+
+void plan_privatised_levels(FieldArgs& a, int counts[4]) {
+  a.priv_mask = 0;
+  a.priv_floats = 0;
+  for (int l = 0; l < 4; ++l) {
+    const long long nv = (long long)a.g.nx[l] * a.g.ny[l] * a.g.nz[l];
+    counts[l] = 0;
+    a.priv_off[l] = 0;
+    if (a.priv_floats + 4 * nv <= kPrivMaxFloats) {
+      a.priv_mask |= 1 << l;
+      a.priv_off[l] = a.priv_floats;
+      counts[l] = (int)(4 * nv);
+      a.priv_floats += (int)(4 * nv);
+    }
+  }
+}
+
+int priv_max_floats() { return kPrivMaxFloats; }
+
 hipError_t launch_field(const FieldArgs& a, int mode, bool bwd, int blocks, hipStream_t st) {
-  const size_t smem = kSmemBytes;
+  const size_t smem = kSmemBytes + (bwd ? (size_t)a.priv_floats * sizeof(float) : 0);
   if (mode == 0 && !bwd) hipLaunchKernelGGL((field_kernel<0, false>), dim3(blocks), dim3(kBlock), smem, st, a);
   else if (mode == 0) hipLaunchKernelGGL((field_kernel<0, true>), dim3(blocks), dim3(kBlock), smem, st, a);
   else if (!bwd) hipLaunchKernelGGL((field_kernel<1, false>), dim3(blocks), dim3(kBlock), smem, st, a);

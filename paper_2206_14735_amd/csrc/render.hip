@@ -300,30 +300,78 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const float* __restric
   }
 }
 
-// grads.mlp += sum over block partials (+ per-ray dv terms), fixed order per entry
-__global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ partial, int n_part,
-                                                          const float* __restrict__ ray_dv, int M,
+// Column sums of a [rows][cols] matrix of block partials, in two fixed-order
+// stages: block (x, y) sums rows y, y + R1, y + 2 R1, ... of columns
+// 256x .. 256x + 255 into tmp[y][col]; the second stage sums the R1 rows of tmp.
+constexpr int kR1 = 64;
+
+__global__ __launch_bounds__(256) void colsum_stage1_kernel(const float* __restrict__ part, int rows, int cols,
+                                                            float* __restrict__ tmp) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  if (e >= cols) return;
+  float s0 = 0.f, s1 = 0.f;
+  int r = y;
+  for (; r + kR1 < rows; r += 2 * kR1) {
+    s0 += part[(size_t)r * cols + e];
+    s1 += part[(size_t)(r + kR1) * cols + e];
+  }
+  if (r < rows) s0 += part[(size_t)r * cols + e];
+  tmp[(size_t)y * cols + e] = s0 + s1;
+}
+
+__device__ __forceinline__ float colsum_stage2(const float* __restrict__ tmp, int cols, int e) {
+  float s = 0.f;
+#pragma unroll 8
+  for (int y = 0; y < kR1; ++y) s += tmp[(size_t)y * cols + e];
+  return s;
+}
+
+// grads.mlp += column sums (all entries but v)
+__global__ __launch_bounds__(256) void grad_stage2_kernel(const float* __restrict__ tmp,
                                                           float* __restrict__ grad_mlp) {
   const int e = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x == gridDim.x - 1) {
-    // last block: the v entry from the per-ray terms
-    __shared__ float red[256];
-    float s = 0.f;
-    for (int m = threadIdx.x; m < M; m += 256) s += ray_dv[m];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) grad_mlp[oV] += red[0];
-    return;
-  }
   if (e >= kMlpNumel || e == oV) return;
-  float s = 0.f;
-  for (int b = 0; b < n_part; ++b) s += partial[(size_t)b * kMlpNumel + e];
-  grad_mlp[e] += s;
+  grad_mlp[e] += colsum_stage2(tmp, kMlpNumel, e);
 }
+
+// grads.mlp[v] += sum over rays of the per-ray dL/dv terms (fixed order)
+__global__ __launch_bounds__(1024) void dv_reduce_kernel(const float* __restrict__ ray_dv, int M,
+                                                         float* __restrict__ grad_mlp) {
+  __shared__ float red[1024];
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  int m = threadIdx.x;
+  for (; m + 3 * 1024 < M; m += 4 * 1024) {
+    s0 += ray_dv[m];
+    s1 += ray_dv[m + 1024];
+    s2 += ray_dv[m + 2048];
+    s3 += ray_dv[m + 3072];
+  }
+  for (; m < M; m += 1024) s0 += ray_dv[m];
+  red[threadIdx.x] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad_mlp[oV] += red[0];
+}
+
+hipError_t launch_colsum_stage1(const float* part, int rows, int cols, float* tmp, hipStream_t st) {
+  hipLaunchKernelGGL(colsum_stage1_kernel, dim3((cols + 255) / 256, kR1), dim3(256), 0, st, part, rows, cols, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
+                              float* tmp, hipStream_t st) {
+  hipError_t e = launch_colsum_stage1(partial, n_part, kMlpNumel, tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(grad_stage2_kernel, dim3((kMlpNumel + 255) / 256), dim3(256), 0, st, tmp, grad_mlp);
+  hipLaunchKernelGGL(dv_reduce_kernel, dim3(1), dim3(1024), 0, st, ray_dv, M, grad_mlp);
+  return hipGetLastError();
+}
+
+int colsum_rows() { return kR1; }
 
 // ---------------------------------------------------------------- Adam
 __global__ __launch_bounds__(256) void adam_kernel(float4* __restrict__ gp, float4* __restrict__ gg,
@@ -377,13 +425,6 @@ hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smoo
                               const float lam[6], float* losses, hipStream_t st) {
   hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, ray_partial, M, smooth_partial, n_sp, S,
                      lam[0], lam[1], lam[2], lam[3], lam[4], lam[5], losses);
-  return hipGetLastError();
-}
-
-hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
-                              hipStream_t st) {
-  const int blocks = (kMlpNumel + 255) / 256 + 1;
-  hipLaunchKernelGGL(grad_reduce_kernel, dim3(blocks), dim3(256), 0, st, partial, n_part, ray_dv, M, grad_mlp);
   return hipGetLastError();
 }
 

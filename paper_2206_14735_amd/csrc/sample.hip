@@ -1,9 +1,9 @@
 // Ray batch and smoothness-point sampling on the device.
 //
-// Thread m < M builds ray m: Philox picks a pixel of any frame, the pixel is
-// back-projected through the pinhole, and its samples are generated in order
-// by merging the stratified list over the span with the stratified list
-// around the observed depth.  Threads M .. M+S-1 build the smoothness pairs.
+// Ray m is built by one wave: Philox picks a pixel of any frame, the pixel is
+// back-projected through the pinhole, and its samples are the stratified list
+// over the span merged in order with the stratified list around the observed
+// depth.  Smoothness pairs are built one per thread.
 #include "args.h"
 
 namespace gs {
@@ -51,105 +51,134 @@ struct UniformStream {
   }
 };
 
-__global__ __launch_bounds__(256) void sample_kernel(SampleArgs A) {
-  const int gid = blockIdx.x * 256 + threadIdx.x;
+// One wave per ray.  Every sample value is computed by one lane; its place
+// in the merged order is its index in its own list plus the number of values
+// of the other list that precede it (stratified first on ties), counted with
+// the same float32 values on every lane, so the ranks form a permutation.
+__global__ __launch_bounds__(256) void sample_rays_kernel(SampleArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (m >= A.M) return;
   const unsigned long long thw = (unsigned long long)A.T * A.H * A.W;
-  if (gid < A.M) {
-    const int m = gid;
-    const U4 w0 = philox((uint32_t)m, A.step, 0u, 0u, A.k0, A.k1);
-    const unsigned long long pix = pick_pixel(w0.x, thw);
-    const PixelRay pr = pixel_ray(A, pix);
-    const float D = A.depth[pix];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      A.o[3 * m + a] = pr.o[a];
-      A.r[3 * m + a] = pr.r[a];
-      A.rgb_out[3 * m + a] = (float)A.rgb[3 * pix + a] / 255.f;
-    }
+  const U4 w0 = philox((uint32_t)m, A.step, 0u, 0u, A.k0, A.k1);
+  const unsigned long long pix = pick_pixel(w0.x, thw);
+  const PixelRay pr = pixel_ray(A, pix);
+  const float D = A.depth[pix];
+  if (lane < 3) {
+    A.o[3 * m + lane] = pr.o[lane];
+    A.r[3 * m + lane] = pr.r[lane];
+    A.rgb_out[3 * m + lane] = (float)A.rgb[3 * pix + lane] / 255.f;
+  }
+  if (lane == 0) {
     A.depth_out[m] = D;
     if (A.pixel) A.pixel[m] = (long long)pix;
-    float tn = A.near_t, tf = A.far_t;
-    if (A.span_mode == GOSURF_SPAN_BOX) {
-      float tmin = -INFINITY, tmax = INFINITY;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const float ta = (A.g.p0[a] - pr.o[a]) / pr.r[a];
-        const float tb = (A.g.p1[a] - pr.o[a]) / pr.r[a];
-        tmin = fmaxf(tmin, fminf(ta, tb));   // NaN (0/0) is ignored by fmin/fmax
-        tmax = fminf(tmax, fmaxf(ta, tb));
-      }
-      tn = fmaxf(tmin, A.near_t);
-      tf = fmaxf(fminf(tmax, A.far_t), tn);
-    }
-    const int n_tot = A.n_strat + A.n_near;
-    const size_t base = (size_t)m * n_tot;
-    UniformStream us{(uint32_t)m, A.step, 1u, A.k0, A.k1, -1, {}};
-    UniformStream un{(uint32_t)m, A.step, 2u, A.k0, A.k1, -1, {}};
-    if (D > 0.f && A.n_near > 0) {
-      const float ds = (tf - tn) / (float)A.n_strat;
-      const float lo = D - A.trunc, dn = (2.f * A.trunc) / (float)A.n_near;
-      int i = 0, jn = 0;
-      float a = tn + ((float)0 + us.get(0)) * ds;
-      float b = lo + ((float)0 + un.get(0)) * dn;
-      for (int k = 0; k < n_tot; ++k) {
-        const bool take_a = jn >= A.n_near || (i < A.n_strat && a <= b);
-        if (take_a) {
-          A.t[base + k] = a;
-          ++i;
-          if (i < A.n_strat) a = tn + ((float)i + us.get(i)) * ds;
-        } else {
-          A.t[base + k] = b;
-          ++jn;
-          if (jn < A.n_near) b = lo + ((float)jn + un.get(jn)) * dn;
-        }
-        A.ray_of[base + k] = m;
-      }
-    } else {
-      const float ds = (tf - tn) / (float)n_tot;
-      for (int k = 0; k < n_tot; ++k) {
-        A.t[base + k] = tn + ((float)k + us.get(k)) * ds;
-        A.ray_of[base + k] = m;
-      }
-    }
-    A.seg[m] = (int)base;
-    if (m == A.M - 1) A.seg[A.M] = (int)((size_t)A.M * n_tot);
-  } else if (gid < A.M + A.S) {
-    const int p = gid - A.M;
-    int found = -1;
-    U4 wf{};
-    unsigned long long pix = 0;
-    for (int att = 0; att < 8; ++att) {
-      const U4 w = philox((uint32_t)p, A.step, 3u, (uint32_t)att, A.k0, A.k1);
-      const unsigned long long c = pick_pixel(w.x, thw);
-      if (A.depth[c] > 0.f) { found = att; wf = w; pix = c; break; }
-    }
-    if (found < 0) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        A.xs[3 * p + a] = 0.5f * (A.g.p0[a] + A.g.p1[a]);
-        A.eps[3 * p + a] = 0.f;
-      }
-      return;
-    }
-    const PixelRay pr = pixel_ray(A, pix);
-    const float d = A.depth[pix] + (2.f * u01(wf.y) - 1.f) * A.trunc;
-    const float zc = 1.f - 2.f * u01(wf.z);
-    const float ph = 6.283185307179586f * u01(wf.w);
-    const float rr = sqrtf(fmaxf(0.f, 1.f - zc * zc));
-    float sn, cs;
-    sincosf(ph, &sn, &cs);
-    const float e[3] = {rr * cs, rr * sn, zc};
+  }
+  float tn = A.near_t, tf = A.far_t;
+  if (A.span_mode == GOSURF_SPAN_BOX) {
+    float tmin = -INFINITY, tmax = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      A.xs[3 * p + a] = pr.o[a] + d * pr.r[a];
-      A.eps[3 * p + a] = A.delta_s * e[a];
+      const float ta = (A.g.p0[a] - pr.o[a]) / pr.r[a];
+      const float tb = (A.g.p1[a] - pr.o[a]) / pr.r[a];
+      tmin = fmaxf(tmin, fminf(ta, tb));   // NaN (0/0) is ignored by fmin/fmax
+      tmax = fminf(tmax, fmaxf(ta, tb));
     }
+    tn = fmaxf(tmin, A.near_t);
+    tf = fmaxf(fminf(tmax, A.far_t), tn);
+  }
+  const int n_tot = A.n_strat + A.n_near;
+  const bool two = D > 0.f && A.n_near > 0;
+  const int ns = two ? A.n_strat : n_tot;   // stratified count over the span
+  const int nn = two ? A.n_near : 0;        // near-depth count
+  const float ds = (tf - tn) / (float)ns;
+  const float lo = D - A.trunc, dn = (2.f * A.trunc) / (float)(nn > 0 ? nn : 1);
+  const size_t base = (size_t)m * n_tot;
+  float av[kChunks], bv[kChunks];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const int i = 64 * c + lane;
+    av[c] = bv[c] = 0.f;
+    if (i < ns) {
+      const U4 w = philox((uint32_t)m, A.step, 1u, (uint32_t)(i >> 2), A.k0, A.k1);
+      const uint32_t x = (i & 3) == 0 ? w.x : ((i & 3) == 1 ? w.y : ((i & 3) == 2 ? w.z : w.w));
+      av[c] = tn + ((float)i + u01(x)) * ds;
+    }
+    if (i < nn) {
+      const U4 w = philox((uint32_t)m, A.step, 2u, (uint32_t)(i >> 2), A.k0, A.k1);
+      const uint32_t x = (i & 3) == 0 ? w.x : ((i & 3) == 1 ? w.y : ((i & 3) == 2 ? w.z : w.w));
+      bv[c] = lo + ((float)i + u01(x)) * dn;
+    }
+  }
+  // ranks: stratified value a_i precedes near value b_j iff a_i <= b_j
+  int ra[kChunks], rb[kChunks];
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) { ra[c] = 64 * c + lane; rb[c] = 64 * c + lane; }
+#pragma unroll
+  for (int c2 = 0; c2 < kChunks; ++c2) {
+    const int cnt_b = nn - 64 * c2, cnt_a = (nn > 0 ? ns : 0) - 64 * c2;
+    for (int l2 = 0; l2 < (cnt_b < 64 ? cnt_b : 64); ++l2) {
+      const float b = __shfl(bv[c2], l2, 64);
+#pragma unroll
+      for (int c = 0; c < kChunks; ++c) ra[c] += (b < av[c]) ? 1 : 0;
+    }
+    for (int l2 = 0; l2 < (cnt_a < 64 ? cnt_a : 64); ++l2) {
+      const float a = __shfl(av[c2], l2, 64);
+#pragma unroll
+      for (int c = 0; c < kChunks; ++c) rb[c] += (a <= bv[c]) ? 1 : 0;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kChunks; ++c) {
+    const int i = 64 * c + lane;
+    if (i < ns) A.t[base + ra[c]] = av[c];
+    if (i < nn) A.t[base + rb[c]] = bv[c];
+    if (i < n_tot) A.ray_of[base + i] = m;
+  }
+  if (lane == 0) {
+    A.seg[m] = (int)base;
+    if (m == A.M - 1) A.seg[A.M] = (int)((size_t)A.M * n_tot);
+  }
+}
+
+// One thread per smoothness pair.
+__global__ __launch_bounds__(256) void sample_points_kernel(SampleArgs A) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= A.S) return;
+  const unsigned long long thw = (unsigned long long)A.T * A.H * A.W;
+  int found = -1;
+  U4 wf{};
+  unsigned long long pix = 0;
+  for (int att = 0; att < 8; ++att) {
+    const U4 w = philox((uint32_t)p, A.step, 3u, (uint32_t)att, A.k0, A.k1);
+    const unsigned long long c = pick_pixel(w.x, thw);
+    if (A.depth[c] > 0.f) { found = att; wf = w; pix = c; break; }
+  }
+  if (found < 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      A.xs[3 * p + a] = 0.5f * (A.g.p0[a] + A.g.p1[a]);
+      A.eps[3 * p + a] = 0.f;
+    }
+    return;
+  }
+  const PixelRay pr = pixel_ray(A, pix);
+  const float d = A.depth[pix] + (2.f * u01(wf.y) - 1.f) * A.trunc;
+  const float zc = 1.f - 2.f * u01(wf.z);
+  const float ph = 6.283185307179586f * u01(wf.w);
+  const float rr = sqrtf(fmaxf(0.f, 1.f - zc * zc));
+  float sn, cs;
+  sincosf(ph, &sn, &cs);
+  const float e[3] = {rr * cs, rr * sn, zc};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    A.xs[3 * p + a] = pr.o[a] + d * pr.r[a];
+    A.eps[3 * p + a] = A.delta_s * e[a];
   }
 }
 
 hipError_t launch_sample(const SampleArgs& a, hipStream_t st) {
-  const int n = a.M + a.S;
-  hipLaunchKernelGGL(sample_kernel, dim3((n + 255) / 256), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(sample_rays_kernel, dim3((a.M + 3) / 4), dim3(256), 0, st, a);
+  if (a.S > 0) hipLaunchKernelGGL(sample_points_kernel, dim3((a.S + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

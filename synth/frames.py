@@ -67,9 +67,9 @@ def render_frames(scene, c2w, H, W, fx, fy, cx=None, cy=None, noise_seed=None,
     cx = W / 2.0 if cx is None else cx
     cy = H / 2.0 if cy is None else cy
     T = c2w.shape[0]
-    rgb = torch.zeros(T, H, W, 3, dtype=torch.uint8)
-    depth = torch.zeros(T, H, W, dtype=torch.float32)
-    depth_gt = torch.zeros(T, H, W, dtype=torch.float32)
+    rgb = torch.zeros(T, H, W, 3, dtype=torch.uint8, device=device)
+    depth = torch.zeros(T, H, W, dtype=torch.float32, device=device)
+    depth_gt = torch.zeros(T, H, W, dtype=torch.float32, device=device)
     vv, uu = torch.meshgrid(torch.arange(H, dtype=torch.float64, device=device),
                             torch.arange(W, dtype=torch.float64, device=device), indexing="ij")
     dcam = torch.stack([(uu + 0.5 - cx) / fx, (vv + 0.5 - cy) / fy, torch.ones_like(uu)], -1)
@@ -84,15 +84,15 @@ def render_frames(scene, c2w, H, W, fx, fy, cx=None, cy=None, noise_seed=None,
         col = col.reshape(d.shape)
         hit = torch.isfinite(t)
         z = torch.where(hit, t, torch.zeros_like(t))
-        depth_gt[s:s + chunk] = z.float().cpu()
+        depth_gt[s:s + chunk] = z.float()
         if noise_coeff > 0:
             n = torch.randn(z.shape, generator=gen, dtype=torch.float64).to(device)
             z = torch.where(hit, (z + noise_coeff * z * z * n).clamp(min=1e-3), z)
         if max_range is not None:
             z = torch.where(z > max_range, torch.zeros_like(z), z)
-        depth[s:s + chunk] = z.float().cpu()
-        rgb[s:s + chunk] = (col * 255.0).round().clamp(0, 255).to(torch.uint8).cpu()
-    return Frames(rgb, depth, c2w.float(), float(fx), float(fy), float(cx), float(cy), depth_gt)
+        depth[s:s + chunk] = z.float()
+        rgb[s:s + chunk] = (col * 255.0).round().clamp(0, 255).to(torch.uint8)
+    return Frames(rgb, depth, c2w.float().to(device), float(fx), float(fy), float(cx), float(cy), depth_gt)
 
 
 def sphere_frames(H=60, W=80, f=60.0):
