@@ -18,6 +18,11 @@
  *                       Sampler", Eqs. second_sdf_grad_theta, second_sdf_grad_omega)
  *   gosurf_adam_step    Adam over all parameters (implementation details)
  *
+ * A precision variant runs the decoders in bfloat16 on the matrix cores with
+ * float32 accumulation and reads grid features from a bfloat16 mirror of the
+ * float32 master table (GOSURF_BF16); rendering, losses, gradient
+ * accumulation and Adam stay float32.
+ *
  * Conventions shared by every call
  * --------------------------------
  * - All array pointers are DEVICE pointers to caller-owned memory, contiguous,
@@ -240,6 +245,12 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
                               const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
                               const gosurf_fwd_out* fwd, float loss_scale, gosurf_grads* grads,
                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Round the float32 grid to its bfloat16 mirror (round to nearest even), as
+   gosurf_adam_step does after every update; call once before the first
+   GOSURF_BF16 forward.  numel = 4 * n_vertices.  Errors: NULL, SHAPE, ALIGN,
+   HIP. */
+gosurf_status gosurf_refresh_bf16(const float* grid, uint16_t* grid_bf16, int64_t numel, void* stream);
 
 /* Adam (Kingma & Ba) with bias correction over both groups, dense: every
    entry is updated, touched or not.  g = grad * inv_loss_scale;

@@ -9,6 +9,7 @@ constexpr int kChunks = GOSURF_MAX_SAMPLES_PER_RAY / 64;
 struct FieldArgs {
   Grid g;
   const float* grid;
+  const uint16_t* grid_bf16;   // non-null: BF16 decoders and gathers from this mirror
   const float* mlp;
   // ray samples
   const float* o;

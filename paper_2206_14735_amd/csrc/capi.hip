@@ -25,6 +25,7 @@ hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray
                               float* tmp, hipStream_t st);
 hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st);
 hipError_t launch_sample(const SampleArgs& a, hipStream_t st);
+hipError_t launch_to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t st);
 
 }  // namespace gs
 
@@ -229,8 +230,6 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   if (!out || !out->rgb_hat || !out->depth_hat || !out->wsum || !out->losses || !out->saved)
     return fail(GOSURF_ERR_NULL, "a forward output array is NULL");
   if (!aligned(out->saved, 16)) return fail(GOSURF_ERR_ALIGN, "out.saved must be 16-byte aligned");
-  if (model->precision != GOSURF_FP32)
-    return fail(GOSURF_ERR_VALUE, "this build implements the GOSURF_FP32 decoders only");
   const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
   if (!ws || ws_bytes < w.bytes)
     return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
@@ -242,6 +241,7 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
 
   gs::FieldArgs fa{};
   fa.g = g; fa.grid = params->grid; fa.mlp = params->mlp;
+  fa.grid_bf16 = model->precision == GOSURF_BF16 ? params->grid_bf16 : nullptr;
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S;
   fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
@@ -279,8 +279,6 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   if (!grads || !grads->grid || !grads->mlp) return fail(GOSURF_ERR_NULL, "gradient buffers are NULL");
   if (!aligned(grads->grid, 16)) return fail(GOSURF_ERR_ALIGN, "grads.grid must be 16-byte aligned");
   if (!(loss_scale > 0.f) || !std::isfinite(loss_scale)) return fail(GOSURF_ERR_VALUE, "loss_scale must be > 0");
-  if (model->precision != GOSURF_FP32)
-    return fail(GOSURF_ERR_VALUE, "this build implements the GOSURF_FP32 decoders only");
   const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
   if (!ws || ws_bytes < w.bytes)
     return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
@@ -300,6 +298,7 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
 
   gs::FieldArgs fa{};
   fa.g = g; fa.grid = params->grid; fa.mlp = params->mlp;
+  fa.grid_bf16 = model->precision == GOSURF_BF16 ? params->grid_bf16 : nullptr;
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S;
   fa.seed4 = w.seed4; fa.eikw = w.eikw; fa.need_gx = need_gx;
@@ -322,6 +321,17 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
     return st;
   if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nbr + nbs, w.ray_dv, b->M, grads->mlp, w.colsum_tmp, s),
                       "grad reduce")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
+gosurf_status gosurf_refresh_bf16(const float* grid, uint16_t* grid_bf16, int64_t numel, void* stream) {
+  if (!grid || !grid_bf16) return fail(GOSURF_ERR_NULL, "grid and grid_bf16 must not be NULL");
+  if (numel < 0 || numel % 4) return fail(GOSURF_ERR_SHAPE, "numel must be a non-negative multiple of 4");
+  if (!aligned(grid, 16) || !aligned(grid_bf16, 8)) return fail(GOSURF_ERR_ALIGN, "grid 16-B, mirror 8-B aligned");
+  gosurf_status st;
+  if ((st = hip_check(gs::launch_to_bf16(grid, grid_bf16, numel, (hipStream_t)stream), "bf16 refresh")) !=
+      GOSURF_OK)
     return st;
   return ok();
 }

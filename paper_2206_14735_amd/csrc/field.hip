@@ -62,54 +62,88 @@ __device__ float table_value(const float* __restrict__ P, int slot, int l) {
   }
 }
 
-// out[bo] = sum over input blocks/steps of A(slot) * in   (NBO output blocks of 16 rows)
-template <int NBO, int NBI>
-__device__ __forceinline__ void layer(const float* __restrict__ tab, int base, const v4f* in, v4f* out,
-                                      int lane) {
-#pragma unroll
-  for (int bo = 0; bo < NBO; ++bo) out[bo] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int bi = 0; bi < NBI; ++bi)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int bo = 0; bo < NBO; ++bo)
-        out[bo] = mfma4(tab[(base + bo * 4 * NBI + bi * 4 + r) * 64 + lane], in[bi][r], out[bo]);
+__device__ __forceinline__ v4s pack_bf16(v4f x) {
+  return v4s{(short)f2bf(x[0]), (short)f2bf(x[1]), (short)f2bf(x[2]), (short)f2bf(x[3])};
+}
+__device__ __forceinline__ v4s pack_bf16(float4 x) {
+  return v4s{(short)f2bf(x.x), (short)f2bf(x.y), (short)f2bf(x.z), (short)f2bf(x.w)};
+}
+__device__ __forceinline__ v4s as_v4s(uint2 u) {
+  v4s r;
+  __builtin_memcpy(&r, &u, sizeof(r));
+  return r;
 }
 
-// LDS scratch row stride for transposed [sample][row] tiles
-constexpr int RS = 36;
+// out[bo] = sum over input blocks/steps of A(slot) * in   (NBO output blocks of 16 rows).
+// FP32: 4 steps of 16x16x4 per input block; BF16: one 16x16x16 per input block
+// whose A operand packs the four fp32 steps' values of the same lane.
+template <bool BF, int NBO, int NBI, class Smem>
+__device__ __forceinline__ void layer(const Smem& sm, int base, const v4f* in, v4f* out, int lane) {
+#pragma unroll
+  for (int bo = 0; bo < NBO; ++bo) out[bo] = v4f{0.f, 0.f, 0.f, 0.f};
+  if constexpr (BF) {
+#pragma unroll
+    for (int bi = 0; bi < NBI; ++bi) {
+      const v4s b = pack_bf16(in[bi]);
+#pragma unroll
+      for (int bo = 0; bo < NBO; ++bo)
+        out[bo] = mfma16_bf16(as_v4s(sm.tabbf[(base / 4 + bo * NBI + bi) * 64 + lane]), b, out[bo]);
+    }
+  } else {
+#pragma unroll
+    for (int bi = 0; bi < NBI; ++bi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int bo = 0; bo < NBO; ++bo)
+          out[bo] = mfma4(sm.tab[(base + bo * 4 * NBI + bi * 4 + r) * 64 + lane], in[bi][r], out[bo]);
+  }
+}
+
+// LDS scratch of one operand: [row][sample], 16 samples + 4 floats of padding
+// per row (rows of the four lane groups land in different banks).
+constexpr int RSR = 20;
 
 template <int NB>
-__device__ __forceinline__ void store_T(float* scr, const v4f* X, int q, int j) {
+__device__ __forceinline__ void store_rows(float* scr, const v4f* X, int q, int j) {
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) scr[j * RS + 16 * b + 4 * q + r] = X[b][r];
+    for (int r = 0; r < 4; ++r) scr[(16 * b + 4 * q + r) * RSR + j] = X[b][r];
 }
 
-// acc[ba][bb] += sum over the tile's 16 samples of A[16ba + i][s] * B[16bb + j][s]
-template <int NA, int NB>
+// acc[ba][bb] += sum over the tile's 16 samples of A[16ba + i][s] * B[16bb + n][s].
+// The sample axis is the MFMA K axis; lane group q supplies samples 4q..4q+3
+// (one 16-byte LDS read per operand block).
+template <bool BF, int NA, int NB>
 __device__ __forceinline__ void outer_acc(float* scrA, float* scrB, const v4f* A, const v4f* B, v4f* acc,
                                           int q, int j) {
-  store_T<NA>(scrA, A, q, j);
-  store_T<NB>(scrB, B, q, j);
+  store_rows<NA>(scrA, A, q, j);
+  store_rows<NB>(scrB, B, q, j);
   wave_lds_fence();
+  float4 av[NA], bv[NB];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    float av[NA], bv[NB];
+  for (int a = 0; a < NA; ++a) av[a] = *reinterpret_cast<const float4*>(scrA + (16 * a + j) * RSR + 4 * q);
 #pragma unroll
-    for (int a = 0; a < NA; ++a) av[a] = scrA[(4 * m + q) * RS + 16 * a + j];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) bv[b] = scrB[(4 * m + q) * RS + 16 * b + j];
+  for (int b = 0; b < NB; ++b) bv[b] = *reinterpret_cast<const float4*>(scrB + (16 * b + j) * RSR + 4 * q);
+  if constexpr (BF) {
 #pragma unroll
     for (int a = 0; a < NA; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) acc[a * NB + b] = mfma4(av[a], bv[b], acc[a * NB + b]);
+      for (int b = 0; b < NB; ++b) acc[a * NB + b] = mfma16_bf16(pack_bf16(av[a]), pack_bf16(bv[b]), acc[a * NB + b]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        acc[a * NB + b] = mfma4(av[a].x, bv[b].x, acc[a * NB + b]);
+        acc[a * NB + b] = mfma4(av[a].y, bv[b].y, acc[a * NB + b]);
+        acc[a * NB + b] = mfma4(av[a].z, bv[b].z, acc[a * NB + b]);
+        acc[a * NB + b] = mfma4(av[a].w, bv[b].w, acc[a * NB + b]);
+      }
   }
   wave_lds_fence();
 }
-
 
 // per-lane gather state of one level
 struct LevelSample {
@@ -139,9 +173,9 @@ __device__ __forceinline__ void locate(const Grid& g, int q, float x, float y, f
 }
 
 // trilinear value (z) and, optionally, dz/dx (G[k][axis]) of one level
-template <bool NEED_G>
-__device__ __forceinline__ void interp(const float* __restrict__ grid, const LevelSample& ls, bool valid,
-                                       float z[4], float G[4][3]) {
+template <bool NEED_G, bool BF>
+__device__ __forceinline__ void interp(const float* __restrict__ grid, const uint16_t* __restrict__ grid_bf,
+                                       const LevelSample& ls, bool valid, float z[4], float G[4][3]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) { z[k] = 0.f; G[k][0] = G[k][1] = G[k][2] = 0.f; }
   if (!valid) return;
@@ -151,7 +185,13 @@ __device__ __forceinline__ void interp(const float* __restrict__ grid, const Lev
   for (int c = 0; c < 8; ++c) {
     const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
     const long long row = ls.row + bx + (long long)by * ls.sy + (long long)bz * ls.sz;
-    th[c] = *reinterpret_cast<const float4*>(grid + row * 4);
+    if constexpr (BF) {
+      const uint2 u = *reinterpret_cast<const uint2*>(grid_bf + row * 4);
+      th[c] = make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                          __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+    } else {
+      th[c] = *reinterpret_cast<const float4*>(grid + row * 4);
+    }
   }
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -193,14 +233,28 @@ __device__ __forceinline__ void run_step(float (&val)[8][4], int segid, int j) {
     }
 }
 
+// Per-wave LDS staging of the scatter: 64 lanes x 32 floats, the head list
+// and the corner-000 row of each head lane.
+struct ScatterStage {
+  float* val;   // [64][32]: per lane, 4 segments (by, bz) of 8 floats (bx, feature)
+  int* heads;   // [64] lane ids of the writing lanes, in lane order
+  int* rows;    // [64] corner-000 row of each lane
+};
+
 // grid scatter: dL/dtheta_c,k = w_c dz_k + a_k (J_c . gvec) / v.
-// The 16 lanes of a level group hold 16 consecutive samples, so runs of
-// samples in the same cell sit in neighbouring lanes: a segmented sum merges
-// each run into its first lane, which alone updates the 32 features, either
-// in the block's LDS copy of a small level or with float atomics in HBM.
+// 1. The 16 lanes of a level group hold 16 consecutive samples, so runs of
+//    samples in the same cell sit in neighbouring lanes: a segmented sum
+//    merges each run into its first lane (the writer).
+// 2. Each writer's 32 values are 4 segments of 8 contiguous floats (the two
+//    x-neighbour vertices of one (by, bz) edge, 4 features each).  Writers
+//    stage them in LDS; then 8 lanes handle one segment, so every atomic
+//    instruction covers 8 contiguous 32-byte segments instead of 64
+//    scattered words (the memory system processes atomics per segment).
+// 3. Small levels go to the block's LDS copy, the others to HBM.
 template <bool HAS_DZ, bool HAS_GV>
-__device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, int q, int j, const LevelSample& ls,
-                                        bool valid, const float dz[4], const float a[4], const float gv[3]) {
+__device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const ScatterStage& S, int lane, int q,
+                                        int j, const LevelSample& ls, bool valid, const float dz[4],
+                                        const float a[4], const float gv[3]) {
   const float fx = ls.f[0], fy = ls.f[1], fz = ls.f[2];
   float val[8][4];
 #pragma unroll
@@ -233,22 +287,44 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, int q, 
   run_step<kRowShl2, 2>(val, segid, j);
   run_step<kRowShl4, 4>(val, segid, j);
   run_step<kRowShl8, 8>(val, segid, j);
-  if (!(head && valid)) return;
-  const bool in_lds = (A.priv_mask >> q) & 1;
+
+  const bool writer = head && valid;
+  const unsigned long long wm = __ballot(writer);
+  const int nw = __popcll(wm);
+  if (writer) {
+    const int rank = __popcll(wm & ((1ull << lane) - 1ull));
+    S.heads[rank] = lane;
+    S.rows[lane] = (int)ls.row;
+    float* st = S.val + lane * 32;
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
-    const long long row = ls.row + bx + (long long)by * ls.sy + (long long)bz * ls.sz;
-    if (in_lds) {
-      float* p = priv + A.priv_off[q] + (int)(row - A.g.off[q]) * 4;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) atomicAdd(p + k, val[c][k]);
-    } else {
-      float* p = A.grad_grid + row * 4;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) atomicAdd(p + k, val[c][k]);
+    for (int sg = 0; sg < 4; ++sg) {
+      const int c0 = sg, c1 = 4 + sg;   // corners (0, by, bz) and (1, by, bz), sg = 2 by + bz
+      *reinterpret_cast<float4*>(st + 8 * sg) = make_float4(val[c0][0], val[c0][1], val[c0][2], val[c0][3]);
+      *reinterpret_cast<float4*>(st + 8 * sg + 4) = make_float4(val[c1][0], val[c1][1], val[c1][2], val[c1][3]);
     }
   }
+  wave_lds_fence();
+  const int jobs = 4 * nw;
+  const int f = lane & 7;
+  for (int base = 0; base < jobs; base += 8) {
+    const int k = base + (lane >> 3);
+    if (k < jobs) {
+      const int h = S.heads[k >> 2], sg = k & 3;
+      const int lq = h >> 4;
+      const float v = S.val[h * 32 + 8 * sg + f];
+      const int nx = lq == 0 ? A.g.nx[0] : lq == 1 ? A.g.nx[1] : lq == 2 ? A.g.nx[2] : A.g.nx[3];
+      const int ny = lq == 0 ? A.g.ny[0] : lq == 1 ? A.g.ny[1] : lq == 2 ? A.g.ny[2] : A.g.ny[3];
+      const long long row = (long long)S.rows[h] + (long long)(sg >> 1) * nx + (long long)(sg & 1) * nx * ny;
+      if ((A.priv_mask >> lq) & 1) {
+        const int po = lq == 0 ? A.priv_off[0] : lq == 1 ? A.priv_off[1] : lq == 2 ? A.priv_off[2] : A.priv_off[3];
+        const long long go = lq == 0 ? A.g.off[0] : lq == 1 ? A.g.off[1] : lq == 2 ? A.g.off[2] : A.g.off[3];
+        atomicAdd(priv + po + (int)(row - go) * 4 + f, v);
+      } else {
+        atomicAdd(A.grad_grid + row * 4 + f, v);
+      }
+    }
+  }
+  wave_lds_fence();
 }
 
 __device__ __forceinline__ v4f relu_mask(v4f x, v4f h) {
@@ -266,10 +342,13 @@ __device__ __forceinline__ float sum16(float v) {   // over the 16 lanes of one 
 
 // LDS footprint of one block
 struct FieldSmem {
-  float tab[T_END * 64];
+  float tab[T_END * 64];                // fp32 A operands, one float per lane per step
+  uint2 tabbf[(T_END / 4) * 64];        // bf16 A operands, four values per lane per block
   float bias[32 + 32 + 16 + 32 + 16];   // b1, b2, b3, c1, c2(pad 16)
   float w3row0[32];
-  float scr[kWavesPerBlock][2][16 * RS];
+  float scr[kWavesPerBlock][2048];       // operand transposes, then scatter staging
+  int heads[kWavesPerBlock][64];
+  int rows[kWavesPerBlock][64];
 };
 constexpr int kRedFloats = kWavesPerBlock * kMlpNumel;
 constexpr int kSmemBytes = (sizeof(FieldSmem) > kRedFloats * 4) ? sizeof(FieldSmem) : kRedFloats * 4;
@@ -277,7 +356,7 @@ constexpr int kPrivMaxFloats = 4096;   // LDS budget for privatised levels (1024
 
 // MODE 0: ray samples; MODE 1: smoothness pairs (16-lane tile = 8 pairs: lanes
 // j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).
-template <int MODE, bool BWD>
+template <int MODE, bool BWD, bool BF>
 __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   FieldSmem& sm = *reinterpret_cast<FieldSmem*>(smem_raw);
@@ -296,9 +375,19 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
     sm.bias[112 + tid] = tid < 3 ? A.mlp[oC2 + tid] : 0.f;
   }
   __syncthreads();
-  const float* tab = sm.tab;
-  float* scrA = sm.scr[wave][0];
-  float* scrB = sm.scr[wave][1];
+  if constexpr (BF) {
+    for (int e = tid; e < (T_END / 4) * 64; e += kBlock) {
+      const int slot = e >> 6, l = e & 63;
+      const float* t4 = sm.tab + (4 * slot) * 64 + l;
+      const uint32_t lo = (uint32_t)f2bf(t4[0]) | ((uint32_t)f2bf(t4[64]) << 16);
+      const uint32_t hi = (uint32_t)f2bf(t4[128]) | ((uint32_t)f2bf(t4[192]) << 16);
+      sm.tabbf[e] = make_uint2(lo, hi);
+    }
+    __syncthreads();
+  }
+  float* scrA = sm.scr[wave];
+  float* scrB = sm.scr[wave] + 32 * RSR;
+  const ScatterStage stage{sm.scr[wave], sm.heads[wave], sm.rows[wave]};
   float* priv = reinterpret_cast<float*>(smem_raw + kSmemBytes);
   if (BWD)
     for (int e = tid; e < A.priv_floats; e += kBlock) priv[e] = 0.f;
@@ -356,34 +445,34 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
     LevelSample ls;
     locate(A.g, q, px, py, pz, ls);
     float zl[4], G[4][3];
-    if (need_g) interp<true>(A.grid, ls, valid, zl, G);
-    else interp<false>(A.grid, ls, valid, zl, G);
+    if (need_g) interp<true, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
+    else interp<false, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
 
     // ---------------- geometry decoder
     v4f zb = v4f{zl[0], zl[1], zl[2], zl[3]};
     v4f h1[2], h2[2], ob, hc[2], cb;
-    layer<2, 1>(tab, T_L1, &zb, h1, lane);
+    layer<BF, 2, 1>(sm, T_L1, &zb, h1, lane);
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) h1[b][r] = fmaxf(h1[b][r] + sm.bias[16 * b + 4 * q + r], 0.f);
-    layer<2, 2>(tab, T_L2, h1, h2, lane);
+    layer<BF, 2, 2>(sm, T_L2, h1, h2, lane);
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) h2[b][r] = fmaxf(h2[b][r] + sm.bias[32 + 16 * b + 4 * q + r], 0.f);
-    layer<1, 2>(tab, T_L3, h2, &ob, lane);
+    layer<BF, 1, 2>(sm, T_L3, h2, &ob, lane);
 #pragma unroll
     for (int r = 0; r < 4; ++r) ob[r] += sm.bias[64 + 4 * q + r];
 
     // ---------------- colour decoder (ray mode)
     if (MODE == 0) {
-      layer<2, 1>(tab, T_C1, &ob, hc, lane);
+      layer<BF, 2, 1>(sm, T_C1, &ob, hc, lane);
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) hc[b][r] = fmaxf(hc[b][r] + sm.bias[80 + 16 * b + 4 * q + r], 0.f);
-      layer<1, 2>(tab, T_C2, hc, &cb, lane);
+      layer<BF, 1, 2>(sm, T_C2, hc, &cb, lane);
 #pragma unroll
       for (int r = 0; r < 4; ++r) cb[r] = sigmoidf_(cb[r] + sm.bias[112 + 4 * q + r]);
     }
@@ -396,10 +485,10 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) e2[b][r] = h2[b][r] > 0.f ? sm.w3row0[16 * b + 4 * q + r] : 0.f;
-      layer<2, 2>(tab, T_L2T, e2, e1, lane);
+      layer<BF, 2, 2>(sm, T_L2T, e2, e1, lane);
 #pragma unroll
       for (int b = 0; b < 2; ++b) e1[b] = relu_mask(e1[b], h1[b]);
-      layer<1, 2>(tab, T_L1T, e1, &ab, lane);
+      layer<BF, 1, 2>(sm, T_L1T, e1, &ab, lane);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         float v = ab[0] * G[0][a] + ab[1] * G[1][a] + ab[2] * G[2][a] + ab[3] * G[3][a];
@@ -451,26 +540,26 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
         dc2[2] = sd.w * cb[2] * (1.f - cb[2]);
       }
       v4f dhc[2], dob;
-      layer<2, 1>(tab, T_C2T, &dc2, dhc, lane);
+      layer<BF, 2, 1>(sm, T_C2T, &dc2, dhc, lane);
 #pragma unroll
       for (int b = 0; b < 2; ++b) dhc[b] = relu_mask(dhc[b], hc[b]);
-      layer<1, 2>(tab, T_C1T, dhc, &dob, lane);
+      layer<BF, 1, 2>(sm, T_C1T, dhc, &dob, lane);
       if (q == 0) dob[0] += sd.x;
       v4f dh2[2], dh1[2], dz;
-      layer<2, 1>(tab, T_L3T, &dob, dh2, lane);
+      layer<BF, 2, 1>(sm, T_L3T, &dob, dh2, lane);
 #pragma unroll
       for (int b = 0; b < 2; ++b) dh2[b] = relu_mask(dh2[b], h2[b]);
-      layer<2, 2>(tab, T_L2T, dh2, dh1, lane);
+      layer<BF, 2, 2>(sm, T_L2T, dh2, dh1, lane);
 #pragma unroll
       for (int b = 0; b < 2; ++b) dh1[b] = relu_mask(dh1[b], h1[b]);
-      layer<1, 2>(tab, T_L1T, dh1, &dz, lane);
+      layer<BF, 1, 2>(sm, T_L1T, dh1, &dz, lane);
 
       // weight gradients (sum over the tile's samples)
-      outer_acc<1, 2>(scrA, scrB, &dc2, hc, aU2, q, j);
-      outer_acc<2, 1>(scrA, scrB, dhc, &ob, aU1, q, j);
-      outer_acc<1, 2>(scrA, scrB, &dob, h2, aW3, q, j);
-      outer_acc<2, 2>(scrA, scrB, dh2, h1, aW2, q, j);
-      outer_acc<2, 1>(scrA, scrB, dh1, &zb, aW1, q, j);
+      outer_acc<BF, 1, 2>(scrA, scrB, &dc2, hc, aU2, q, j);
+      outer_acc<BF, 2, 1>(scrA, scrB, dhc, &ob, aU1, q, j);
+      outer_acc<BF, 1, 2>(scrA, scrB, &dob, h2, aW3, q, j);
+      outer_acc<BF, 2, 2>(scrA, scrB, dh2, h1, aW2, q, j);
+      outer_acc<BF, 2, 1>(scrA, scrB, dh1, &zb, aW1, q, j);
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         gB1[b] += dh1[b];
@@ -487,19 +576,19 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) qv[k] = gv[0] * G[k][0] + gv[1] * G[k][1] + gv[2] * G[k][2];
         v4f r1[2], w2r1[2];
-        layer<2, 1>(tab, T_L1, &qv, r1, lane);
+        layer<BF, 2, 1>(sm, T_L1, &qv, r1, lane);
 #pragma unroll
         for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
-        layer<2, 2>(tab, T_L2, r1, w2r1, lane);
+        layer<BF, 2, 2>(sm, T_L2, r1, w2r1, lane);
 #pragma unroll
         for (int b = 0; b < 2; ++b) gW3r0[b] += relu_mask(w2r1[b], h2[b]);
-        outer_acc<2, 2>(scrA, scrB, e2, r1, aW2, q, j);
-        outer_acc<2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
+        outer_acc<BF, 2, 2>(scrA, scrB, e2, r1, aW2, q, j);
+        outer_acc<BF, 2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
         const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
-        scatter<true, true>(A, priv, q, j, ls, valid, dzl, al, gv);
+        scatter<true, true>(A, priv, stage, lane, q, j, ls, valid, dzl, al, gv);
       } else {
         const float al[4] = {0, 0, 0, 0};
-        scatter<true, false>(A, priv, q, j, ls, valid, dzl, al, gv);
+        scatter<true, false>(A, priv, stage, lane, q, j, ls, valid, dzl, al, gv);
       }
     } else {
       // smoothness pair: d|g(x) - g(x+eps)|^2 / dg at either point is
@@ -514,17 +603,17 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) qv[k] = gv[0] * G[k][0] + gv[1] * G[k][1] + gv[2] * G[k][2];
       v4f r1[2], w2r1[2];
-      layer<2, 1>(tab, T_L1, &qv, r1, lane);
+      layer<BF, 2, 1>(sm, T_L1, &qv, r1, lane);
 #pragma unroll
       for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
-      layer<2, 2>(tab, T_L2, r1, w2r1, lane);
+      layer<BF, 2, 2>(sm, T_L2, r1, w2r1, lane);
 #pragma unroll
       for (int b = 0; b < 2; ++b) gW3r0[b] += relu_mask(w2r1[b], h2[b]);
-      outer_acc<2, 2>(scrA, scrB, e2, r1, aW2, q, j);
-      outer_acc<2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
+      outer_acc<BF, 2, 2>(scrA, scrB, e2, r1, aW2, q, j);
+      outer_acc<BF, 2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
       const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
       const float dzl[4] = {0, 0, 0, 0};
-      scatter<false, true>(A, priv, q, j, ls, pv, dzl, al, gv);
+      scatter<false, true>(A, priv, stage, lane, q, j, ls, pv, dzl, al, gv);
     }
   }
 
@@ -677,10 +766,26 @@ int priv_max_floats() { return kPrivMaxFloats; }
 
 hipError_t launch_field(const FieldArgs& a, int mode, bool bwd, int blocks, hipStream_t st) {
   const size_t smem = kSmemBytes + (bwd ? (size_t)a.priv_floats * sizeof(float) : 0);
-  if (mode == 0 && !bwd) hipLaunchKernelGGL((field_kernel<0, false>), dim3(blocks), dim3(kBlock), smem, st, a);
-  else if (mode == 0) hipLaunchKernelGGL((field_kernel<0, true>), dim3(blocks), dim3(kBlock), smem, st, a);
-  else if (!bwd) hipLaunchKernelGGL((field_kernel<1, false>), dim3(blocks), dim3(kBlock), smem, st, a);
-  else hipLaunchKernelGGL((field_kernel<1, true>), dim3(blocks), dim3(kBlock), smem, st, a);
+  const dim3 g(blocks), b(kBlock);
+  const bool bf = a.grid_bf16 != nullptr;
+#define GS_LAUNCH(M, B, F)                                                                              \
+  do {                                                                                                   \
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<M, B, F>),                           \
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);                          \
+    hipLaunchKernelGGL((field_kernel<M, B, F>), g, b, smem, st, a);                                      \
+  } while (0)
+  if (!bf) {
+    if (mode == 0 && !bwd) GS_LAUNCH(0, false, false);
+    else if (mode == 0) GS_LAUNCH(0, true, false);
+    else if (!bwd) GS_LAUNCH(1, false, false);
+    else GS_LAUNCH(1, true, false);
+  } else {
+    if (mode == 0 && !bwd) GS_LAUNCH(0, false, true);
+    else if (mode == 0) GS_LAUNCH(0, true, true);
+    else if (!bwd) GS_LAUNCH(1, false, true);
+    else GS_LAUNCH(1, true, true);
+  }
+#undef GS_LAUNCH
   return hipGetLastError();
 }
 

@@ -428,6 +428,25 @@ hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smoo
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float4* __restrict__ src, uint2* __restrict__ dst,
+                                                      long long n4) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
+    const float4 v = src[i];
+    dst[i] = make_uint2((uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16),
+                        (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16));
+  }
+}
+
+hipError_t launch_to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t st) {
+  const long long n4 = n / 4;
+  long long blocks = (n4 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<const float4*>(src),
+                     reinterpret_cast<uint2*>(dst), n4);
+  return hipGetLastError();
+}
+
 hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st) {
   const long long n4g = s.grid_numel / 4;
   const int n4m = s.mlp_numel / 4;

@@ -89,7 +89,7 @@ class AdamState(C.Structure):
 
 
 EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "gosurf_workspace_bytes",
-           "gosurf_forward", "gosurf_backward", "gosurf_adam_step")
+           "gosurf_forward", "gosurf_backward", "gosurf_adam_step", "gosurf_refresh_bf16")
 
 _lib = None
 
@@ -114,7 +114,9 @@ def lib():
                                       C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_float, C.POINTER(GradsC),
                                       C.c_void_p, C.c_size_t, C.c_void_p]
         L.gosurf_adam_step.argtypes = [C.POINTER(AdamCfg), C.POINTER(AdamState), C.c_void_p]
-        for f in ("gosurf_sample_rays", "gosurf_forward", "gosurf_backward", "gosurf_adam_step"):
+        L.gosurf_refresh_bf16.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        for f in ("gosurf_sample_rays", "gosurf_forward", "gosurf_backward", "gosurf_adam_step",
+                  "gosurf_refresh_bf16"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -317,6 +319,14 @@ def gosurf_adam_step(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_grad, mlp_m
                   grid.numel(), _ptr(mlp, F32), _ptr(mlp_grad, F32), _ptr(mlp_m, F32), _ptr(mlp_v, F32),
                   mlp.numel())
     _check("gosurf_adam_step", lib().gosurf_adam_step(C.byref(c), C.byref(s), _stream(stream)))
+
+
+def gosurf_refresh_bf16(grid, grid_bf16, stream=None):
+    """grid_bf16 (int16/uint16/bfloat16 storage, same numel) := bfloat16(grid)."""
+    if grid_bf16.numel() != grid.numel() or grid_bf16.element_size() != 2:
+        raise ValueError("grid_bf16 must hold one 2-byte value per grid entry")
+    _check("gosurf_refresh_bf16", lib().gosurf_refresh_bf16(_ptr(grid, F32), _ptr(grid_bf16), grid.numel(),
+                                                            _stream(stream)))
 
 
 def workspace_for(model, M, total, S, device="cuda"):

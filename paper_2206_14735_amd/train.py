@@ -32,6 +32,9 @@ class Reconstruction:
         self.mlp_m = torch.zeros_like(self.mlp)
         self.mlp_v = torch.zeros_like(self.mlp)
         self.grid_bf16 = None
+        if precision == G.BF16:
+            self.grid_bf16 = torch.empty(self.grid.shape, dtype=torch.bfloat16, device=self.device)
+            G.gosurf_refresh_bf16(self.grid, self.grid_bf16)
         self.frames = frames.to(self.device)
         self.cfg = G.SampleCfg(M, n_strat, n_near, span_mode, near, far, trunc, S, delta_s, seed, 0)
         self.loss_cfg = G.make_loss_cfg(lambdas, trunc, alpha_fs)
