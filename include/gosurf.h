@@ -73,6 +73,7 @@ extern "C" {
 #define GOSURF_MLP_NUMEL 2740
 #define GOSURF_MAX_SAMPLES_PER_RAY 256
 #define GOSURF_N_LOSSES 8
+#define GOSURF_PROPOSAL_NUMEL 6851
 
 typedef enum {
   GOSURF_OK = 0,
@@ -131,6 +132,15 @@ typedef struct {
   float delta_s;        /* perturbation length (metres) */
   uint64_t seed;
   uint32_t step;
+  /* Learned proposal (optional).  With proposal != NULL each ray first gets
+     (near, far, confidence) from the proposal network (see
+     gosurf_proposal_forward); rays with confidence >= conf_threshold get
+     n_proposal stratified samples in [near, far], the others fall back to the
+     plain n_strat + n_near samples.  Rays then have different lengths. */
+  const float* proposal;   /* [GOSURF_PROPOSAL_NUMEL] network parameters, or NULL */
+  const float* grid;       /* float32 grid features read by the proposal (its level 1) */
+  int32_t n_proposal;      /* samples per confident ray (>= 1) */
+  float conf_threshold;
 } gosurf_sample_cfg;
 
 /* A ray batch.  Written by gosurf_sample_rays, read by forward/backward.
@@ -151,6 +161,7 @@ typedef struct {
   float* xs;            /* [S][3] smoothness points */
   float* eps;           /* [S][3] perturbations; the pair is (x, x + eps rounded to float32) */
   int64_t* pixel;       /* [M] flat pixel index of each ray (output only; may be NULL) */
+  float* prop;          /* [M][3] proposal near, far, confidence (written with a proposal) */
 } gosurf_ray_batch;
 
 /* Loss configuration (Sec. 3.3-3.5 and implementation details). */
@@ -186,19 +197,22 @@ typedef struct {
   float inv_loss_scale; /* gradients are multiplied by this before use */
 } gosurf_adam_cfg;
 
-/* Parameters, gradients and Adam moments of both groups. */
+/* Parameters, gradients and Adam moments of both groups (a group with 0
+   entries may pass NULL pointers). */
 typedef struct {
   float* grid; float* grid_grad; float* grid_m; float* grid_v;
   uint16_t* grid_bf16;  /* refreshed bfloat16 mirror of grid, or NULL */
   int64_t grid_numel;   /* multiple of 4 */
   float* mlp; float* mlp_grad; float* mlp_m; float* mlp_v;
-  int32_t mlp_numel;    /* multiple of 4 */
+  int32_t mlp_numel;    /* any size (e.g. the decoders' 2740 or the proposal's 6851) */
 } gosurf_adam_state;
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* gosurf_last_error(void);
 
-/* Number of samples one ray batch drawn with `cfg` holds (M * (n_strat + n_near)). */
+/* Sample capacity of a batch drawn with `cfg`: M * (n_strat + n_near), or
+   M * max(n_strat + n_near, n_proposal) with a proposal (the actual count is
+   then seg[M], on the device). */
 int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg);
 
 /* Draw a ray batch (Sec. 3.2, 3.4, 3.5).  `out` arrays must be sized for
@@ -245,6 +259,45 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
                               const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
                               const gosurf_fwd_out* fwd, float loss_scale, gosurf_grads* grads,
                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned proposal sampler.  Not part of the paper: a small network trained
+ * on the per-ray weight distributions that plain sampling produces, which
+ * predicts a narrow depth interval per ray.  Input (38): the 4 features of
+ * grid level 1 at the 8 bin centres t_lo + (b + 1/2)(t_hi - t_lo)/8 of the
+ * ray's span (0 outside the box), then o and r.  Network 38-64-64-3 (ReLU),
+ * parameters packed P1[64][38] q1[64] P2[64][64] q2[64] P3[3][64] q3[3].
+ * near = t_lo + (t_hi - t_lo) sigmoid(o0); far = near + (t_hi - near)
+ * sigmoid(o1); confidence = sigmoid(o2).  The span [t_lo, t_hi] is the plain
+ * sampler's (span_mode, near_t, far_t of `span`).
+ * ------------------------------------------------------------------------- */
+
+/* out3[M][3] = (near, far, confidence) for the rays of `rays` (uses M, o, r). */
+gosurf_status gosurf_proposal_forward(const gosurf_model* model, const float* grid, const float* proposal,
+                                      const gosurf_ray_batch* rays, const gosurf_sample_cfg* span, float* out3,
+                                      void* stream);
+
+/* Training targets from a logged plain batch and its forward weights: per ray
+   p_i = w_i / sum w; the 0.5 % and 99.5 % first crossings of the piecewise-
+   linear CDF through (t_0, p_0), (t_1, p_0 + p_1), ..., widened by `widen`
+   and clipped to the span; confidence target = [sum w >= 0.5].
+   targets[M][3] = (near*, far*, conf*). */
+gosurf_status gosurf_proposal_targets(const gosurf_model* model, const gosurf_ray_batch* rays,
+                                      const gosurf_sample_cfg* span, const float* weights, float widen,
+                                      float* targets, void* stream);
+
+size_t gosurf_proposal_workspace_bytes(int32_t M);
+
+/* Mean over rays of conf* (smoothL1(near - near*) + smoothL1(far - far*)) +
+   BCE(confidence, k) (smooth-L1 transition `beta`), with the confidence label
+   k = conf* [near <= near* + cover_tol] [far >= far* - cover_tol] (the current
+   interval covers the target one; a decision, not differentiated).  *loss is
+   set to it and its gradient is ADDED to grad[GOSURF_PROPOSAL_NUMEL]
+   (fixed-order sums).  The grid is not differentiated. */
+gosurf_status gosurf_proposal_backward(const gosurf_model* model, const float* grid, const float* proposal,
+                                       const gosurf_ray_batch* rays, const gosurf_sample_cfg* span,
+                                       const float* targets, float beta, float cover_tol, float* grad,
+                                       float* loss, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Round the float32 grid to its bfloat16 mirror (round to nearest even), as
    gosurf_adam_step does after every update; call once before the first

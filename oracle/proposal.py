@@ -18,8 +18,13 @@ Eq. volume_rendering).  Its definition, written out step by step:
   the t-quantiles at 0.5 % and 99.5 % of the piecewise-linear CDF through
   (t_0, p_0), (t_1, p_0 + p_1), ..., widened by `widen` on both sides and
   clipped to the span; confidence target = [sum w >= 0.5];
-* loss per ray: conf* (smoothL1_beta(near - near*) + smoothL1_beta(far - far*))
-  + BCE(conf, conf*), averaged over rays.
+* loss per ray: c (smoothL1_beta(near - near*) + smoothL1_beta(far - far*))
+  + BCE(conf, k), averaged over rays, where c = [sum w >= 0.5] is the logged
+  confidence target and the confidence label k = c [near <= near* + tol]
+  [far >= far* - tol] says whether the current interval covers the target
+  interval within `tol`; the label is a decision, not differentiated.  The
+  confidence thereby predicts where the interval can be trusted, and rays
+  below the threshold fall back to plain sampling.
 """
 import numpy as np
 import torch
@@ -132,16 +137,27 @@ def smooth_l1(x, beta):
     return torch.where(ax < beta, 0.5 * x * x / beta, ax - 0.5 * beta)
 
 
-def loss(out, tn, tf, tgt, beta):
+def confidence_label(near, far, tgt, tol):
+    """k = c [near <= near* + tol] [far >= far* - tol], decided in float32."""
+    n32 = near.detach().numpy().astype(np.float32)
+    f32 = far.detach().numpy().astype(np.float32)
+    t32 = np.asarray(tgt, dtype=np.float32)
+    tol32 = np.float32(tol)
+    cov = (n32 <= t32[:, 0] + tol32) & (f32 >= t32[:, 1] - tol32)
+    return torch.from_numpy(((t32[:, 2] > 0.5) & cov).astype(np.float64))
+
+
+def loss(out, tn, tf, tgt, beta, tol):
     near, far, conf = interval(out, tn, tf)
+    k = confidence_label(near, far, tgt, tol)
     tgt = torch.as_tensor(tgt, dtype=torch.float64)
     c = tgt[:, 2]
     reg = c * (smooth_l1(near - tgt[:, 0], beta) + smooth_l1(far - tgt[:, 1], beta))
-    bce = F.binary_cross_entropy_with_logits(out[:, 2], c, reduction="none")
+    bce = F.binary_cross_entropy_with_logits(out[:, 2], k, reduction="none")
     return (reg + bce).mean()
 
 
-def evaluate(grid, layout, prop, o, r, tn, tf, tgt=None, beta=0.05, want_grads=False):
+def evaluate(grid, layout, prop, o, r, tn, tf, tgt=None, beta=0.05, tol=0.05, want_grads=False):
     """Forward (and optionally the loss and its gradient w.r.t. the proposal parameters)."""
     pv = torch.as_tensor(np.asarray(prop), dtype=torch.float64).clone().requires_grad_(want_grads)
     P = unpack(pv)
@@ -151,7 +167,7 @@ def evaluate(grid, layout, prop, o, r, tn, tf, tgt=None, beta=0.05, want_grads=F
         near, far, conf = interval(out, tn, tf)
         res = {"near": near.detach(), "far": far.detach(), "conf": conf.detach(), "inputs": inp.detach()}
         if tgt is not None:
-            L = loss(out, tn, tf, tgt, beta)
+            L = loss(out, tn, tf, tgt, beta, tol)
             res["loss"] = float(L.detach())
             if want_grads:
                 res["grad"], = torch.autograd.grad(L, pv)

@@ -32,6 +32,7 @@ struct FieldArgs {
   float* grad_grid;       // [V][4]
   float* mlp_partial;     // [gridDim.x][kMlpNumel]
   int need_gx;            // ray mode: compute grad phi for the Eikonal term
+  const int* seg_end;     // ray mode: device copy of the sample count (seg[M]); total is then a capacity
   // levels whose gradient is accumulated in LDS per block (bit l) and the
   // float offset of each such level inside the block's LDS area
   int priv_mask;
@@ -68,6 +69,38 @@ struct RenderArgs {
   float* ray_dv;        // [M]
 };
 
+// proposal network over a set of rays
+struct PropArgs {
+  Grid g;
+  const float* grid;
+  const float* prop;     // packed proposal parameters
+  const float* o;
+  const float* r;
+  int M;
+  int span_mode;
+  float near_t, far_t;
+  float* out3;           // [M][3] near, far, confidence (or null)
+  const float* tgt;      // [M][3] training targets
+  float beta;            // smooth-L1 transition
+  float cover_tol;       // confidence label: interval covers the target within this
+  float* grad_partial;   // [gridDim.x][numel + 1] (last entry: loss)
+};
+
+// training targets from logged per-sample weights
+struct TargetArgs {
+  Grid g;
+  const float* t;
+  const float* w;
+  const int* seg;
+  const float* o;
+  const float* r;
+  int M;
+  int span_mode;
+  float near_t, far_t;
+  float widen, q_lo, q_hi, conf_min;
+  float* tgt;            // [M][3]
+};
+
 struct SampleArgs {
   Grid g;
   const uint8_t* rgb;
@@ -90,6 +123,12 @@ struct SampleArgs {
   float* xs;
   float* eps;
   long long* pixel;
+  // proposal-driven sampling: per-ray (near, far, confidence); rays with
+  // confidence >= conf_thr get n_prop samples in [near, far], the others the
+  // plain n_strat + n_near; seg is then filled beforehand by the scan
+  const float* prop3;
+  float conf_thr;
+  int n_prop;
 };
 
 }  // namespace gs

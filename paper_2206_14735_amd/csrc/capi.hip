@@ -26,6 +26,16 @@ hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray
 hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st);
 hipError_t launch_sample(const SampleArgs& a, hipStream_t st);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t st);
+hipError_t launch_sample_rays_only(const SampleArgs& a, hipStream_t st);
+hipError_t launch_sample_gen_only(const SampleArgs& a, hipStream_t st);
+hipError_t launch_proposal(const PropArgs& a, bool train, int blocks, hipStream_t st);
+hipError_t launch_proposal_targets(const TargetArgs& a, hipStream_t st);
+hipError_t launch_proposal_seg(const float* prop3, int M, float thr, int n_prop, int n_plain, int* seg,
+                               hipStream_t st);
+int proposal_blocks(int M);
+int proposal_numel();
+hipError_t launch_colsum(const float* part, int rows, int cols, float* tmp, float* add_dst, int n_add,
+                         float* set_dst, int set_col, hipStream_t st);
 
 }  // namespace gs
 
@@ -167,7 +177,9 @@ const char* gosurf_last_error(void) { return g_err.c_str(); }
 
 int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg) {
   if (!cfg) return -1;
-  return (int64_t)cfg->M * (int64_t)(cfg->n_strat + cfg->n_near);
+  int64_t n = cfg->n_strat + cfg->n_near;
+  if (cfg->proposal && cfg->n_proposal > n) n = cfg->n_proposal;
+  return (int64_t)cfg->M * n;
 }
 
 size_t gosurf_workspace_bytes(const gosurf_model* model, int32_t M, int32_t total, int32_t S) {
@@ -191,8 +203,16 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
   if (c->n_strat + c->n_near > GOSURF_MAX_SAMPLES_PER_RAY)
     return fail(GOSURF_ERR_SHAPE, "n_strat + n_near = %d exceeds %d", c->n_strat + c->n_near,
                 GOSURF_MAX_SAMPLES_PER_RAY);
-  const long long total = (long long)c->M * (c->n_strat + c->n_near);
+  const long long total = gosurf_batch_samples(c);
   if (total * 4 >= (1LL << 31)) return fail(GOSURF_ERR_SHAPE, "too many samples (%lld)", total);
+  if (c->proposal) {
+    if (!c->grid) return fail(GOSURF_ERR_NULL, "the proposal needs the grid");
+    if (!out->prop) return fail(GOSURF_ERR_NULL, "out.prop must hold [M][3] with a proposal");
+    if (c->n_proposal < 1 || c->n_proposal > GOSURF_MAX_SAMPLES_PER_RAY)
+      return fail(GOSURF_ERR_SHAPE, "n_proposal = %d must lie in [1, %d]", c->n_proposal,
+                  GOSURF_MAX_SAMPLES_PER_RAY);
+    if (!std::isfinite(c->conf_threshold)) return fail(GOSURF_ERR_VALUE, "conf_threshold must be finite");
+  }
   if (out->M != c->M || out->total != total || out->S != c->S)
     return fail(GOSURF_ERR_SHAPE, "out sizes (M=%d total=%d S=%d) do not match cfg (M=%d total=%lld S=%d)",
                 out->M, out->total, out->S, c->M, total, c->S);
@@ -215,7 +235,23 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
   a.o = out->o; a.r = out->r; a.rgb_out = out->rgb; a.depth_out = out->depth; a.t = out->t;
   a.seg = out->seg; a.ray_of = out->ray_of; a.xs = out->xs; a.eps = out->eps;
   a.pixel = reinterpret_cast<long long*>(out->pixel);
-  if ((st = hip_check(gs::launch_sample(a, (hipStream_t)stream), "sample_kernel")) != GOSURF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!c->proposal) {
+    if ((st = hip_check(gs::launch_sample(a, s), "sample_kernel")) != GOSURF_OK) return st;
+    return ok();
+  }
+  if ((st = hip_check(gs::launch_sample_rays_only(a, s), "sample rays")) != GOSURF_OK) return st;
+  gs::PropArgs pa{};
+  pa.g = a.g; pa.grid = c->grid; pa.prop = c->proposal; pa.o = out->o; pa.r = out->r; pa.M = c->M;
+  pa.span_mode = c->span_mode; pa.near_t = c->near_t; pa.far_t = c->far_t; pa.out3 = out->prop;
+  if ((st = hip_check(gs::launch_proposal(pa, false, gs::proposal_blocks(c->M), s), "proposal")) != GOSURF_OK)
+    return st;
+  if ((st = hip_check(gs::launch_proposal_seg(out->prop, c->M, c->conf_threshold, c->n_proposal,
+                                              c->n_strat + c->n_near, out->seg, s),
+                      "proposal seg")) != GOSURF_OK)
+    return st;
+  a.prop3 = out->prop; a.conf_thr = c->conf_threshold; a.n_prop = c->n_proposal;
+  if ((st = hip_check(gs::launch_sample_gen_only(a, s), "proposal samples")) != GOSURF_OK) return st;
   return ok();
 }
 
@@ -243,7 +279,7 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   fa.g = g; fa.grid = params->grid; fa.mlp = params->mlp;
   fa.grid_bf16 = model->precision == GOSURF_BF16 ? params->grid_bf16 : nullptr;
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
-  fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S;
+  fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
   if ((st = hip_check(gs::launch_field(fa, 0, false, gs::field_blocks(b->total, 16), s), "field fwd")) != GOSURF_OK)
     return st;
@@ -300,7 +336,7 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   fa.g = g; fa.grid = params->grid; fa.mlp = params->mlp;
   fa.grid_bf16 = model->precision == GOSURF_BF16 ? params->grid_bf16 : nullptr;
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
-  fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S;
+  fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.seed4 = w.seed4; fa.eikw = w.eikw; fa.need_gx = need_gx;
   fa.grad_grid = grads->grid; fa.mlp_partial = w.mlp_partial;
   fa.smooth_coef = b->S > 0 ? 2.f * loss->lambda[5] * loss_scale / (float)b->S : 0.f;
@@ -325,6 +361,88 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   return ok();
 }
 
+static gosurf_status check_rays(const gosurf_ray_batch* r, const gosurf_sample_cfg* span) {
+  if (!r || !span) return fail(GOSURF_ERR_NULL, "rays and span must not be NULL");
+  if (r->M < 1) return fail(GOSURF_ERR_SHAPE, "M = %d < 1", r->M);
+  if (!r->o || !r->r) return fail(GOSURF_ERR_NULL, "rays.o / rays.r are NULL");
+  if (span->span_mode != GOSURF_SPAN_FIXED && span->span_mode != GOSURF_SPAN_BOX)
+    return fail(GOSURF_ERR_VALUE, "unknown span_mode %d", span->span_mode);
+  if (!(span->far_t >= span->near_t)) return fail(GOSURF_ERR_VALUE, "need near <= far");
+  return GOSURF_OK;
+}
+
+gosurf_status gosurf_proposal_forward(const gosurf_model* model, const float* grid, const float* proposal,
+                                      const gosurf_ray_batch* rays, const gosurf_sample_cfg* span, float* out3,
+                                      void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if ((st = check_rays(rays, span)) != GOSURF_OK) return st;
+  if (!grid || !proposal || !out3) return fail(GOSURF_ERR_NULL, "grid, proposal and out3 must not be NULL");
+  if (!aligned(grid, 16)) return fail(GOSURF_ERR_ALIGN, "grid must be 16-byte aligned");
+  gs::PropArgs pa{};
+  pa.g = to_grid(model); pa.grid = grid; pa.prop = proposal; pa.o = rays->o; pa.r = rays->r; pa.M = rays->M;
+  pa.span_mode = span->span_mode; pa.near_t = span->near_t; pa.far_t = span->far_t; pa.out3 = out3;
+  if ((st = hip_check(gs::launch_proposal(pa, false, gs::proposal_blocks(rays->M), (hipStream_t)stream),
+                      "proposal forward")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
+gosurf_status gosurf_proposal_targets(const gosurf_model* model, const gosurf_ray_batch* rays,
+                                      const gosurf_sample_cfg* span, const float* weights, float widen,
+                                      float* targets, void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if ((st = check_rays(rays, span)) != GOSURF_OK) return st;
+  if (!rays->t || !rays->seg || !weights || !targets)
+    return fail(GOSURF_ERR_NULL, "rays.t, rays.seg, weights and targets must not be NULL");
+  if (!(widen >= 0.f) || !std::isfinite(widen)) return fail(GOSURF_ERR_VALUE, "widen must be >= 0");
+  gs::TargetArgs ta{};
+  ta.g = to_grid(model); ta.t = rays->t; ta.w = weights; ta.seg = rays->seg; ta.o = rays->o; ta.r = rays->r;
+  ta.M = rays->M; ta.span_mode = span->span_mode; ta.near_t = span->near_t; ta.far_t = span->far_t;
+  ta.widen = widen; ta.q_lo = 0.005f; ta.q_hi = 0.995f; ta.conf_min = 0.5f; ta.tgt = targets;
+  if ((st = hip_check(gs::launch_proposal_targets(ta, (hipStream_t)stream), "proposal targets")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
+size_t gosurf_proposal_workspace_bytes(int32_t M) {
+  if (M < 1) return 0;
+  const size_t cols = (size_t)gs::proposal_numel() + 1;
+  return up(sizeof(float) * (size_t)gs::proposal_blocks(M) * cols) + up(sizeof(float) * 64 * cols);
+}
+
+gosurf_status gosurf_proposal_backward(const gosurf_model* model, const float* grid, const float* proposal,
+                                       const gosurf_ray_batch* rays, const gosurf_sample_cfg* span,
+                                       const float* targets, float beta, float cover_tol, float* grad,
+                                       float* loss, void* ws, size_t ws_bytes, void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if ((st = check_rays(rays, span)) != GOSURF_OK) return st;
+  if (!grid || !proposal || !targets || !grad || !loss)
+    return fail(GOSURF_ERR_NULL, "grid, proposal, targets, grad and loss must not be NULL");
+  if (!aligned(grid, 16)) return fail(GOSURF_ERR_ALIGN, "grid must be 16-byte aligned");
+  if (!(beta > 0.f) || !std::isfinite(beta)) return fail(GOSURF_ERR_VALUE, "beta must be > 0");
+  if (!(cover_tol >= 0.f) || !std::isfinite(cover_tol)) return fail(GOSURF_ERR_VALUE, "cover_tol must be >= 0");
+  const size_t need = gosurf_proposal_workspace_bytes(rays->M);
+  if (!ws || ws_bytes < need)
+    return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+  const int blocks = gs::proposal_blocks(rays->M);
+  const int cols = gs::proposal_numel() + 1;
+  float* part = static_cast<float*>(ws);
+  float* tmp = reinterpret_cast<float*>(static_cast<char*>(ws) + up(sizeof(float) * (size_t)blocks * cols));
+  gs::PropArgs pa{};
+  pa.g = to_grid(model); pa.grid = grid; pa.prop = proposal; pa.o = rays->o; pa.r = rays->r; pa.M = rays->M;
+  pa.span_mode = span->span_mode; pa.near_t = span->near_t; pa.far_t = span->far_t; pa.out3 = nullptr;
+  pa.tgt = targets; pa.beta = beta; pa.cover_tol = cover_tol; pa.grad_partial = part;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = hip_check(gs::launch_proposal(pa, true, blocks, s), "proposal backward")) != GOSURF_OK) return st;
+  if ((st = hip_check(gs::launch_colsum(part, blocks, cols, tmp, grad, cols - 1, loss, cols - 1, s),
+                      "proposal reduce")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
 gosurf_status gosurf_refresh_bf16(const float* grid, uint16_t* grid_bf16, int64_t numel, void* stream) {
   if (!grid || !grid_bf16) return fail(GOSURF_ERR_NULL, "grid and grid_bf16 must not be NULL");
   if (numel < 0 || numel % 4) return fail(GOSURF_ERR_SHAPE, "numel must be a non-negative multiple of 4");
@@ -338,10 +456,12 @@ gosurf_status gosurf_refresh_bf16(const float* grid, uint16_t* grid_bf16, int64_
 
 gosurf_status gosurf_adam_step(const gosurf_adam_cfg* c, gosurf_adam_state* s, void* stream) {
   if (!c || !s) return fail(GOSURF_ERR_NULL, "cfg and state must not be NULL");
-  if (!s->grid || !s->grid_grad || !s->grid_m || !s->grid_v || !s->mlp || !s->mlp_grad || !s->mlp_m || !s->mlp_v)
-    return fail(GOSURF_ERR_NULL, "an Adam array is NULL");
-  if (s->grid_numel < 0 || s->grid_numel % 4 || s->mlp_numel < 0 || s->mlp_numel % 4)
-    return fail(GOSURF_ERR_SHAPE, "group sizes must be non-negative multiples of 4");
+  if (s->grid_numel > 0 && (!s->grid || !s->grid_grad || !s->grid_m || !s->grid_v))
+    return fail(GOSURF_ERR_NULL, "a grid-group Adam array is NULL");
+  if (s->mlp_numel > 0 && (!s->mlp || !s->mlp_grad || !s->mlp_m || !s->mlp_v))
+    return fail(GOSURF_ERR_NULL, "a decoder-group Adam array is NULL");
+  if (s->grid_numel < 0 || s->grid_numel % 4 || s->mlp_numel < 0)
+    return fail(GOSURF_ERR_SHAPE, "grid group: non-negative multiple of 4; decoder group: non-negative");
   const void* ptrs[] = {s->grid, s->grid_grad, s->grid_m, s->grid_v, s->mlp, s->mlp_grad, s->mlp_m, s->mlp_v};
   for (const void* p : ptrs)
     if (!aligned(p, 16)) return fail(GOSURF_ERR_ALIGN, "Adam arrays must be 16-byte aligned");

@@ -59,6 +59,27 @@ __device__ __forceinline__ bool inside_box(const Grid& g, float x, float y, floa
          z <= g.p1[2];
 }
 
+// The plain sampler's span of a ray: fixed [near, far], or its passage
+// through the grid box clipped to [near, far] (slab test; 0/0 -> NaN is
+// ignored by fminf/fmaxf).
+__device__ __forceinline__ void ray_span(const Grid& g, const float o[3], const float r[3], int mode, float near_t,
+                                         float far_t, float& tn, float& tf) {
+  tn = near_t;
+  tf = far_t;
+  if (mode == GOSURF_SPAN_BOX) {
+    float tmin = -INFINITY, tmax = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float ta = (g.p0[a] - o[a]) / r[a];
+      const float tb = (g.p1[a] - o[a]) / r[a];
+      tmin = fmaxf(tmin, fminf(ta, tb));
+      tmax = fminf(tmax, fmaxf(ta, tb));
+    }
+    tn = fmaxf(tmin, near_t);
+    tf = fmaxf(fminf(tmax, far_t), tn);
+  }
+}
+
 // ---------------------------------------------------------------- numerics
 __device__ __forceinline__ float log_sigmoid(float x) {
   // log(1 / (1 + e^-x)) = -softplus(-x), evaluated without overflow

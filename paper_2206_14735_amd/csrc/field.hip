@@ -13,6 +13,8 @@
 //   Weight gradients (sums over samples) are MFMAs with the sample axis as K;
 //   their operands are transposed through a small per-wave LDS scratch.
 #include "args.h"
+#include "gather.h"
+#include "mfma.h"
 
 namespace gs {
 
@@ -62,18 +64,6 @@ __device__ float table_value(const float* __restrict__ P, int slot, int l) {
   }
 }
 
-__device__ __forceinline__ v4s pack_bf16(v4f x) {
-  return v4s{(short)f2bf(x[0]), (short)f2bf(x[1]), (short)f2bf(x[2]), (short)f2bf(x[3])};
-}
-__device__ __forceinline__ v4s pack_bf16(float4 x) {
-  return v4s{(short)f2bf(x.x), (short)f2bf(x.y), (short)f2bf(x.z), (short)f2bf(x.w)};
-}
-__device__ __forceinline__ v4s as_v4s(uint2 u) {
-  v4s r;
-  __builtin_memcpy(&r, &u, sizeof(r));
-  return r;
-}
-
 // out[bo] = sum over input blocks/steps of A(slot) * in   (NBO output blocks of 16 rows).
 // FP32: 4 steps of 16x16x4 per input block; BF16: one 16x16x16 per input block
 // whose A operand packs the four fp32 steps' values of the same lane.
@@ -90,131 +80,7 @@ __device__ __forceinline__ void layer(const Smem& sm, int base, const v4f* in, v
         out[bo] = mfma16_bf16(as_v4s(sm.tabbf[(base / 4 + bo * NBI + bi) * 64 + lane]), b, out[bo]);
     }
   } else {
-#pragma unroll
-    for (int bi = 0; bi < NBI; ++bi)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int bo = 0; bo < NBO; ++bo)
-          out[bo] = mfma4(sm.tab[(base + bo * 4 * NBI + bi * 4 + r) * 64 + lane], in[bi][r], out[bo]);
-  }
-}
-
-// LDS scratch of one operand: [row][sample], 16 samples + 4 floats of padding
-// per row (rows of the four lane groups land in different banks).
-constexpr int RSR = 20;
-
-template <int NB>
-__device__ __forceinline__ void store_rows(float* scr, const v4f* X, int q, int j) {
-#pragma unroll
-  for (int b = 0; b < NB; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) scr[(16 * b + 4 * q + r) * RSR + j] = X[b][r];
-}
-
-// acc[ba][bb] += sum over the tile's 16 samples of A[16ba + i][s] * B[16bb + n][s].
-// The sample axis is the MFMA K axis; lane group q supplies samples 4q..4q+3
-// (one 16-byte LDS read per operand block).
-template <bool BF, int NA, int NB>
-__device__ __forceinline__ void outer_acc(float* scrA, float* scrB, const v4f* A, const v4f* B, v4f* acc,
-                                          int q, int j) {
-  store_rows<NA>(scrA, A, q, j);
-  store_rows<NB>(scrB, B, q, j);
-  wave_lds_fence();
-  float4 av[NA], bv[NB];
-#pragma unroll
-  for (int a = 0; a < NA; ++a) av[a] = *reinterpret_cast<const float4*>(scrA + (16 * a + j) * RSR + 4 * q);
-#pragma unroll
-  for (int b = 0; b < NB; ++b) bv[b] = *reinterpret_cast<const float4*>(scrB + (16 * b + j) * RSR + 4 * q);
-  if constexpr (BF) {
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[a * NB + b] = mfma16_bf16(pack_bf16(av[a]), pack_bf16(bv[b]), acc[a * NB + b]);
-  } else {
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        acc[a * NB + b] = mfma4(av[a].x, bv[b].x, acc[a * NB + b]);
-        acc[a * NB + b] = mfma4(av[a].y, bv[b].y, acc[a * NB + b]);
-        acc[a * NB + b] = mfma4(av[a].z, bv[b].z, acc[a * NB + b]);
-        acc[a * NB + b] = mfma4(av[a].w, bv[b].w, acc[a * NB + b]);
-      }
-  }
-  wave_lds_fence();
-}
-
-// per-lane gather state of one level
-struct LevelSample {
-  float f[3];
-  long long row;   // corner 000
-  int sy, sz;      // row strides of +y, +z corners
-  float inv_v;
-};
-
-__device__ __forceinline__ void locate(const Grid& g, int q, float x, float y, float z, LevelSample& ls) {
-  const float xyz[3] = {x, y, z};
-  const int n[3] = {g.nx[q], g.ny[q], g.nz[q]};
-  const float v = g.voxel[q];
-  int i0[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float u = (xyz[a] - g.p0[a]) / v;
-    int c = (int)floorf(u);
-    c = c < 0 ? 0 : (c > n[a] - 2 ? n[a] - 2 : c);
-    i0[a] = c;
-    ls.f[a] = u - (float)c;
-  }
-  ls.sy = n[0];
-  ls.sz = n[0] * n[1];
-  ls.row = g.off[q] + ((long long)i0[2] * n[1] + i0[1]) * n[0] + i0[0];
-  ls.inv_v = 1.f / v;
-}
-
-// trilinear value (z) and, optionally, dz/dx (G[k][axis]) of one level
-template <bool NEED_G, bool BF>
-__device__ __forceinline__ void interp(const float* __restrict__ grid, const uint16_t* __restrict__ grid_bf,
-                                       const LevelSample& ls, bool valid, float z[4], float G[4][3]) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) { z[k] = 0.f; G[k][0] = G[k][1] = G[k][2] = 0.f; }
-  if (!valid) return;
-  const float fx = ls.f[0], fy = ls.f[1], fz = ls.f[2];
-  float4 th[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
-    const long long row = ls.row + bx + (long long)by * ls.sy + (long long)bz * ls.sz;
-    if constexpr (BF) {
-      const uint2 u = *reinterpret_cast<const uint2*>(grid_bf + row * 4);
-      th[c] = make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
-                          __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
-    } else {
-      th[c] = *reinterpret_cast<const float4*>(grid + row * 4);
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
-    const float wx = bx ? fx : 1.f - fx, wy = by ? fy : 1.f - fy, wz = bz ? fz : 1.f - fz;
-    const float w = wx * wy * wz;
-    const float tv[4] = {th[c].x, th[c].y, th[c].z, th[c].w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) z[k] += w * tv[k];
-    if (NEED_G) {
-      const float jx = (bx ? 1.f : -1.f) * wy * wz, jy = (by ? 1.f : -1.f) * wx * wz,
-                  jz = (bz ? 1.f : -1.f) * wx * wy;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        G[k][0] += jx * tv[k];
-        G[k][1] += jy * tv[k];
-        G[k][2] += jz * tv[k];
-      }
-    }
-  }
-  if (NEED_G) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { G[k][0] *= ls.inv_v; G[k][1] *= ls.inv_v; G[k][2] *= ls.inv_v; }
+    layer_f32<NBO, NBI>(sm.tab, base, in, out, lane);
   }
 }
 
@@ -394,7 +260,8 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
   __syncthreads();
 
   const bool need_g = (MODE == 1) || A.need_gx;
-  const int n_items = MODE == 0 ? A.total : 2 * A.S;   // lanes of work
+  const int total = (MODE == 0 && A.seg_end) ? *A.seg_end : A.total;
+  const int n_items = MODE == 0 ? total : 2 * A.S;   // lanes of work
   const int per_tile = MODE == 0 ? 16 : 16;
   const int n_tiles = (n_items + per_tile - 1) / per_tile;
 
@@ -416,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
     bool live;
     if (MODE == 0) {
       item = tile * 16 + j;
-      live = item < A.total;
+      live = item < total;
       px = py = pz = 0.f;
       if (live) {
         const int ray = A.ray_of[item];

@@ -1,0 +1,81 @@
+// Trilinear gather of one grid level for one lane (Sec. 3.1; coefficient
+// vector and Jacobian of the supplementary "Second-order Grid Sampler").
+#pragma once
+#include "device.h"
+
+namespace gs {
+
+// per-lane gather state of one level
+struct LevelSample {
+  float f[3];
+  long long row;   // corner 000
+  int sy, sz;      // row strides of +y, +z corners
+  float inv_v;
+};
+
+__device__ __forceinline__ void locate(const Grid& g, int q, float x, float y, float z, LevelSample& ls) {
+  const float xyz[3] = {x, y, z};
+  const int n[3] = {g.nx[q], g.ny[q], g.nz[q]};
+  const float v = g.voxel[q];
+  int i0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float u = (xyz[a] - g.p0[a]) / v;
+    int c = (int)floorf(u);
+    c = c < 0 ? 0 : (c > n[a] - 2 ? n[a] - 2 : c);
+    i0[a] = c;
+    ls.f[a] = u - (float)c;
+  }
+  ls.sy = n[0];
+  ls.sz = n[0] * n[1];
+  ls.row = g.off[q] + ((long long)i0[2] * n[1] + i0[1]) * n[0] + i0[0];
+  ls.inv_v = 1.f / v;
+}
+
+// trilinear value (z) and, optionally, dz/dx (G[k][axis]) of one level
+template <bool NEED_G, bool BF>
+__device__ __forceinline__ void interp(const float* __restrict__ grid, const uint16_t* __restrict__ grid_bf,
+                                       const LevelSample& ls, bool valid, float z[4], float G[4][3]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) { z[k] = 0.f; G[k][0] = G[k][1] = G[k][2] = 0.f; }
+  if (!valid) return;
+  const float fx = ls.f[0], fy = ls.f[1], fz = ls.f[2];
+  float4 th[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+    const long long row = ls.row + bx + (long long)by * ls.sy + (long long)bz * ls.sz;
+    if constexpr (BF) {
+      const uint2 u = *reinterpret_cast<const uint2*>(grid_bf + row * 4);
+      th[c] = make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                          __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+    } else {
+      th[c] = *reinterpret_cast<const float4*>(grid + row * 4);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = (c >> 2) & 1, by = (c >> 1) & 1, bz = c & 1;
+    const float wx = bx ? fx : 1.f - fx, wy = by ? fy : 1.f - fy, wz = bz ? fz : 1.f - fz;
+    const float w = wx * wy * wz;
+    const float tv[4] = {th[c].x, th[c].y, th[c].z, th[c].w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z[k] += w * tv[k];
+    if (NEED_G) {
+      const float jx = (bx ? 1.f : -1.f) * wy * wz, jy = (by ? 1.f : -1.f) * wx * wz,
+                  jz = (bz ? 1.f : -1.f) * wx * wy;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        G[k][0] += jx * tv[k];
+        G[k][1] += jy * tv[k];
+        G[k][2] += jz * tv[k];
+      }
+    }
+  }
+  if (NEED_G) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { G[k][0] *= ls.inv_v; G[k][1] *= ls.inv_v; G[k][2] *= ls.inv_v; }
+  }
+}
+
+}  // namespace gs

@@ -373,6 +373,26 @@ hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray
 
 int colsum_rows() { return kR1; }
 
+// dst[e] += column sum e for e < n_add; set_dst = column sum `set_col`
+__global__ __launch_bounds__(256) void colsum_stage2_kernel(const float* __restrict__ tmp, int cols,
+                                                            float* __restrict__ add_dst, int n_add,
+                                                            float* __restrict__ set_dst, int set_col) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= cols) return;
+  const float v = colsum_stage2(tmp, cols, e);
+  if (e < n_add) add_dst[e] += v;
+  if (e == set_col && set_dst) *set_dst = v;
+}
+
+hipError_t launch_colsum(const float* part, int rows, int cols, float* tmp, float* add_dst, int n_add,
+                         float* set_dst, int set_col, hipStream_t st) {
+  hipError_t e = launch_colsum_stage1(part, rows, cols, tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_stage2_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, tmp, cols, add_dst, n_add,
+                     set_dst, set_col);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- Adam
 __global__ __launch_bounds__(256) void adam_kernel(float4* __restrict__ gp, float4* __restrict__ gg,
                                                    float4* __restrict__ gm, float4* __restrict__ gv,
@@ -447,9 +467,23 @@ hipError_t launch_to_bf16(const float* src, uint16_t* dst, long long n, hipStrea
   return hipGetLastError();
 }
 
+// the last numel % 4 entries of a group (scalar)
+__global__ void adam_tail_kernel(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
+                                 float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float inv_bc1,
+                                 float inv_sqrt_bc2, float inv_scale) {
+  const int i = threadIdx.x;
+  if (i >= n) return;
+  const float gg = g[i] * inv_scale;
+  m[i] = b1 * m[i] + (1.f - b1) * gg;
+  v[i] = b2 * v[i] + (1.f - b2) * gg * gg;
+  p[i] -= lr * (m[i] * inv_bc1) / (sqrtf(v[i]) * inv_sqrt_bc2 + eps);
+  g[i] = 0.f;
+}
+
 hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st) {
   const long long n4g = s.grid_numel / 4;
   const int n4m = s.mlp_numel / 4;
+  const int tail = s.mlp_numel - 4 * n4m;
   const double bc1 = 1.0 - pow((double)c.beta1, (double)c.step);
   const double bc2 = 1.0 - pow((double)c.beta2, (double)c.step);
   long long blocks = (n4g + n4m + 255) / 256;
@@ -462,6 +496,12 @@ hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream
                      reinterpret_cast<float4*>(s.mlp_m), reinterpret_cast<float4*>(s.mlp_v), n4m, c.lr_grid,
                      c.lr_mlp, c.beta1, c.beta2, c.eps, (float)(1.0 / bc1), (float)(1.0 / sqrt(bc2)),
                      c.inv_loss_scale);
+  if (tail > 0) {
+    const size_t o = 4 * (size_t)n4m;
+    hipLaunchKernelGGL(adam_tail_kernel, dim3(1), dim3(64), 0, st, s.mlp + o, s.mlp_grad + o, s.mlp_m + o,
+                       s.mlp_v + o, tail, c.lr_mlp, c.beta1, c.beta2, c.eps, (float)(1.0 / bc1),
+                       (float)(1.0 / sqrt(bc2)), c.inv_loss_scale);
+  }
   return hipGetLastError();
 }
 

@@ -55,44 +55,49 @@ struct UniformStream {
 // in the merged order is its index in its own list plus the number of values
 // of the other list that precede it (stratified first on ties), counted with
 // the same float32 values on every lane, so the ranks form a permutation.
+// RAY: pick the pixel and write the ray; GEN: write the ray's samples (with a
+// proposal, confident rays get n_prop stratified samples in [near, far] and
+// their first sample comes from the precomputed seg).
+template <bool RAY, bool GEN>
 __global__ __launch_bounds__(256) void sample_rays_kernel(SampleArgs A) {
   const int lane = threadIdx.x & 63;
   const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (m >= A.M) return;
-  const unsigned long long thw = (unsigned long long)A.T * A.H * A.W;
-  const U4 w0 = philox((uint32_t)m, A.step, 0u, 0u, A.k0, A.k1);
-  const unsigned long long pix = pick_pixel(w0.x, thw);
-  const PixelRay pr = pixel_ray(A, pix);
-  const float D = A.depth[pix];
-  if (lane < 3) {
-    A.o[3 * m + lane] = pr.o[lane];
-    A.r[3 * m + lane] = pr.r[lane];
-    A.rgb_out[3 * m + lane] = (float)A.rgb[3 * pix + lane] / 255.f;
-  }
-  if (lane == 0) {
-    A.depth_out[m] = D;
-    if (A.pixel) A.pixel[m] = (long long)pix;
-  }
-  float tn = A.near_t, tf = A.far_t;
-  if (A.span_mode == GOSURF_SPAN_BOX) {
-    float tmin = -INFINITY, tmax = INFINITY;
+  float o[3], r[3], D;
+  if (RAY) {
+    const unsigned long long thw = (unsigned long long)A.T * A.H * A.W;
+    const U4 w0 = philox((uint32_t)m, A.step, 0u, 0u, A.k0, A.k1);
+    const unsigned long long pix = pick_pixel(w0.x, thw);
+    const PixelRay pr = pixel_ray(A, pix);
+    D = A.depth[pix];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float ta = (A.g.p0[a] - pr.o[a]) / pr.r[a];
-      const float tb = (A.g.p1[a] - pr.o[a]) / pr.r[a];
-      tmin = fmaxf(tmin, fminf(ta, tb));   // NaN (0/0) is ignored by fmin/fmax
-      tmax = fminf(tmax, fmaxf(ta, tb));
+    for (int a = 0; a < 3; ++a) { o[a] = pr.o[a]; r[a] = pr.r[a]; }
+    if (lane < 3) {
+      A.o[3 * m + lane] = pr.o[lane];
+      A.r[3 * m + lane] = pr.r[lane];
+      A.rgb_out[3 * m + lane] = (float)A.rgb[3 * pix + lane] / 255.f;
     }
-    tn = fmaxf(tmin, A.near_t);
-    tf = fmaxf(fminf(tmax, A.far_t), tn);
+    if (lane == 0) {
+      A.depth_out[m] = D;
+      if (A.pixel) A.pixel[m] = (long long)pix;
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { o[a] = A.o[3 * m + a]; r[a] = A.r[3 * m + a]; }
+    D = A.depth_out[m];
   }
+  if (!GEN) return;
+  float tn, tf;
+  ray_span(A.g, o, r, A.span_mode, A.near_t, A.far_t, tn, tf);
   const int n_tot = A.n_strat + A.n_near;
-  const bool two = D > 0.f && A.n_near > 0;
-  const int ns = two ? A.n_strat : n_tot;   // stratified count over the span
-  const int nn = two ? A.n_near : 0;        // near-depth count
+  const bool proposed = A.prop3 != nullptr && A.prop3[3 * m + 2] >= A.conf_thr;
+  const bool two = !proposed && D > 0.f && A.n_near > 0;
+  const int ns = proposed ? A.n_prop : (two ? A.n_strat : n_tot);   // stratified count
+  const int nn = two ? A.n_near : 0;                                // near-depth count
+  if (proposed) { tn = A.prop3[3 * m]; tf = A.prop3[3 * m + 1]; }
   const float ds = (tf - tn) / (float)ns;
   const float lo = D - A.trunc, dn = (2.f * A.trunc) / (float)(nn > 0 ? nn : 1);
-  const size_t base = (size_t)m * n_tot;
+  const size_t base = A.prop3 != nullptr ? (size_t)A.seg[m] : (size_t)m * n_tot;
   float av[kChunks], bv[kChunks];
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
@@ -132,9 +137,9 @@ __global__ __launch_bounds__(256) void sample_rays_kernel(SampleArgs A) {
     const int i = 64 * c + lane;
     if (i < ns) A.t[base + ra[c]] = av[c];
     if (i < nn) A.t[base + rb[c]] = bv[c];
-    if (i < n_tot) A.ray_of[base + i] = m;
+    if (i < ns + nn) A.ray_of[base + i] = m;
   }
-  if (lane == 0) {
+  if (lane == 0 && A.prop3 == nullptr) {
     A.seg[m] = (int)base;
     if (m == A.M - 1) A.seg[A.M] = (int)((size_t)A.M * n_tot);
   }
@@ -177,8 +182,20 @@ __global__ __launch_bounds__(256) void sample_points_kernel(SampleArgs A) {
 }
 
 hipError_t launch_sample(const SampleArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(sample_rays_kernel, dim3((a.M + 3) / 4), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((sample_rays_kernel<true, true>), dim3((a.M + 3) / 4), dim3(256), 0, st, a);
   if (a.S > 0) hipLaunchKernelGGL(sample_points_kernel, dim3((a.S + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// proposal mode: rays first, then (after inference and the seg scan) samples
+hipError_t launch_sample_rays_only(const SampleArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((sample_rays_kernel<true, false>), dim3((a.M + 3) / 4), dim3(256), 0, st, a);
+  if (a.S > 0) hipLaunchKernelGGL(sample_points_kernel, dim3((a.S + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_gen_only(const SampleArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((sample_rays_kernel<false, true>), dim3((a.M + 3) / 4), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgosurf.so")
 
 LEVELS = 4
 MLP_NUMEL = 2740
+PROPOSAL_NUMEL = 6851
 N_LOSSES = 8
 MAX_SAMPLES_PER_RAY = 256
 FP32, BF16 = 0, 1
@@ -53,14 +54,16 @@ class FramesC(C.Structure):
 class SampleCfg(C.Structure):
     _fields_ = [("M", C.c_int32), ("n_strat", C.c_int32), ("n_near", C.c_int32), ("span_mode", C.c_int32),
                 ("near_t", C.c_float), ("far_t", C.c_float), ("trunc", C.c_float), ("S", C.c_int32),
-                ("delta_s", C.c_float), ("seed", C.c_uint64), ("step", C.c_uint32)]
+                ("delta_s", C.c_float), ("seed", C.c_uint64), ("step", C.c_uint32),
+                ("proposal", C.c_void_p), ("grid", C.c_void_p), ("n_proposal", C.c_int32),
+                ("conf_threshold", C.c_float)]
 
 
 class RayBatchC(C.Structure):
     _fields_ = [("M", C.c_int32), ("total", C.c_int32), ("S", C.c_int32),
                 ("o", C.c_void_p), ("r", C.c_void_p), ("rgb", C.c_void_p), ("depth", C.c_void_p),
                 ("t", C.c_void_p), ("seg", C.c_void_p), ("ray_of", C.c_void_p),
-                ("xs", C.c_void_p), ("eps", C.c_void_p), ("pixel", C.c_void_p)]
+                ("xs", C.c_void_p), ("eps", C.c_void_p), ("pixel", C.c_void_p), ("prop", C.c_void_p)]
 
 
 class LossCfg(C.Structure):
@@ -89,7 +92,9 @@ class AdamState(C.Structure):
 
 
 EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "gosurf_workspace_bytes",
-           "gosurf_forward", "gosurf_backward", "gosurf_adam_step", "gosurf_refresh_bf16")
+           "gosurf_forward", "gosurf_backward", "gosurf_adam_step", "gosurf_refresh_bf16",
+           "gosurf_proposal_forward", "gosurf_proposal_targets", "gosurf_proposal_workspace_bytes",
+           "gosurf_proposal_backward")
 
 _lib = None
 
@@ -115,8 +120,18 @@ def lib():
                                       C.c_void_p, C.c_size_t, C.c_void_p]
         L.gosurf_adam_step.argtypes = [C.POINTER(AdamCfg), C.POINTER(AdamState), C.c_void_p]
         L.gosurf_refresh_bf16.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.gosurf_proposal_forward.argtypes = [C.POINTER(Model), C.c_void_p, C.c_void_p, C.POINTER(RayBatchC),
+                                              C.POINTER(SampleCfg), C.c_void_p, C.c_void_p]
+        L.gosurf_proposal_targets.argtypes = [C.POINTER(Model), C.POINTER(RayBatchC), C.POINTER(SampleCfg),
+                                              C.c_void_p, C.c_float, C.c_void_p, C.c_void_p]
+        L.gosurf_proposal_workspace_bytes.restype = C.c_size_t
+        L.gosurf_proposal_workspace_bytes.argtypes = [C.c_int32]
+        L.gosurf_proposal_backward.argtypes = [C.POINTER(Model), C.c_void_p, C.c_void_p, C.POINTER(RayBatchC),
+                                               C.POINTER(SampleCfg), C.c_void_p, C.c_float, C.c_float,
+                                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         for f in ("gosurf_sample_rays", "gosurf_forward", "gosurf_backward", "gosurf_adam_step",
-                  "gosurf_refresh_bf16"):
+                  "gosurf_refresh_bf16", "gosurf_proposal_forward", "gosurf_proposal_targets",
+                  "gosurf_proposal_backward"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -129,7 +144,7 @@ def _check(fn, status):
 
 def _ptr(t, dtype=None):
     if t is None:
-        return None
+        return C.c_void_p(None)
     if not t.is_contiguous():
         raise ValueError("tensors passed to libgosurf must be contiguous")
     if dtype is not None and t.dtype != dtype:
@@ -188,6 +203,7 @@ class RayBatch:
     xs: torch.Tensor
     eps: torch.Tensor
     pixel: torch.Tensor | None = None
+    prop: torch.Tensor | None = None
 
     @property
     def M(self):
@@ -205,19 +221,24 @@ class RayBatch:
         b = RayBatchC()
         b.M, b.total, b.S = self.M, self.total, self.S
         types = dict(seg=torch.int32, ray_of=torch.int32, pixel=torch.int64)
-        for f in ("o", "r", "rgb", "depth", "t", "seg", "ray_of", "xs", "eps", "pixel"):
+        for f in ("o", "r", "rgb", "depth", "t", "seg", "ray_of", "xs", "eps", "pixel", "prop"):
             setattr(b, f, _ptr(getattr(self, f), types.get(f, F32)))
         return b
 
     @staticmethod
-    def empty(M, total, S, device="cuda"):
+    def empty(M, total, S, device="cuda", proposal=False):
         f = dict(device=device, dtype=torch.float32)
         return RayBatch(torch.empty(M, 3, **f), torch.empty(M, 3, **f), torch.empty(M, 3, **f),
                         torch.empty(M, **f), torch.empty(total, **f),
                         torch.empty(M + 1, device=device, dtype=torch.int32),
                         torch.empty(total, device=device, dtype=torch.int32),
                         torch.empty(S, 3, **f), torch.empty(S, 3, **f),
-                        torch.empty(M, device=device, dtype=torch.int64))
+                        torch.empty(M, device=device, dtype=torch.int64),
+                        torch.empty(M, 3, **f) if proposal else None)
+
+    def n_samples(self):
+        """Actual number of samples (seg[M]; a device read)."""
+        return int(self.seg[-1].item())
 
     @staticmethod
     def from_host(b, device="cuda"):
@@ -281,7 +302,7 @@ def gosurf_sample_rays(model, frames, cfg, out=None, stream=None):
     total = gosurf_batch_samples(cfg)
     dev = frames.depth.device
     if out is None:
-        out = RayBatch.empty(cfg.M, total, cfg.S, dev)
+        out = RayBatch.empty(cfg.M, total, cfg.S, dev, proposal=bool(cfg.proposal))
     fc = frames_c(frames)
     bc = out.c()
     _check("gosurf_sample_rays", lib().gosurf_sample_rays(C.byref(model), C.byref(fc), C.byref(cfg),
@@ -315,10 +336,55 @@ def gosurf_adam_step(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_grad, mlp_m
                      lr_mlp=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, inv_loss_scale=1.0, grid_bf16=None,
                      stream=None):
     c = AdamCfg(lr_grid, lr_mlp, beta1, beta2, eps, int(step), inv_loss_scale)
+    ng = 0 if grid is None else grid.numel()
     s = AdamState(_ptr(grid, F32), _ptr(grid_grad, F32), _ptr(grid_m, F32), _ptr(grid_v, F32), _ptr(grid_bf16),
-                  grid.numel(), _ptr(mlp, F32), _ptr(mlp_grad, F32), _ptr(mlp_m, F32), _ptr(mlp_v, F32),
-                  mlp.numel())
+                  ng, _ptr(mlp, F32), _ptr(mlp_grad, F32), _ptr(mlp_m, F32), _ptr(mlp_v, F32), mlp.numel())
     _check("gosurf_adam_step", lib().gosurf_adam_step(C.byref(c), C.byref(s), _stream(stream)))
+
+
+def set_proposal(cfg, proposal, grid, n_proposal=24, conf_threshold=0.5):
+    """Enable (or, with proposal=None, disable) proposal-driven sampling in cfg.
+    The tensors must stay alive while cfg is used."""
+    cfg.proposal = None if proposal is None else _ptr(proposal, F32).value
+    cfg.grid = None if proposal is None else _ptr(grid, F32).value
+    cfg.n_proposal = n_proposal
+    cfg.conf_threshold = conf_threshold
+    return cfg
+
+
+def gosurf_proposal_forward(model, grid, proposal, rays, span_cfg, out3=None, stream=None):
+    if out3 is None:
+        out3 = torch.empty(rays.M, 3, device=grid.device, dtype=torch.float32)
+    rc = rays.c()
+    _check("gosurf_proposal_forward", lib().gosurf_proposal_forward(C.byref(model), _ptr(grid, F32),
+                                                                    _ptr(proposal, F32), C.byref(rc),
+                                                                    C.byref(span_cfg), _ptr(out3, F32),
+                                                                    _stream(stream)))
+    return out3
+
+
+def gosurf_proposal_targets(model, rays, span_cfg, weights, widen, out=None, stream=None):
+    if out is None:
+        out = torch.empty(rays.M, 3, device=weights.device, dtype=torch.float32)
+    rc = rays.c()
+    _check("gosurf_proposal_targets", lib().gosurf_proposal_targets(C.byref(model), C.byref(rc),
+                                                                    C.byref(span_cfg), _ptr(weights, F32),
+                                                                    float(widen), _ptr(out, F32),
+                                                                    _stream(stream)))
+    return out
+
+
+def gosurf_proposal_workspace_bytes(M):
+    return int(lib().gosurf_proposal_workspace_bytes(M))
+
+
+def gosurf_proposal_backward(model, grid, proposal, rays, span_cfg, targets, beta, cover_tol, grad, loss,
+                             workspace, stream=None):
+    rc = rays.c()
+    _check("gosurf_proposal_backward", lib().gosurf_proposal_backward(
+        C.byref(model), _ptr(grid, F32), _ptr(proposal, F32), C.byref(rc), C.byref(span_cfg),
+        _ptr(targets, F32), float(beta), float(cover_tol), _ptr(grad, F32), _ptr(loss, F32), _ptr(workspace),
+        workspace.numel(), _stream(stream)))
 
 
 def gosurf_refresh_bf16(grid, grid_bf16, stream=None):

@@ -77,6 +77,16 @@ class Reconstruction:
         self.adam()
         self.it += 1
 
+    def use_proposal(self, proposal, n_proposal=24, conf_threshold=0.5):
+        """Sample with the learned proposal from now on (None: plain sampling)."""
+        self.proposal = proposal
+        G.set_proposal(self.cfg, proposal, self.grid, n_proposal, conf_threshold)
+        self.total = G.gosurf_batch_samples(self.cfg)
+        M, S = self.cfg.M, self.cfg.S
+        self.batch = G.RayBatch.empty(M, self.total, S, self.device, proposal=proposal is not None)
+        self.fwd = G.FwdOut.empty(M, self.total, self.device)
+        self.ws = G.workspace_for(self.model, M, self.total, S, self.device)
+
     def losses(self):
         v = self.fwd.losses.tolist()
         return dict(zip(G.LOSS_NAMES, v))

@@ -15,7 +15,7 @@ from paper_2206_14735_amd import gosurf as G  # noqa: E402
 
 def _declared():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(gosurf_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(gosurf_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -142,5 +142,5 @@ def test_adam_rejects_bad_step_and_sizes(lib):
     s = G.AdamState(16, 16, 16, 16, None, 8, 16, 16, 16, 16, 4)
     assert lib.gosurf_adam_step(C.byref(c), C.byref(s), None) == 4
     c.step = 1
-    s.grid_numel = 6
+    s.grid_numel = 6                       # grid group must be a multiple of 4
     assert lib.gosurf_adam_step(C.byref(c), C.byref(s), None) == 2

@@ -167,8 +167,9 @@ def test_adam_matches_oracle():
     n = 4 * 1003
     p, gr = torch.randn(n, generator=g), torch.randn(n, generator=g) * 1e-2
     m, v = torch.randn(n, generator=g) * 1e-3, torch.rand(n, generator=g) * 1e-4
-    pm, grm = torch.randn(2740, generator=g), torch.randn(2740, generator=g)
-    mm, vm = torch.zeros(2740), torch.zeros(2740)
+    # second group of ragged size (the proposal's 6851 entries): vector body + scalar tail
+    pm, grm = torch.randn(6851, generator=g), torch.randn(6851, generator=g)
+    mm, vm = torch.zeros(6851), torch.zeros(6851)
     dev = [x.clone().cuda() for x in (p, gr, m, v, pm, grm, mm, vm)]
     bf = torch.empty(n, dtype=torch.int16, device="cuda")
     G.gosurf_adam_step(5, dev[0], dev[1], dev[2], dev[3], dev[4], dev[5], dev[6], dev[7], lr_grid=1e-2,
@@ -188,7 +189,8 @@ def test_adam_matches_oracle():
     assert np.all(np.abs(dev[2].cpu().double().numpy() - rm.numpy()) <= 1e-6 * scale_m.numpy() + 1e-30)
     np.testing.assert_allclose(dev[3].cpu().numpy(), rv.numpy(), rtol=1e-6, atol=1e-14)
     assert torch.count_nonzero(dev[1]) == 0 and torch.count_nonzero(dev[5]) == 0
-    rpm = ostep.adam(pm.double(), grm.double(), mm.double(), vm.double(), 5, f(1e-3), **hp)[0]
+    assert torch.count_nonzero(dev[4].cpu() - pm) == 6851   # every entry moved, tail included
+    rpm = ostep.adam(pm.double(), grm.double(), mm.double(), vm.double(), 5, f(1e-3), inv_scale=0.5, **hp)[0]
     errm = np.abs(dev[4].cpu().double().numpy() - rpm.numpy())
     ulpm = np.spacing(np.abs(rpm.numpy()).astype(np.float32)).astype(np.float64)
     assert np.all(errm <= 1e-5 * np.abs((rpm - pm.double()).numpy()) + ulpm)

@@ -1,0 +1,171 @@
+"""Learned proposal on the device: inference, training gradient and targets
+against the FP64 oracle; proposal-driven sampling; and what the trained
+network gains over plain sampling at the same sample count."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import proposal as OP, sampler as osampler, step as ostep
+from oracle.philox import philox4x32_10, uniform01
+from tests.helpers import FWD_TOL, GRAD_TOL, check_close, f32_layout
+
+pytestmark = pytest.mark.gpu
+
+
+def _G():
+    from paper_2206_14735_amd import gosurf as G
+    G.lib()
+    return G
+
+
+def _room(M=333, seed=4):
+    L = f32_layout(synth.configs.ROOM.layout())
+    fr, _ = synth.room_frames(4, H=96, W=128, f=105.0, seed=seed)
+    b, _, _ = osampler.sample_batch(fr, L, M, 16, 8, "aabb", 0.1, 1e9, 0.1, 0, 0.004, seed=seed, step=0)
+    g = torch.Generator().manual_seed(seed)
+    grid = (torch.randn(L.n_vertices, 4, generator=g) * 0.3).float()
+    prop = synth.init_proposal(seed)
+    return L, fr, b, grid, prop
+
+
+def _span_cfg(G):
+    return G.SampleCfg(1, 1, 0, G.SPAN_BOX, 0.1, 1e9, 0.1, 0, 0.004, 0, 0)
+
+
+def test_proposal_forward_matches_oracle():
+    G = _G()
+    L, fr, b, grid, prop = _room()
+    from paper_2206_14735_amd.proposal import rays_view
+    o, r = torch.from_numpy(b.o).cuda(), torch.from_numpy(b.r).cuda()
+    out = G.gosurf_proposal_forward(G.make_model(L), grid.cuda(), prop.cuda(), rays_view(o, r), _span_cfg(G))
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    tn, tf = OP.ray_span(b.o, b.r, L, "aabb", 0.1, 1e9)
+    ref = OP.evaluate(grid.double().numpy(), L, prop.double().numpy(), b.o, b.r, tn, tf)
+    check_close("near", out[:, 0], ref["near"].numpy(), FWD_TOL)
+    check_close("far", out[:, 1], ref["far"].numpy(), FWD_TOL)
+    check_close("conf", out[:, 2], ref["conf"].numpy(), FWD_TOL)
+
+
+def test_proposal_backward_matches_oracle():
+    G = _G()
+    L, fr, b, grid, prop = _room(M=1000, seed=6)
+    from paper_2206_14735_amd.proposal import rays_view
+    tn, tf = OP.ray_span(b.o, b.r, L, "aabb", 0.1, 1e9)
+    rng = np.random.default_rng(2)
+    a = rng.uniform(0.1, 0.6, len(tn))
+    tgt = np.column_stack([tn + a * (tf - tn), tn + (a + 0.2) * (tf - tn), rng.uniform(size=len(tn)) > 0.3])
+    tgt = tgt.astype(np.float32)
+    o, r = torch.from_numpy(b.o).cuda(), torch.from_numpy(b.r).cuda()
+    grad = torch.zeros(G.PROPOSAL_NUMEL, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    ws = torch.empty(G.gosurf_proposal_workspace_bytes(len(tn)), dtype=torch.uint8, device="cuda")
+    G.gosurf_proposal_backward(G.make_model(L), grid.cuda(), prop.cuda(), rays_view(o, r), _span_cfg(G),
+                               torch.from_numpy(tgt).cuda(), 0.05, 0.3, grad, loss, ws)
+    torch.cuda.synchronize()
+    ref = OP.evaluate(grid.double().numpy(), L, prop.double().numpy(), b.o, b.r, tn, tf,
+                      tgt.astype(np.float64), beta=0.05, tol=0.3, want_grads=True)
+    assert abs(float(loss) - ref["loss"]) <= FWD_TOL * abs(ref["loss"])
+    check_close("proposal grad", grad.cpu().numpy(), ref["grad"].numpy(), GRAD_TOL, max_bad_frac=0.002)
+
+
+def test_proposal_targets_match_oracle():
+    G = _G()
+    from tests.helpers import sphere_case
+    L, fr, b, grid, mlp = sphere_case(M=300, S=0, grid_std=0.3)
+    res = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, want_grads=False)
+    w = res["w"].numpy().astype(np.float32)
+    tn, tf = OP.ray_span(b.o, b.r, L, "fixed", 0.1, 3.0)
+    ref = OP.targets(b.t, w.astype(np.float64), b.seg, tn, tf, widen=0.0125)
+    db = G.RayBatch.from_host(b)
+    span = G.SampleCfg(1, 1, 0, G.SPAN_FIXED, 0.1, 3.0, 0.1, 0, 0.004, 0, 0)
+    got = G.gosurf_proposal_targets(G.make_model(L), db, span, torch.from_numpy(w).cuda(), 0.0125)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert np.array_equal(got[:, 2], ref[:, 2])
+    # quantiles: float32 prefix sums move a crossing by a fraction of one interval at most
+    dt = 2.9 / 64
+    assert np.max(np.abs(got[:, :2] - ref[:, :2])) < 1e-3 * dt + 1e-6
+
+
+def test_proposal_driven_sampling():
+    G = _G()
+    L, fr, b, grid, prop = _room(M=8, seed=7)
+    M = 500
+    model = G.make_model(L)
+    cfg = G.SampleCfg(M, 16, 8, G.SPAN_BOX, 0.1, 1e9, 0.1, 0, 0.004, 99, 3)
+    gd, pd = grid.cuda(), prop.cuda()
+    G.set_proposal(cfg, pd, gd, n_proposal=12, conf_threshold=0.5)
+    batch = G.gosurf_sample_rays(model, fr.to("cuda"), cfg)
+    torch.cuda.synchronize()
+    p3 = batch.prop.cpu().numpy()
+    seg = batch.seg.cpu().numpy()
+    t = batch.t.cpu().numpy()
+    conf_ok = p3[:, 2] >= 0.5
+    assert 0 < conf_ok.sum() < M      # both branches exercised by the random network
+    lens = np.where(conf_ok, 12, 24)
+    assert np.array_equal(np.diff(seg), lens) and seg[0] == 0
+    # plain rays: identical to the plain sampler's rays; proposal rays: stratified in [near, far]
+    plain, _, _ = osampler.sample_batch(fr, L, M, 16, 8, "aabb", 0.1, 1e9, 0.1, 0, 0.004, seed=99, step=3)
+    for m in range(M):
+        tt = t[seg[m]:seg[m + 1]]
+        if conf_ok[m]:
+            w = philox4x32_10(np.stack([np.full(3, m), np.full(3, 3), np.full(3, 1), np.arange(3)], -1),
+                              np.array([99, 0]))
+            u = uniform01(w.reshape(-1))[:12]
+            ref = p3[m, 0] + (np.arange(12) + u) * (p3[m, 1] - p3[m, 0]) / 12
+            assert np.allclose(tt, ref, rtol=4e-6, atol=1e-6)
+        else:
+            assert np.allclose(tt, plain.t[24 * m:24 * (m + 1)], rtol=4e-6, atol=1e-6)
+    assert np.array_equal(batch.ray_of.cpu().numpy()[:seg[-1]], np.repeat(np.arange(M), lens))
+
+
+def test_trained_proposal_beats_plain_sampling_at_equal_samples():
+    """Sphere workload: plain training, logged weight distributions, proposal
+    training, then the rendered depth error with 24 samples per ray from the
+    proposal against 24 plain stratified samples (and plain 64 as reference)."""
+    G = _G()
+    from paper_2206_14735_amd.proposal import ProposalLog, ProposalTrainer
+    from paper_2206_14735_amd.train import Reconstruction
+    w = synth.configs.SPHERE
+    fr = synth.sphere_frames().to("cuda")
+    rec = Reconstruction.from_workload(w, fr, seed=0)
+    for _ in range(400):
+        rec.step()
+    log = ProposalLog()
+    for _ in range(48):                          # ~50k logged rays
+        rec.sample()
+        log.add(rec, widen=2 * 2.9 / 64)
+        rec.it += 1
+    trainer = ProposalTrainer(rec.model, rec.cfg, synth.init_proposal(1), lr=2e-3, batch=8192)
+    final_loss = trainer.fit(rec.grid, log, steps=600)
+
+    def depth_l1(n_plain, proposal):
+        ev = Reconstruction.from_workload(w, fr, seed=0, grid=rec.grid.clone(), mlp=rec.mlp.clone())
+        ev.cfg.n_strat, ev.cfg.n_near, ev.cfg.S = n_plain, 0, 0
+        ev.cfg.seed = 12345
+        if proposal is not None:
+            ev.use_proposal(proposal, n_proposal=24, conf_threshold=0.5)
+        else:
+            ev.use_proposal(None)
+        errs, fallback = [], []
+        for k in range(8):
+            ev.it = 10_000 + k
+            ev.sample()
+            ev.forward()
+            torch.cuda.synchronize()
+            d = ev.batch.depth
+            ok = d > 0
+            errs.append((ev.fwd.depth_hat[ok] - d[ok]).abs().mean().item())
+            if proposal is not None:
+                fallback.append((ev.batch.prop[:, 2] < 0.5).float().mean().item())
+        return float(np.mean(errs)), (float(np.mean(fallback)) if fallback else 0.0)
+
+    e24, _ = depth_l1(24, None)
+    e64, _ = depth_l1(64, None)
+    ep, fb = depth_l1(64, trainer.prop)          # fallback rays use the plain 64
+    print(f"depth L1: plain24 {e24:.4f} plain64 {e64:.4f} proposal24 {ep:.4f} fallback {fb:.3f} "
+          f"proposal loss {final_loss:.4f}")
+    assert ep < 0.5 * e24
+    assert ep < 1.5 * e64 + 2e-3

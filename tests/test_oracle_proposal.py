@@ -66,10 +66,19 @@ def test_loss_shapes():
     sl = OP.smooth_l1(x, 0.05)
     assert torch.allclose(sl[:2], 0.5 * x[:2] ** 2 / 0.05)
     assert torch.allclose(sl[2:], x[2:].abs() - 0.025)
-    # with conf* = 0 only the BCE term remains: -log(1 - sigmoid(o2))
+    # with conf* = 0 only the BCE term remains, with label 0: -log(1 - sigmoid(o2))
     out = torch.tensor([[0.0, 0.0, 1.3]], dtype=torch.float64)
-    L = OP.loss(out, np.array([1.0]), np.array([3.0]), np.array([[0.0, 0.0, 0.0]]), 0.05)
+    L = OP.loss(out, np.array([1.0]), np.array([3.0]), np.array([[0.0, 0.0, 0.0]]), 0.05, 0.05)
     assert abs(float(L) - math.log(1 + math.exp(1.3))) < 1e-14
+    # the interval (2, 2.5) covers a target (2.02, 2.48) -> label 1: BCE = -log(sigmoid(o2));
+    # it does not cover (1.9, 2.6) within tol 0.05 -> label 0, plus the regression terms
+    tn, tf = np.array([1.0]), np.array([3.0])
+    L1 = OP.loss(out, tn, tf, np.array([[2.02, 2.48, 1.0]]), 0.05, 0.05)
+    reg = 0.5 * 0.02 ** 2 / 0.05 * 2
+    assert abs(float(L1) - (reg + math.log(1 + math.exp(-1.3)))) < 1e-12
+    L0 = OP.loss(out, tn, tf, np.array([[1.9, 2.6, 1.0]]), 0.05, 0.05)
+    reg0 = (0.1 - 0.025) * 2
+    assert abs(float(L0) - (reg0 + math.log(1 + math.exp(1.3)))) < 1e-12
 
 
 def _vertex_positions(L, l):
@@ -108,14 +117,15 @@ def test_proposal_gradient_matches_central_differences():
     r = np.column_stack([rng.uniform(-1, 1, M), rng.uniform(-1, 1, M), np.ones(M)])
     tn, tf = OP.ray_span(o, r, L, "aabb", 0.1, 1e9)
     tgt = np.column_stack([tn + 0.3 * (tf - tn), tn + 0.6 * (tf - tn), (np.arange(M) % 3 > 0).astype(float)])
-    res = OP.evaluate(grid, L, prop, o, r, tn, tf, tgt, want_grads=True)
+    res = OP.evaluate(grid, L, prop, o, r, tn, tf, tgt, tol=0.3, want_grads=True)
     h = 1e-6
     bad = 0
     for i in rng.choice(len(prop), 20, replace=False):
         pp, pm = prop.copy(), prop.copy()
         pp[i] += h
         pm[i] -= h
-        fd = (OP.evaluate(grid, L, pp, o, r, tn, tf, tgt)["loss"] - OP.evaluate(grid, L, pm, o, r, tn, tf, tgt)["loss"]) / (2 * h)
+        fd = (OP.evaluate(grid, L, pp, o, r, tn, tf, tgt, tol=0.3)["loss"]
+              - OP.evaluate(grid, L, pm, o, r, tn, tf, tgt, tol=0.3)["loss"]) / (2 * h)
         gi = float(res["grad"][i])
         bad += not (abs(fd - gi) <= 1e-5 * max(abs(gi), 1e-4))
     assert bad <= 1
