@@ -34,7 +34,41 @@ def parse():
     ap.add_argument("--frames", type=int, default=None, help="override the number of frames")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=512)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for memory counters)")
     return ap.parse_args()
+
+
+# Algorithmic bytes per unit of work of the timed kernels (FP32):
+#   backward field kernel, per sample: 4 levels x 8 corners x 16 B gathered
+#   (512 B) + 128 float atomic read-modify-writes of 4 B (512 B) + backward
+#   seeds (20 B) + depth and ray index (8 B) = 1052 B;
+#   forward field kernel, per sample: 512 B gathered + 8 B in + 20 B out;
+#   Adam, per parameter: p, g, m, v read and written (32 B).
+BYTES_PER_SAMPLE = {"field_bwd": 1052.0, "field_fwd": 540.0}
+BYTES_PER_PARAM_ADAM = 32.0
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_2206_14735_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    entry = data.get(kernel)
+    if not entry or entry.get("source_digest") != source_digest():
+        return None
+    return entry.get("bytes_per_launch")
 
 
 def cpu_baseline(w, frames_cpu, grid, mlp, n_rays):
@@ -128,14 +162,49 @@ def main():
            for i, n in enumerate(names)}
     print(f"# per call (ms): {per}", file=sys.stderr, flush=True)
 
-    # roofline of the dense Adam kernel (one kernel per call): 32 B per parameter
+    # per-kernel durations: HIP events recorded by the library around each launch
+    kern = {}
+    for name, kid in (("field_fwd", G.KERNEL_FIELD_FWD), ("field_bwd", G.KERNEL_FIELD_BWD),
+                      ("smooth_bwd", G.KERNEL_SMOOTH_BWD), ("adam", G.KERNEL_ADAM)):
+        pairs = []
+        for _ in range(a.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)   # creates the events; the library re-records them around the kernel
+            e1.record(st)
+            G.gosurf_time_kernel(kid, e0, e1)
+            rec.step()
+            pairs.append((e0, e1))
+        G.gosurf_time_kernel(0)
+        torch.cuda.synchronize()
+        kern[name] = sum(x.elapsed_time(y) for x, y in pairs) / len(pairs)
+    print(f"# per kernel (ms): {kern}", file=sys.stderr, flush=True)
+
     n_par = rec.grid.numel() + rec.mlp.numel()
-    adam_bytes = 32.0 * n_par
-    adam_gbs = adam_bytes / (per["adam_step"] * 1e-3) / 1e9
-    dominant = max(per, key=per.get)
-    roof = {"kernel": "adam_kernel (gosurf_adam_step)", "bound": "hbm", "achieved": round(adam_gbs, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(adam_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None, "algorithmic_bytes": adam_bytes}
+    samples_now = rec.batch.n_samples()
+
+    def roofline(name, bytes_per_launch, ms, label):
+        gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+        traffic = measured_traffic(name)
+        return {"kernel": label, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": bytes_per_launch, "ms_per_launch": round(ms, 4)}
+
+    roofs = {
+        "field_bwd": roofline("field_bwd", BYTES_PER_SAMPLE["field_bwd"] * samples_now, kern["field_bwd"],
+                              "field_kernel<rays, backward> (gosurf_backward)"),
+        "field_fwd": roofline("field_fwd", BYTES_PER_SAMPLE["field_fwd"] * samples_now, kern["field_fwd"],
+                              "field_kernel<rays, forward> (gosurf_forward)"),
+        "adam": roofline("adam", BYTES_PER_PARAM_ADAM * n_par, kern["adam"], "adam_kernel (gosurf_adam_step)"),
+    }
+    dominant = max(("field_fwd", "field_bwd", "adam"), key=lambda k: kern[k])
+    roof = roofs[dominant]
+
+    if a.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)   # elementwise kernel: 1 GiB read, 1 GiB written
+        torch.cuda.synchronize()
+        print("# calibration copy: 1 GiB read + 1 GiB written", file=sys.stderr, flush=True)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -158,8 +227,10 @@ def main():
                    "rays": w.M, "samples_per_ray": w.n_samples, "smoothness_pairs": w.S,
                    "grid_params": rec.grid.numel(), "frames": n_frames},
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
-        "dominant_call": dominant,
+        "per_kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "roofline": roof,
+        "other_rooflines": {k: v for k, v in roofs.items() if k != dominant},
+        "source_digest": source_digest(),
         "cpu_baseline": cpu,
         "losses": rec.losses(),
     }

@@ -207,6 +207,21 @@ typedef struct {
   int32_t mlp_numel;    /* any size (e.g. the decoders' 2740 or the proposal's 6851) */
 } gosurf_adam_state;
 
+/* Kernels that can be timed individually (see gosurf_time_kernel). */
+typedef enum {
+  GOSURF_KERNEL_NONE = 0,
+  GOSURF_KERNEL_FIELD_FWD = 1,     /* per-sample forward field kernel of gosurf_forward */
+  GOSURF_KERNEL_FIELD_BWD = 2,     /* per-sample backward field kernel of gosurf_backward */
+  GOSURF_KERNEL_SMOOTH_BWD = 3,    /* smoothness-pair backward kernel of gosurf_backward */
+  GOSURF_KERNEL_ADAM = 4           /* the dense Adam kernel of gosurf_adam_step */
+} gosurf_kernel_id;
+
+/* Measurement hook (this thread only): while set, every launch of `kernel` is
+   bracketed by hipEventRecord(start) and hipEventRecord(stop) on the launch
+   stream; start/stop are caller-created hipEvent_t handles.  kernel =
+   GOSURF_KERNEL_NONE (or NULL events) clears it.  Errors: VALUE. */
+gosurf_status gosurf_time_kernel(int32_t kernel, void* start_event, void* stop_event);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* gosurf_last_error(void);
 

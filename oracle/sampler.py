@@ -63,7 +63,7 @@ def pixel_rays(frames, pix):
     r = np.einsum("nij,nj->ni", c2w[:, :3, :3], dcam)
     o = c2w[:, :3, 3]
     rgb = np.asarray(frames.rgb)[f, v, u].astype(np.float64) / 255.0
-    depth = np.asarray(frames.depth, dtype=np.float64)[f, v, u]
+    depth = np.asarray(frames.depth)[f, v, u].astype(np.float64)
     return o, r, rgb, depth
 
 
@@ -120,24 +120,23 @@ def sample_batch(frames, layout, M, n_strat, n_near, span_mode, near, far, trunc
         pts = np.arange(S)
         words = _draw(pts[:, None], step, STREAM_SMOOTH, np.arange(SMOOTH_ATTEMPTS)[None, :], seed)
         cand = ((words[..., 0].astype(np.uint64) * np.uint64(thw)) >> np.uint64(32)).astype(np.int64)
-        dflat = np.asarray(frames.depth, dtype=np.float64).reshape(-1)
+        dflat = np.asarray(frames.depth).reshape(-1)
         okc = dflat[cand] > 0
         first = np.where(okc.any(1), okc.argmax(1), -1)
         centre = (np.asarray(layout.p0) + np.asarray(layout.p1)) / 2
-        for p in range(S):
-            a = first[p]
-            if a < 0:
-                xs[p] = centre
-                continue
-            spix[p] = cand[p, a]
-            po, pr, _, pd = pixel_rays(frames, cand[p, a:a + 1])
-            u1, u2, u3 = uniform01(words[p, a, 1:4])
-            d = pd[0] + (2 * u1 - 1) * trunc
-            xs[p] = po[0] + d * pr[0]
-            zc = 1 - 2 * u2
-            ph = 2 * np.pi * u3
-            rr = np.sqrt(max(0.0, 1 - zc * zc))
-            eps[p] = delta_s * np.array([rr * np.cos(ph), rr * np.sin(ph), zc])
+        found = first >= 0
+        xs[~found] = centre
+        idx = np.nonzero(found)[0]
+        a = first[idx]
+        spix[idx] = cand[idx, a]
+        po, pr, _, pd = pixel_rays(frames, spix[idx])
+        u = uniform01(words[idx, a, 1:4])
+        d = pd + (2 * u[:, 0] - 1) * trunc
+        xs[idx] = po + d[:, None] * pr
+        zc = 1 - 2 * u[:, 1]
+        ph = 2 * np.pi * u[:, 2]
+        rr = np.sqrt(np.maximum(0.0, 1 - zc * zc))
+        eps[idx] = delta_s * np.stack([rr * np.cos(ph), rr * np.sin(ph), zc], -1)
     f32 = lambda a: np.asarray(a, dtype=np.float32)  # noqa: E731
     batch = Batch(f32(o), f32(r), f32(rgb), f32(depth), f32(t), seg.astype(np.int32), f32(xs), f32(eps))
     return batch, pix, spix

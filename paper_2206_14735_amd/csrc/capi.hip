@@ -43,6 +43,15 @@ namespace {
 
 thread_local std::string g_err;
 
+// optional event pair recorded around one kernel (measurement hook)
+thread_local int g_timed_kernel = GOSURF_KERNEL_NONE;
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+void mark(int kernel, bool start, hipStream_t s) {
+  if (kernel != g_timed_kernel || !g_ev_start || !g_ev_stop) return;
+  hipEventRecord(start ? g_ev_start : g_ev_stop, s);
+}
+
 gosurf_status fail(gosurf_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 gosurf_status fail(gosurf_status s, const char* fmt, ...) {
   char buf[512];
@@ -175,6 +184,14 @@ extern "C" {
 
 const char* gosurf_last_error(void) { return g_err.c_str(); }
 
+gosurf_status gosurf_time_kernel(int32_t kernel, void* start_event, void* stop_event) {
+  if (kernel < GOSURF_KERNEL_NONE || kernel > GOSURF_KERNEL_ADAM) return fail(GOSURF_ERR_VALUE, "unknown kernel %d", kernel);
+  g_timed_kernel = (start_event && stop_event) ? kernel : GOSURF_KERNEL_NONE;
+  g_ev_start = static_cast<hipEvent_t>(start_event);
+  g_ev_stop = static_cast<hipEvent_t>(stop_event);
+  return ok();
+}
+
 int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg) {
   if (!cfg) return -1;
   int64_t n = cfg->n_strat + cfg->n_near;
@@ -281,8 +298,10 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
+  mark(GOSURF_KERNEL_FIELD_FWD, true, s);
   if ((st = hip_check(gs::launch_field(fa, 0, false, gs::field_blocks(b->total, 16), s), "field fwd")) != GOSURF_OK)
     return st;
+  mark(GOSURF_KERNEL_FIELD_FWD, false, s);
   int n_sp = 0;
   if (b->S > 0 && loss->lambda[5] != 0.f) {
     n_sp = gs::field_blocks(2 * b->S, 16);
@@ -344,13 +363,17 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   gs::plan_privatised_levels(fa, counts);
   fa.priv_partial = w.priv_partial;
   const int nbr = gs::field_blocks(b->total, 16);
+  mark(GOSURF_KERNEL_FIELD_BWD, true, s);
   if ((st = hip_check(gs::launch_field(fa, 0, true, nbr, s), "field bwd")) != GOSURF_OK) return st;
+  mark(GOSURF_KERNEL_FIELD_BWD, false, s);
   int nbs = 0;
   if (b->S > 0 && loss->lambda[5] != 0.f) {
     nbs = gs::field_blocks(2 * b->S, 16);
     fa.mlp_partial = w.mlp_partial + (size_t)nbr * gs::kMlpNumel;
     fa.priv_partial = w.priv_partial + (size_t)nbr * fa.priv_floats;
+    mark(GOSURF_KERNEL_SMOOTH_BWD, true, s);
     if ((st = hip_check(gs::launch_field(fa, 1, true, nbs, s), "smoothness bwd")) != GOSURF_OK) return st;
+    mark(GOSURF_KERNEL_SMOOTH_BWD, false, s);
   }
   fa.priv_partial = w.priv_partial;
   if ((st = hip_check(gs::launch_priv_reduce(fa, nbr + nbs, counts, w.colsum_tmp, s), "level reduce")) != GOSURF_OK)
@@ -474,7 +497,9 @@ gosurf_status gosurf_adam_step(const gosurf_adam_cfg* c, gosurf_adam_state* s, v
     return fail(GOSURF_ERR_VALUE, "eps must be > 0 and rates finite");
   gosurf_status st;
   gosurf_adam_state copy = *s;
+  mark(GOSURF_KERNEL_ADAM, true, (hipStream_t)stream);
   if ((st = hip_check(gs::launch_adam(*c, copy, (hipStream_t)stream), "adam")) != GOSURF_OK) return st;
+  mark(GOSURF_KERNEL_ADAM, false, (hipStream_t)stream);
   return ok();
 }
 

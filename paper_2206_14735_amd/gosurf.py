@@ -94,7 +94,7 @@ class AdamState(C.Structure):
 EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "gosurf_workspace_bytes",
            "gosurf_forward", "gosurf_backward", "gosurf_adam_step", "gosurf_refresh_bf16",
            "gosurf_proposal_forward", "gosurf_proposal_targets", "gosurf_proposal_workspace_bytes",
-           "gosurf_proposal_backward")
+           "gosurf_proposal_backward", "gosurf_time_kernel")
 
 _lib = None
 
@@ -129,9 +129,10 @@ def lib():
         L.gosurf_proposal_backward.argtypes = [C.POINTER(Model), C.c_void_p, C.c_void_p, C.POINTER(RayBatchC),
                                                C.POINTER(SampleCfg), C.c_void_p, C.c_float, C.c_float,
                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.gosurf_time_kernel.argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
         for f in ("gosurf_sample_rays", "gosurf_forward", "gosurf_backward", "gosurf_adam_step",
                   "gosurf_refresh_bf16", "gosurf_proposal_forward", "gosurf_proposal_targets",
-                  "gosurf_proposal_backward"):
+                  "gosurf_proposal_backward", "gosurf_time_kernel"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -393,6 +394,16 @@ def gosurf_refresh_bf16(grid, grid_bf16, stream=None):
         raise ValueError("grid_bf16 must hold one 2-byte value per grid entry")
     _check("gosurf_refresh_bf16", lib().gosurf_refresh_bf16(_ptr(grid, F32), _ptr(grid_bf16), grid.numel(),
                                                             _stream(stream)))
+
+
+KERNEL_FIELD_FWD, KERNEL_FIELD_BWD, KERNEL_SMOOTH_BWD, KERNEL_ADAM = 1, 2, 3, 4
+
+
+def gosurf_time_kernel(kernel, start=None, stop=None):
+    """Record torch.cuda.Event start/stop around every launch of `kernel` (None: stop)."""
+    sp = None if start is None else start.cuda_event
+    ep = None if stop is None else stop.cuda_event
+    _check("gosurf_time_kernel", lib().gosurf_time_kernel(int(kernel) if start is not None else 0, sp, ep))
 
 
 def workspace_for(model, M, total, S, device="cuda"):
