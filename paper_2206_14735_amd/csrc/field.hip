@@ -198,18 +198,12 @@ __device__ __forceinline__ v4f relu_mask(v4f x, v4f h) {
              h[3] > 0.f ? x[3] : 0.f};
 }
 
-__device__ __forceinline__ float sum16(float v) {   // over the 16 lanes of one level group
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  v += __shfl_xor(v, 8, 64);
-  return v;
-}
-
-// LDS footprint of one block
+// LDS footprint of one block.  The fp32 kernels keep one float per lane per
+// MFMA step, the bf16 kernels four packed bf16 values per lane per input block.
+template <bool BF>
 struct FieldSmem {
-  float tab[T_END * 64];                // fp32 A operands, one float per lane per step
-  uint2 tabbf[(T_END / 4) * 64];        // bf16 A operands, four values per lane per block
+  float tab[BF ? 1 : T_END * 64];
+  uint2 tabbf[BF ? (T_END / 4) * 64 : 1];
   float bias[32 + 32 + 16 + 32 + 16];   // b1, b2, b3, c1, c2(pad 16)
   float w3row0[32];
   float scr[kWavesPerBlock][2048];       // operand transposes, then scatter staging
@@ -217,19 +211,35 @@ struct FieldSmem {
   int rows[kWavesPerBlock][64];
 };
 constexpr int kRedFloats = kWavesPerBlock * kMlpNumel;
-constexpr int kSmemBytes = (sizeof(FieldSmem) > kRedFloats * 4) ? sizeof(FieldSmem) : kRedFloats * 4;
+template <bool BF>
+constexpr int smem_bytes() {
+  return (sizeof(FieldSmem<BF>) > kRedFloats * 4) ? (int)sizeof(FieldSmem<BF>) : kRedFloats * 4;
+}
 constexpr int kPrivMaxFloats = 4096;   // LDS budget for privatised levels (1024 vertices)
 
 // MODE 0: ray samples; MODE 1: smoothness pairs (16-lane tile = 8 pairs: lanes
 // j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).
 template <int MODE, bool BWD, bool BF>
-__global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
+// At least two waves per SIMD: the backward kernels then fit 256 registers
+// without spilling, and a second wave hides the gather and atomic latency.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void field_kernel(FieldArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  FieldSmem& sm = *reinterpret_cast<FieldSmem*>(smem_raw);
+  FieldSmem<BF>& sm = *reinterpret_cast<FieldSmem<BF>*>(smem_raw);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
 
-  for (int e = tid; e < T_END * 64; e += kBlock) sm.tab[e] = table_value(A.mlp, e >> 6, e & 63);
+  if constexpr (BF) {
+    for (int e = tid; e < (T_END / 4) * 64; e += kBlock) {
+      const int slot = e >> 6, l = e & 63;
+      const uint32_t lo = (uint32_t)f2bf(table_value(A.mlp, 4 * slot + 0, l)) |
+                          ((uint32_t)f2bf(table_value(A.mlp, 4 * slot + 1, l)) << 16);
+      const uint32_t hi = (uint32_t)f2bf(table_value(A.mlp, 4 * slot + 2, l)) |
+                          ((uint32_t)f2bf(table_value(A.mlp, 4 * slot + 3, l)) << 16);
+      sm.tabbf[e] = make_uint2(lo, hi);
+    }
+  } else {
+    for (int e = tid; e < T_END * 64; e += kBlock) sm.tab[e] = table_value(A.mlp, e >> 6, e & 63);
+  }
   if (tid < 32) {
     sm.bias[tid] = A.mlp[oB1 + tid];
     sm.bias[32 + tid] = A.mlp[oB2 + tid];
@@ -240,21 +250,10 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
     sm.bias[64 + tid] = A.mlp[oB3 + tid];
     sm.bias[112 + tid] = tid < 3 ? A.mlp[oC2 + tid] : 0.f;
   }
-  __syncthreads();
-  if constexpr (BF) {
-    for (int e = tid; e < (T_END / 4) * 64; e += kBlock) {
-      const int slot = e >> 6, l = e & 63;
-      const float* t4 = sm.tab + (4 * slot) * 64 + l;
-      const uint32_t lo = (uint32_t)f2bf(t4[0]) | ((uint32_t)f2bf(t4[64]) << 16);
-      const uint32_t hi = (uint32_t)f2bf(t4[128]) | ((uint32_t)f2bf(t4[192]) << 16);
-      sm.tabbf[e] = make_uint2(lo, hi);
-    }
-    __syncthreads();
-  }
   float* scrA = sm.scr[wave];
   float* scrB = sm.scr[wave] + 32 * RSR;
   const ScatterStage stage{sm.scr[wave], sm.heads[wave], sm.rows[wave]};
-  float* priv = reinterpret_cast<float*>(smem_raw + kSmemBytes);
+  float* priv = reinterpret_cast<float*>(smem_raw + smem_bytes<BF>());
   if (BWD)
     for (int e = tid; e < A.priv_floats; e += kBlock) priv[e] = 0.f;
   __syncthreads();
@@ -265,15 +264,18 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
   const int per_tile = MODE == 0 ? 16 : 16;
   const int n_tiles = (n_items + per_tile - 1) / per_tile;
 
-  // accumulators (backward)
-  v4f aW1[2], aW2[4], aW3[2], aU1[2], aU2[2];
-  v4f gB1[2], gB2[2], gB3, gC1[2], gC2, gW3r0[2];
+  // accumulators of the decoder gradients (backward), in MFMA accumulator layout:
+  // aW1 [32 x 16], aW2 [32 x 32], aW3 [16 x 32], aU1 [32 x 16 o-index; column 0
+  // holds c1]; aS [16 x 16] gathers the small ones by column: 0-1 b1, 2-3 b2,
+  // 4 b3, 5 c2, 6-7 the Eikonal part of W3 row 0, 10-15 U2 (column 10 + 3b + c
+  // holds U2[c][16b + row]).
+  v4f aW1[2], aW2[4], aW3[2], aU1[2], aS;
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
-    aW1[b] = aW3[b] = aU1[b] = aU2[b] = gB1[b] = gB2[b] = gC1[b] = gW3r0[b] = v4f{0, 0, 0, 0};
+    aW1[b] = aW3[b] = aU1[b] = v4f{0, 0, 0, 0};
     aW2[b] = aW2[b + 2] = v4f{0, 0, 0, 0};
   }
-  gB3 = gC2 = v4f{0, 0, 0, 0};
+  aS = v4f{0, 0, 0, 0};
   float smooth_acc = 0.f;
 
   for (int tile = blockIdx.x * kWavesPerBlock + wave; tile < n_tiles; tile += gridDim.x * kWavesPerBlock) {
@@ -421,20 +423,49 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
       for (int b = 0; b < 2; ++b) dh1[b] = relu_mask(dh1[b], h1[b]);
       layer<BF, 1, 2>(sm, T_L1T, dh1, &dz, lane);
 
-      // weight gradients (sum over the tile's samples)
-      outer_acc<BF, 1, 2>(scrA, scrB, &dc2, hc, aU2, q, j);
-      outer_acc<BF, 2, 1>(scrA, scrB, dhc, &ob, aU1, q, j);
-      outer_acc<BF, 1, 2>(scrA, scrB, &dob, h2, aW3, q, j);
-      outer_acc<BF, 2, 2>(scrA, scrB, dh2, h1, aW2, q, j);
-      outer_acc<BF, 2, 1>(scrA, scrB, dh1, &zb, aW1, q, j);
+      // weight gradients (sums over the tile's samples, the MFMA K axis)
+      float4 tX[2], tY[2];
+      // U2 and c2: U2[c][k] = sum_s dc2[c][s] hc[k][s] goes to column 10 + 3b + c
+      // of aS (row k - 16b), with hc as the A operand and dc2 row c as the B
+      // operand of exactly those columns
+      rows_to_lanes<2>(scrA, hc, tX, q, j);
+      rows_to_lanes<1>(scrB, &dc2, tY, q, j);
+      colsum_into(tY[0], 5, aS, j);
+      {
+        const int c = j >= 13 ? j - 13 : (j >= 10 ? j - 10 : 0);
+        const float4 d = *reinterpret_cast<const float4*>(scrB + c * RSR + 4 * q);
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        gB1[b] += dh1[b];
-        gB2[b] += dh2[b];
-        gC1[b] += dhc[b];
+        for (int b = 0; b < 2; ++b) {
+          const bool on = j >= 10 + 3 * b && j < 13 + 3 * b;
+          aS = mfma4(tX[b].x, on ? d.x : 0.f, aS);
+          aS = mfma4(tX[b].y, on ? d.y : 0.f, aS);
+          aS = mfma4(tX[b].z, on ? d.z : 0.f, aS);
+          aS = mfma4(tX[b].w, on ? d.w : 0.f, aS);
+        }
       }
-      gB3 += dob;
-      gC2 += dc2;
+      // U1 and c1: o-index 0 (phi) does not feed the colour decoder; its
+      // operand row is replaced by ones, so column 0 of aU1 sums dhc (= dc1)
+      rows_to_lanes<2>(scrA, dhc, tX, q, j);
+      rows_to_lanes<1>(scrB, &ob, tY, q, j);
+      if (j == 0) tY[0] = make_float4(1.f, 1.f, 1.f, 1.f);
+      outer_lanes<BF, 2, 1>(tX, tY, aU1);
+      // W3 and b3
+      rows_to_lanes<1>(scrA, &dob, tX, q, j);
+      rows_to_lanes<2>(scrB, h2, tY, q, j);
+      outer_lanes<BF, 1, 2>(tX, tY, aW3);
+      colsum_into(tX[0], 4, aS, j);
+      // W2 and b2
+      rows_to_lanes<2>(scrA, dh2, tX, q, j);
+      rows_to_lanes<2>(scrB, h1, tY, q, j);
+      outer_lanes<BF, 2, 2>(tX, tY, aW2);
+      colsum_into(tX[0], 2, aS, j);
+      colsum_into(tX[1], 3, aS, j);
+      // W1 and b1
+      rows_to_lanes<2>(scrA, dh1, tX, q, j);
+      rows_to_lanes<1>(scrB, &zb, tY, q, j);
+      outer_lanes<BF, 2, 1>(tX, tY, aW1);
+      colsum_into(tX[0], 0, aS, j);
+      colsum_into(tX[1], 1, aS, j);
 
       const float dzl[4] = {dz[0], dz[1], dz[2], dz[3]};
       if (A.need_gx) {
@@ -448,9 +479,17 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
         for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
         layer<BF, 2, 2>(sm, T_L2, r1, w2r1, lane);
 #pragma unroll
-        for (int b = 0; b < 2; ++b) gW3r0[b] += relu_mask(w2r1[b], h2[b]);
-        outer_acc<BF, 2, 2>(scrA, scrB, e2, r1, aW2, q, j);
-        outer_acc<BF, 2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
+        for (int b = 0; b < 2; ++b) w2r1[b] = relu_mask(w2r1[b], h2[b]);
+        float4 tX[2], tY[2];
+        rows_to_lanes<2>(scrA, w2r1, tX, q, j);
+        colsum_into(tX[0], 6, aS, j);
+        colsum_into(tX[1], 7, aS, j);
+        rows_to_lanes<2>(scrA, e2, tX, q, j);
+        rows_to_lanes<2>(scrB, r1, tY, q, j);
+        outer_lanes<BF, 2, 2>(tX, tY, aW2);
+        rows_to_lanes<2>(scrA, e1, tX, q, j);
+        rows_to_lanes<1>(scrB, &qv, tY, q, j);
+        outer_lanes<BF, 2, 1>(tX, tY, aW1);
         const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
         scatter<true, true>(A, priv, stage, lane, q, j, ls, valid, dzl, al, gv);
       } else {
@@ -475,9 +514,17 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
       for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
       layer<BF, 2, 2>(sm, T_L2, r1, w2r1, lane);
 #pragma unroll
-      for (int b = 0; b < 2; ++b) gW3r0[b] += relu_mask(w2r1[b], h2[b]);
-      outer_acc<BF, 2, 2>(scrA, scrB, e2, r1, aW2, q, j);
-      outer_acc<BF, 2, 1>(scrA, scrB, e1, &qv, aW1, q, j);
+      for (int b = 0; b < 2; ++b) w2r1[b] = relu_mask(w2r1[b], h2[b]);
+      float4 tX[2], tY[2];
+      rows_to_lanes<2>(scrA, w2r1, tX, q, j);
+      colsum_into(tX[0], 6, aS, j);
+      colsum_into(tX[1], 7, aS, j);
+      rows_to_lanes<2>(scrA, e2, tX, q, j);
+      rows_to_lanes<2>(scrB, r1, tY, q, j);
+      outer_lanes<BF, 2, 2>(tX, tY, aW2);
+      rows_to_lanes<2>(scrA, e1, tX, q, j);
+      rows_to_lanes<1>(scrB, &qv, tY, q, j);
+      outer_lanes<BF, 2, 1>(tX, tY, aW1);
       const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
       const float dzl[4] = {0, 0, 0, 0};
       scatter<false, true>(A, priv, stage, lane, q, j, ls, pv, dzl, al, gv);
@@ -521,40 +568,28 @@ __global__ __launch_bounds__(kBlock) void field_kernel(FieldArgs A) {
       red[oW2 + row * 32 + j] = aW2[ba * 2 + 0][r];
       red[oW2 + row * 32 + 16 + j] = aW2[ba * 2 + 1][r];
       if (j >= 1) red[oU1 + row * 15 + j - 1] = aU1[ba][r];
+      else red[oC1 + row] = aU1[ba][r];
     }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = 4 * q + r;
-    float w3a = aW3[0][r], w3b = aW3[1][r];
-    red[oW3 + row * 32 + j] = w3a;
-    red[oW3 + row * 32 + 16 + j] = w3b;
-    if (row < 3) {
-      red[oU2 + row * 32 + j] = aU2[0][r];
-      red[oU2 + row * 32 + 16 + j] = aU2[1][r];
-    }
+    red[oW3 + row * 32 + j] = aW3[0][r];
+    red[oW3 + row * 32 + 16 + j] = aW3[1][r];
   }
   wave_lds_fence();
-  // bias gradients and the W3 row-0 term: sums over the 16 sample lanes
-#pragma unroll
-  for (int b = 0; b < 2; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * b + 4 * q + r;
-      const float s1 = sum16(gB1[b][r]), s2 = sum16(gB2[b][r]), s3 = sum16(gC1[b][r]), s4 = sum16(gW3r0[b][r]);
-      if (j == 0) {
-        red[oB1 + row] = s1;
-        red[oB2 + row] = s2;
-        red[oC1 + row] = s3;
-        red[oW3 + row] += s4;
-      }
-    }
+  // the columns of aS (lane j holds column j, rows 4q..4q+3)
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const float s1 = sum16(gB3[r]), s2 = sum16(gC2[r]);
-    const int row = 4 * q + r;
-    if (j == 0) {
-      red[oB3 + row] = s1;
-      if (row < 3) red[oC2 + row] = s2;
+    const int i = 4 * q + r;
+    const float v = aS[r];
+    if (j < 2) red[oB1 + 16 * j + i] = v;
+    else if (j < 4) red[oB2 + 16 * (j - 2) + i] = v;
+    else if (j == 4) red[oB3 + i] = v;
+    else if (j == 5) { if (i < 3) red[oC2 + i] = v; }
+    else if (j < 8) red[oW3 + 16 * (j - 6) + i] += v;
+    else if (j >= 10) {
+      const int b = (j - 10) / 3, c = (j - 10) % 3;
+      red[oU2 + c * 32 + 16 * b + i] = v;
     }
   }
   __syncthreads();
@@ -632,9 +667,10 @@ void plan_privatised_levels(FieldArgs& a, int counts[4]) {
 int priv_max_floats() { return kPrivMaxFloats; }
 
 hipError_t launch_field(const FieldArgs& a, int mode, bool bwd, int blocks, hipStream_t st) {
-  const size_t smem = kSmemBytes + (bwd ? (size_t)a.priv_floats * sizeof(float) : 0);
-  const dim3 g(blocks), b(kBlock);
   const bool bf = a.grid_bf16 != nullptr;
+  const size_t smem = (size_t)(bf ? smem_bytes<true>() : smem_bytes<false>()) +
+                      (bwd ? (size_t)a.priv_floats * sizeof(float) : 0);
+  const dim3 g(blocks), b(kBlock);
 #define GS_LAUNCH(M, B, F)                                                                              \
   do {                                                                                                   \
     hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<M, B, F>),                           \

@@ -44,6 +44,48 @@ __device__ __forceinline__ void store_rows(float* scr, const v4f* X, int q, int 
     for (int r = 0; r < 4; ++r) scr[(16 * b + 4 * q + r) * RSR + j] = X[b][r];
 }
 
+// X (NB blocks of 16 rows in accumulator layout, [row][sample]) passed through
+// the wave's LDS scratch so that lane (q, j) receives row 16b + j at samples
+// 4q..4q+3: the operand layout of a product that contracts over the samples.
+template <int NB>
+__device__ __forceinline__ void rows_to_lanes(float* scr, const v4f* X, float4* out, int q, int j) {
+  wave_lds_fence();
+  store_rows<NB>(scr, X, q, j);
+  wave_lds_fence();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) out[b] = *reinterpret_cast<const float4*>(scr + (16 * b + j) * RSR + 4 * q);
+}
+
+// acc[a][b] += sum over the tile's 16 samples of A[16a + i][s] * B[16b + n][s],
+// with both operands from rows_to_lanes.
+template <bool BF, int NA, int NB>
+__device__ __forceinline__ void outer_lanes(const float4* av, const float4* bv, v4f* acc) {
+  if constexpr (BF) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[a * NB + b] = mfma16_bf16(pack_bf16(av[a]), pack_bf16(bv[b]), acc[a * NB + b]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        acc[a * NB + b] = mfma4(av[a].x, bv[b].x, acc[a * NB + b]);
+        acc[a * NB + b] = mfma4(av[a].y, bv[b].y, acc[a * NB + b]);
+        acc[a * NB + b] = mfma4(av[a].z, bv[b].z, acc[a * NB + b]);
+        acc[a * NB + b] = mfma4(av[a].w, bv[b].w, acc[a * NB + b]);
+      }
+  }
+}
+
+// Column `col` of the 16x16 accumulator gains the sums over the tile's samples
+// of the 16 rows in av (from rows_to_lanes); the other columns are unchanged.
+// The B operand is the indicator of column `col`, so one MFMA sums the four
+// lane groups' partial sums.
+__device__ __forceinline__ void colsum_into(const float4& av, int col, v4f& acc, int j) {
+  acc = mfma4((av.x + av.y) + (av.z + av.w), j == col ? 1.f : 0.f, acc);
+}
+
 // acc[ba][bb] += sum over the tile's 16 samples of A[16ba + i][s] * B[16bb + n][s].
 // The sample axis is the MFMA K axis; lane group q supplies samples 4q..4q+3
 // (one 16-byte LDS read per operand block).
