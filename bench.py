@@ -39,13 +39,17 @@ def parse():
     return ap.parse_args()
 
 
-# Algorithmic bytes per unit of work of the timed kernels (FP32):
-#   backward field kernel, per sample: 4 levels x 8 corners x 16 B gathered
-#   (512 B) + 128 float atomic read-modify-writes of 4 B (512 B) + backward
-#   seeds (20 B) + depth and ray index (8 B) = 1052 B;
-#   forward field kernel, per sample: 512 B gathered + 8 B in + 20 B out;
+# Algorithmic bytes per unit of work of the timed kernels (FP32).  The field
+# kernels process ray samples and smoothness pairs in one launch:
+#   backward, per sample: 4 levels x 8 corners x 16 B gathered (512 B) + 128
+#   float atomic adds of 4 B (512 B) + backward seeds (20 B) + depth and ray
+#   index (8 B) = 1052 B; per pair: two points of 512 B gathered + 512 B
+#   atomics + 12 B position / perturbation = 2072 B;
+#   forward, per sample: 512 B gathered + 8 B in + 20 B out = 540 B; per pair:
+#   two points of 512 B gathered + 12 B = 1048 B;
 #   Adam, per parameter: p, g, m, v read and written (32 B).
 BYTES_PER_SAMPLE = {"field_bwd": 1052.0, "field_fwd": 540.0}
+BYTES_PER_PAIR = {"field_bwd": 2072.0, "field_fwd": 1048.0}
 BYTES_PER_PARAM_ADAM = 32.0
 
 
@@ -165,7 +169,7 @@ def main():
     # per-kernel durations: HIP events recorded by the library around each launch
     kern = {}
     for name, kid in (("field_fwd", G.KERNEL_FIELD_FWD), ("field_bwd", G.KERNEL_FIELD_BWD),
-                      ("smooth_bwd", G.KERNEL_SMOOTH_BWD), ("adam", G.KERNEL_ADAM)):
+                      ("adam", G.KERNEL_ADAM)):
         pairs = []
         for _ in range(a.steps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -189,11 +193,16 @@ def main():
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": bytes_per_launch, "ms_per_launch": round(ms, 4)}
 
+    pairs = w.S
+
+    def field_bytes(k):
+        return BYTES_PER_SAMPLE[k] * samples_now + BYTES_PER_PAIR[k] * pairs
+
     roofs = {
-        "field_bwd": roofline("field_bwd", BYTES_PER_SAMPLE["field_bwd"] * samples_now, kern["field_bwd"],
-                              "field_kernel<rays, backward> (gosurf_backward)"),
-        "field_fwd": roofline("field_fwd", BYTES_PER_SAMPLE["field_fwd"] * samples_now, kern["field_fwd"],
-                              "field_kernel<rays, forward> (gosurf_forward)"),
+        "field_bwd": roofline("field_bwd", field_bytes("field_bwd"), kern["field_bwd"],
+                              "field_kernel<backward> (gosurf_backward: samples and smoothness pairs)"),
+        "field_fwd": roofline("field_fwd", field_bytes("field_fwd"), kern["field_fwd"],
+                              "field_kernel<forward> (gosurf_forward: samples and smoothness pairs)"),
         "adam": roofline("adam", BYTES_PER_PARAM_ADAM * n_par, kern["adam"], "adam_kernel (gosurf_adam_step)"),
     }
     dominant = max(("field_fwd", "field_bwd", "adam"), key=lambda k: kern[k])

@@ -210,9 +210,8 @@ typedef struct {
 /* Kernels that can be timed individually (see gosurf_time_kernel). */
 typedef enum {
   GOSURF_KERNEL_NONE = 0,
-  GOSURF_KERNEL_FIELD_FWD = 1,     /* per-sample forward field kernel of gosurf_forward */
-  GOSURF_KERNEL_FIELD_BWD = 2,     /* per-sample backward field kernel of gosurf_backward */
-  GOSURF_KERNEL_SMOOTH_BWD = 3,    /* smoothness-pair backward kernel of gosurf_backward */
+  GOSURF_KERNEL_FIELD_FWD = 1,     /* forward field kernel of gosurf_forward (samples and smoothness pairs) */
+  GOSURF_KERNEL_FIELD_BWD = 2,     /* backward field kernel of gosurf_backward (samples and smoothness pairs) */
   GOSURF_KERNEL_ADAM = 4           /* the dense Adam kernel of gosurf_adam_step */
 } gosurf_kernel_id;
 

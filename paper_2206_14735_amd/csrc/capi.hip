@@ -13,11 +13,11 @@
 
 namespace gs {
 
-hipError_t launch_field(const FieldArgs& a, int mode, bool bwd, int blocks, hipStream_t st);
+hipError_t launch_field(const FieldArgs& a, bool bwd, int blocks, hipStream_t st);
 hipError_t launch_priv_reduce(const FieldArgs& a, int n_part, const int counts[4], float* tmp, hipStream_t st);
 void plan_privatised_levels(FieldArgs& a, int counts[4]);
 int priv_max_floats();
-int field_blocks(int n_items, int per_tile);
+int field_blocks(int total, int pairs);
 hipError_t launch_render(const RenderArgs& a, bool bwd, hipStream_t st);
 hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smooth_partial, int n_sp, int S,
                               const float lam[6], float* losses, hipStream_t st);
@@ -185,7 +185,9 @@ extern "C" {
 const char* gosurf_last_error(void) { return g_err.c_str(); }
 
 gosurf_status gosurf_time_kernel(int32_t kernel, void* start_event, void* stop_event) {
-  if (kernel < GOSURF_KERNEL_NONE || kernel > GOSURF_KERNEL_ADAM) return fail(GOSURF_ERR_VALUE, "unknown kernel %d", kernel);
+  if (kernel != GOSURF_KERNEL_NONE && kernel != GOSURF_KERNEL_FIELD_FWD && kernel != GOSURF_KERNEL_FIELD_BWD &&
+      kernel != GOSURF_KERNEL_ADAM)
+    return fail(GOSURF_ERR_VALUE, "unknown kernel %d", kernel);
   g_timed_kernel = (start_event && stop_event) ? kernel : GOSURF_KERNEL_NONE;
   g_ev_start = static_cast<hipEvent_t>(start_event);
   g_ev_stop = static_cast<hipEvent_t>(stop_event);
@@ -298,15 +300,12 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
+  if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped
+  const int nb = gs::field_blocks(b->total, fa.S);
   mark(GOSURF_KERNEL_FIELD_FWD, true, s);
-  if ((st = hip_check(gs::launch_field(fa, 0, false, gs::field_blocks(b->total, 16), s), "field fwd")) != GOSURF_OK)
-    return st;
+  if ((st = hip_check(gs::launch_field(fa, false, nb, s), "field fwd")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_FIELD_FWD, false, s);
-  int n_sp = 0;
-  if (b->S > 0 && loss->lambda[5] != 0.f) {
-    n_sp = gs::field_blocks(2 * b->S, 16);
-    if ((st = hip_check(gs::launch_field(fa, 1, false, n_sp, s), "smoothness fwd")) != GOSURF_OK) return st;
-  }
+  const int n_sp = fa.S > 0 ? nb : 0;
   gs::RenderArgs ra{};
   ra.g = g; ra.o = b->o; ra.r = b->r; ra.rgb = b->rgb; ra.depth = b->depth; ra.t = b->t; ra.seg = b->seg;
   ra.M = b->M; ra.mlp = params->mlp; ra.out4 = out->saved; ra.eik = need_gx ? eik : nullptr;
@@ -359,26 +358,17 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   fa.seed4 = w.seed4; fa.eikw = w.eikw; fa.need_gx = need_gx;
   fa.grad_grid = grads->grid; fa.mlp_partial = w.mlp_partial;
   fa.smooth_coef = b->S > 0 ? 2.f * loss->lambda[5] * loss_scale / (float)b->S : 0.f;
+  if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped
   int counts[4];
   gs::plan_privatised_levels(fa, counts);
   fa.priv_partial = w.priv_partial;
-  const int nbr = gs::field_blocks(b->total, 16);
+  const int nb = gs::field_blocks(b->total, fa.S);
   mark(GOSURF_KERNEL_FIELD_BWD, true, s);
-  if ((st = hip_check(gs::launch_field(fa, 0, true, nbr, s), "field bwd")) != GOSURF_OK) return st;
+  if ((st = hip_check(gs::launch_field(fa, true, nb, s), "field bwd")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_FIELD_BWD, false, s);
-  int nbs = 0;
-  if (b->S > 0 && loss->lambda[5] != 0.f) {
-    nbs = gs::field_blocks(2 * b->S, 16);
-    fa.mlp_partial = w.mlp_partial + (size_t)nbr * gs::kMlpNumel;
-    fa.priv_partial = w.priv_partial + (size_t)nbr * fa.priv_floats;
-    mark(GOSURF_KERNEL_SMOOTH_BWD, true, s);
-    if ((st = hip_check(gs::launch_field(fa, 1, true, nbs, s), "smoothness bwd")) != GOSURF_OK) return st;
-    mark(GOSURF_KERNEL_SMOOTH_BWD, false, s);
-  }
-  fa.priv_partial = w.priv_partial;
-  if ((st = hip_check(gs::launch_priv_reduce(fa, nbr + nbs, counts, w.colsum_tmp, s), "level reduce")) != GOSURF_OK)
+  if ((st = hip_check(gs::launch_priv_reduce(fa, nb, counts, w.colsum_tmp, s), "level reduce")) != GOSURF_OK)
     return st;
-  if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nbr + nbs, w.ray_dv, b->M, grads->mlp, w.colsum_tmp, s),
+  if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nb, w.ray_dv, b->M, grads->mlp, w.colsum_tmp, s),
                       "grad reduce")) != GOSURF_OK)
     return st;
   return ok();

@@ -199,32 +199,296 @@ __device__ __forceinline__ v4f relu_mask(v4f x, v4f h) {
 }
 
 // LDS footprint of one block.  The fp32 kernels keep one float per lane per
-// MFMA step, the bf16 kernels four packed bf16 values per lane per input block.
-template <bool BF>
+// MFMA step, the bf16 kernels four packed bf16 values per lane per input block;
+// only the backward kernels need the per-wave scratch.
+template <bool BF, bool BWD>
 struct FieldSmem {
   float tab[BF ? 1 : T_END * 64];
   uint2 tabbf[BF ? (T_END / 4) * 64 : 1];
   float bias[32 + 32 + 16 + 32 + 16];   // b1, b2, b3, c1, c2(pad 16)
   float w3row0[32];
-  float scr[kWavesPerBlock][2048];       // operand transposes, then scatter staging
-  int heads[kWavesPerBlock][64];
-  int rows[kWavesPerBlock][64];
+  float scr[kWavesPerBlock][BWD ? 2048 : 1];   // operand transposes, then scatter staging
+  int heads[kWavesPerBlock][BWD ? 64 : 1];
+  int rows[kWavesPerBlock][BWD ? 64 : 1];
 };
 constexpr int kRedFloats = kWavesPerBlock * kMlpNumel;
-template <bool BF>
+// the area is reused at the end for the per-wave block partials
+template <bool BF, bool BWD>
 constexpr int smem_bytes() {
-  return (sizeof(FieldSmem<BF>) > kRedFloats * 4) ? (int)sizeof(FieldSmem<BF>) : kRedFloats * 4;
+  constexpr int red = BWD ? kRedFloats * 4 : kWavesPerBlock * 4;
+  return (sizeof(FieldSmem<BF, BWD>) > red) ? (int)sizeof(FieldSmem<BF, BWD>) : red;
 }
 constexpr int kPrivMaxFloats = 4096;   // LDS budget for privatised levels (1024 vertices)
 
-// MODE 0: ray samples; MODE 1: smoothness pairs (16-lane tile = 8 pairs: lanes
+// One wave-tile: MODE 0 = 16 ray samples, MODE 1 = 8 smoothness pairs (lanes
 // j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).
-template <int MODE, bool BWD, bool BF>
+template <int MODE, bool BWD, bool BF, class Smem>
+__device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, int tile, int total, int lane, int q,
+                                           int j, float* scrA, float* scrB, const ScatterStage& stage, float* priv,
+                                           v4f (&aW1)[2], v4f (&aW2)[4], v4f (&aW3)[2], v4f (&aU1)[2], v4f& aS,
+                                           float& smooth_acc) {
+  const bool need_g = (MODE == 1) || A.need_gx;
+  // ---------------- sample position
+  int item;
+  float px, py, pz;
+  bool live;
+  if (MODE == 0) {
+    item = tile * 16 + j;
+    live = item < total;
+    px = py = pz = 0.f;
+    if (live) {
+      const int ray = A.ray_of[item];
+      const float tt = A.t[item];
+      px = mad_norm(tt, A.r[3 * ray + 0], A.o[3 * ray + 0]);
+      py = mad_norm(tt, A.r[3 * ray + 1], A.o[3 * ray + 1]);
+      pz = mad_norm(tt, A.r[3 * ray + 2], A.o[3 * ray + 2]);
+    }
+  } else {
+    const int pair = tile * 8 + (j & 7);
+    item = pair;
+    live = pair < A.S;
+    px = py = pz = 0.f;
+    if (live) {
+      px = A.xs[3 * pair + 0];
+      py = A.xs[3 * pair + 1];
+      pz = A.xs[3 * pair + 2];
+      if (j >= 8) {
+        px = __fadd_rn(px, A.eps[3 * pair + 0]);
+        py = __fadd_rn(py, A.eps[3 * pair + 1]);
+        pz = __fadd_rn(pz, A.eps[3 * pair + 2]);
+      }
+    }
+  }
+  const bool valid = live && inside_box(A.g, px, py, pz);
+  LevelSample ls;
+  locate(A.g, q, px, py, pz, ls);
+  float zl[4], G[4][3];
+  if (need_g) interp<true, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
+  else interp<false, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
+
+  // ---------------- geometry decoder
+  v4f zb = v4f{zl[0], zl[1], zl[2], zl[3]};
+  v4f h1[2], h2[2], ob, hc[2], cb;
+  layer<BF, 2, 1>(sm, T_L1, &zb, h1, lane);
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h1[b][r] = fmaxf(h1[b][r] + sm.bias[16 * b + 4 * q + r], 0.f);
+  layer<BF, 2, 2>(sm, T_L2, h1, h2, lane);
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h2[b][r] = fmaxf(h2[b][r] + sm.bias[32 + 16 * b + 4 * q + r], 0.f);
+  layer<BF, 1, 2>(sm, T_L3, h2, &ob, lane);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ob[r] += sm.bias[64 + 4 * q + r];
+
+  // ---------------- colour decoder (ray mode)
+  if (MODE == 0) {
+    layer<BF, 2, 1>(sm, T_C1, &ob, hc, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) hc[b][r] = fmaxf(hc[b][r] + sm.bias[80 + 16 * b + 4 * q + r], 0.f);
+    layer<BF, 1, 2>(sm, T_C2, hc, &cb, lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cb[r] = sigmoidf_(cb[r] + sm.bias[112 + 4 * q + r]);
+  }
+
+  // ---------------- d phi / d x
+  v4f e2[2], e1[2], ab;
+  float gx[3] = {0.f, 0.f, 0.f};
+  if (need_g) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) e2[b][r] = h2[b][r] > 0.f ? sm.w3row0[16 * b + 4 * q + r] : 0.f;
+    layer<BF, 2, 2>(sm, T_L2T, e2, e1, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) e1[b] = relu_mask(e1[b], h1[b]);
+    layer<BF, 1, 2>(sm, T_L1T, e1, &ab, lane);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float v = ab[0] * G[0][a] + ab[1] * G[1][a] + ab[2] * G[2][a] + ab[3] * G[3][a];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      gx[a] = v;
+    }
+  }
+
+  if constexpr (!BWD) {
+    if (MODE == 0) {
+      if (q == 0 && live) {
+        *reinterpret_cast<float4*>(A.out4 + 4 * (size_t)item) = make_float4(ob[0], cb[0], cb[1], cb[2]);
+        if (A.need_gx) {
+          const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
+          A.eik[item] = (1.f - n) * (1.f - n);
+        }
+      }
+    } else {
+      // pair partner is lane j ^ 8 of the same level group
+      float d0 = gx[0] - __shfl_xor(gx[0], 8, 64);
+      float d1 = gx[1] - __shfl_xor(gx[1], 8, 64);
+      float d2 = gx[2] - __shfl_xor(gx[2], 8, 64);
+      const bool pv = valid && __shfl_xor((int)valid, 8, 64);
+      if (q == 0 && j < 8 && pv) smooth_acc += d0 * d0 + d1 * d1 + d2 * d2;
+    }
+    return;
+  } else {
+
+  // ================================================================ backward
+  float gv[3] = {0.f, 0.f, 0.f};   // dL / d(grad phi)
+  if (MODE == 0) {
+    float4 sd = make_float4(0.f, 0.f, 0.f, 0.f);
+    float ew = 0.f;
+    if (live && valid) {
+      sd = *reinterpret_cast<const float4*>(A.seed4 + 4 * (size_t)item);
+      if (A.need_gx) ew = A.eikw[item];
+    }
+    if (A.need_gx && ew != 0.f) {
+      const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
+      const float c = n > 0.f ? ew * 2.f * (n - 1.f) / n : 0.f;
+      gv[0] = c * gx[0]; gv[1] = c * gx[1]; gv[2] = c * gx[2];
+    }
+    // colour: dL/d(pre-sigmoid) for rows 0..2 held by level-group 0
+    v4f dc2 = v4f{0, 0, 0, 0};
+    if (q == 0) {
+      dc2[0] = sd.y * cb[0] * (1.f - cb[0]);
+      dc2[1] = sd.z * cb[1] * (1.f - cb[1]);
+      dc2[2] = sd.w * cb[2] * (1.f - cb[2]);
+    }
+    v4f dhc[2], dob;
+    layer<BF, 2, 1>(sm, T_C2T, &dc2, dhc, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) dhc[b] = relu_mask(dhc[b], hc[b]);
+    layer<BF, 1, 2>(sm, T_C1T, dhc, &dob, lane);
+    if (q == 0) dob[0] += sd.x;
+    v4f dh2[2], dh1[2], dz;
+    layer<BF, 2, 1>(sm, T_L3T, &dob, dh2, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) dh2[b] = relu_mask(dh2[b], h2[b]);
+    layer<BF, 2, 2>(sm, T_L2T, dh2, dh1, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) dh1[b] = relu_mask(dh1[b], h1[b]);
+    layer<BF, 1, 2>(sm, T_L1T, dh1, &dz, lane);
+
+    // weight gradients (sums over the tile's samples, the MFMA K axis)
+    float4 tX[2], tY[2];
+    // U2 and c2: U2[c][k] = sum_s dc2[c][s] hc[k][s] goes to column 10 + 3b + c
+    // of aS (row k - 16b), with hc as the A operand and dc2 row c as the B
+    // operand of exactly those columns
+    rows_to_lanes<2>(scrA, hc, tX, q, j);
+    rows_to_lanes<1>(scrB, &dc2, tY, q, j);
+    colsum_into(tY[0], 5, aS, j);
+    {
+      const int c = j >= 13 ? j - 13 : (j >= 10 ? j - 10 : 0);
+      const float4 d = *reinterpret_cast<const float4*>(scrB + c * RSR + 4 * q);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const bool on = j >= 10 + 3 * b && j < 13 + 3 * b;
+        aS = mfma4(tX[b].x, on ? d.x : 0.f, aS);
+        aS = mfma4(tX[b].y, on ? d.y : 0.f, aS);
+        aS = mfma4(tX[b].z, on ? d.z : 0.f, aS);
+        aS = mfma4(tX[b].w, on ? d.w : 0.f, aS);
+      }
+    }
+    // U1 and c1: o-index 0 (phi) does not feed the colour decoder; its
+    // operand row is replaced by ones, so column 0 of aU1 sums dhc (= dc1)
+    rows_to_lanes<2>(scrA, dhc, tX, q, j);
+    rows_to_lanes<1>(scrB, &ob, tY, q, j);
+    if (j == 0) tY[0] = make_float4(1.f, 1.f, 1.f, 1.f);
+    outer_lanes<BF, 2, 1>(tX, tY, aU1);
+    // W3 and b3
+    rows_to_lanes<1>(scrA, &dob, tX, q, j);
+    rows_to_lanes<2>(scrB, h2, tY, q, j);
+    outer_lanes<BF, 1, 2>(tX, tY, aW3);
+    colsum_into(tX[0], 4, aS, j);
+    // W2 and b2
+    rows_to_lanes<2>(scrA, dh2, tX, q, j);
+    rows_to_lanes<2>(scrB, h1, tY, q, j);
+    outer_lanes<BF, 2, 2>(tX, tY, aW2);
+    colsum_into(tX[0], 2, aS, j);
+    colsum_into(tX[1], 3, aS, j);
+    // W1 and b1
+    rows_to_lanes<2>(scrA, dh1, tX, q, j);
+    rows_to_lanes<1>(scrB, &zb, tY, q, j);
+    outer_lanes<BF, 2, 1>(tX, tY, aW1);
+    colsum_into(tX[0], 0, aS, j);
+    colsum_into(tX[1], 1, aS, j);
+
+    const float dzl[4] = {dz[0], dz[1], dz[2], dz[3]};
+    if (A.need_gx) {
+      // second-order terms of the Eikonal residual
+      v4f qv;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) qv[k] = gv[0] * G[k][0] + gv[1] * G[k][1] + gv[2] * G[k][2];
+      v4f r1[2], w2r1[2];
+      layer<BF, 2, 1>(sm, T_L1, &qv, r1, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
+      layer<BF, 2, 2>(sm, T_L2, r1, w2r1, lane);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) w2r1[b] = relu_mask(w2r1[b], h2[b]);
+      float4 tX[2], tY[2];
+      rows_to_lanes<2>(scrA, w2r1, tX, q, j);
+      colsum_into(tX[0], 6, aS, j);
+      colsum_into(tX[1], 7, aS, j);
+      rows_to_lanes<2>(scrA, e2, tX, q, j);
+      rows_to_lanes<2>(scrB, r1, tY, q, j);
+      outer_lanes<BF, 2, 2>(tX, tY, aW2);
+      rows_to_lanes<2>(scrA, e1, tX, q, j);
+      rows_to_lanes<1>(scrB, &qv, tY, q, j);
+      outer_lanes<BF, 2, 1>(tX, tY, aW1);
+      const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
+      scatter<true, true>(A, priv, stage, lane, q, j, ls, valid, dzl, al, gv);
+    } else {
+      const float al[4] = {0, 0, 0, 0};
+      scatter<true, false>(A, priv, stage, lane, q, j, ls, valid, dzl, al, gv);
+    }
+  } else {
+    // smoothness pair: d|g(x) - g(x+eps)|^2 / dg at either point is
+    // 2 (own gradient - partner's gradient); smooth_coef carries the 2.
+    const bool pv = valid && __shfl_xor((int)valid, 8, 64);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float d = gx[a] - __shfl_xor(gx[a], 8, 64);
+      gv[a] = pv ? A.smooth_coef * d : 0.f;
+    }
+    v4f qv;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qv[k] = gv[0] * G[k][0] + gv[1] * G[k][1] + gv[2] * G[k][2];
+    v4f r1[2], w2r1[2];
+    layer<BF, 2, 1>(sm, T_L1, &qv, r1, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
+    layer<BF, 2, 2>(sm, T_L2, r1, w2r1, lane);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) w2r1[b] = relu_mask(w2r1[b], h2[b]);
+    float4 tX[2], tY[2];
+    rows_to_lanes<2>(scrA, w2r1, tX, q, j);
+    colsum_into(tX[0], 6, aS, j);
+    colsum_into(tX[1], 7, aS, j);
+    rows_to_lanes<2>(scrA, e2, tX, q, j);
+    rows_to_lanes<2>(scrB, r1, tY, q, j);
+    outer_lanes<BF, 2, 2>(tX, tY, aW2);
+    rows_to_lanes<2>(scrA, e1, tX, q, j);
+    rows_to_lanes<1>(scrB, &qv, tY, q, j);
+    outer_lanes<BF, 2, 1>(tX, tY, aW1);
+    const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
+    const float dzl[4] = {0, 0, 0, 0};
+    scatter<false, true>(A, priv, stage, lane, q, j, ls, pv, dzl, al, gv);
+  }
+  }
+}
+
+// Pair tiles come first, then ray tiles, in one launch: the few pair tiles
+// overlap with the ray tiles of other waves.
 // At least two waves per SIMD: the backward kernels then fit 256 registers
 // without spilling, and a second wave hides the gather and atomic latency.
+template <bool BWD, bool BF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void field_kernel(FieldArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  FieldSmem<BF>& sm = *reinterpret_cast<FieldSmem<BF>*>(smem_raw);
+  FieldSmem<BF, BWD>& sm = *reinterpret_cast<FieldSmem<BF, BWD>*>(smem_raw);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
 
@@ -250,19 +514,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     sm.bias[64 + tid] = A.mlp[oB3 + tid];
     sm.bias[112 + tid] = tid < 3 ? A.mlp[oC2 + tid] : 0.f;
   }
-  float* scrA = sm.scr[wave];
-  float* scrB = sm.scr[wave] + 32 * RSR;
-  const ScatterStage stage{sm.scr[wave], sm.heads[wave], sm.rows[wave]};
-  float* priv = reinterpret_cast<float*>(smem_raw + smem_bytes<BF>());
+  float* scrA = BWD ? sm.scr[wave] : nullptr;
+  float* scrB = BWD ? sm.scr[wave] + 32 * RSR : nullptr;
+  const ScatterStage stage{scrA, BWD ? sm.heads[wave] : nullptr, BWD ? sm.rows[wave] : nullptr};
+  float* priv = reinterpret_cast<float*>(smem_raw + smem_bytes<BF, BWD>());
   if (BWD)
     for (int e = tid; e < A.priv_floats; e += kBlock) priv[e] = 0.f;
   __syncthreads();
 
-  const bool need_g = (MODE == 1) || A.need_gx;
-  const int total = (MODE == 0 && A.seg_end) ? *A.seg_end : A.total;
-  const int n_items = MODE == 0 ? total : 2 * A.S;   // lanes of work
-  const int per_tile = MODE == 0 ? 16 : 16;
-  const int n_tiles = (n_items + per_tile - 1) / per_tile;
+  const int total = A.seg_end ? *A.seg_end : A.total;
+  const int n_pair_tiles = (A.S + 7) / 8;
+  const int n_tiles = n_pair_tiles + (total + 15) / 16;
 
   // accumulators of the decoder gradients (backward), in MFMA accumulator layout:
   // aW1 [32 x 16], aW2 [32 x 32], aW3 [16 x 32], aU1 [32 x 16 o-index; column 0
@@ -279,260 +541,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   float smooth_acc = 0.f;
 
   for (int tile = blockIdx.x * kWavesPerBlock + wave; tile < n_tiles; tile += gridDim.x * kWavesPerBlock) {
-    // ---------------- sample position
-    int item;
-    float px, py, pz;
-    bool live;
-    if (MODE == 0) {
-      item = tile * 16 + j;
-      live = item < total;
-      px = py = pz = 0.f;
-      if (live) {
-        const int ray = A.ray_of[item];
-        const float tt = A.t[item];
-        px = mad_norm(tt, A.r[3 * ray + 0], A.o[3 * ray + 0]);
-        py = mad_norm(tt, A.r[3 * ray + 1], A.o[3 * ray + 1]);
-        pz = mad_norm(tt, A.r[3 * ray + 2], A.o[3 * ray + 2]);
-      }
-    } else {
-      const int pair = tile * 8 + (j & 7);
-      item = pair;
-      live = pair < A.S;
-      px = py = pz = 0.f;
-      if (live) {
-        px = A.xs[3 * pair + 0];
-        py = A.xs[3 * pair + 1];
-        pz = A.xs[3 * pair + 2];
-        if (j >= 8) {
-          px = __fadd_rn(px, A.eps[3 * pair + 0]);
-          py = __fadd_rn(py, A.eps[3 * pair + 1]);
-          pz = __fadd_rn(pz, A.eps[3 * pair + 2]);
-        }
-      }
-    }
-    const bool valid = live && inside_box(A.g, px, py, pz);
-    LevelSample ls;
-    locate(A.g, q, px, py, pz, ls);
-    float zl[4], G[4][3];
-    if (need_g) interp<true, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
-    else interp<false, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
-
-    // ---------------- geometry decoder
-    v4f zb = v4f{zl[0], zl[1], zl[2], zl[3]};
-    v4f h1[2], h2[2], ob, hc[2], cb;
-    layer<BF, 2, 1>(sm, T_L1, &zb, h1, lane);
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h1[b][r] = fmaxf(h1[b][r] + sm.bias[16 * b + 4 * q + r], 0.f);
-    layer<BF, 2, 2>(sm, T_L2, h1, h2, lane);
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h2[b][r] = fmaxf(h2[b][r] + sm.bias[32 + 16 * b + 4 * q + r], 0.f);
-    layer<BF, 1, 2>(sm, T_L3, h2, &ob, lane);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) ob[r] += sm.bias[64 + 4 * q + r];
-
-    // ---------------- colour decoder (ray mode)
-    if (MODE == 0) {
-      layer<BF, 2, 1>(sm, T_C1, &ob, hc, lane);
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) hc[b][r] = fmaxf(hc[b][r] + sm.bias[80 + 16 * b + 4 * q + r], 0.f);
-      layer<BF, 1, 2>(sm, T_C2, hc, &cb, lane);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) cb[r] = sigmoidf_(cb[r] + sm.bias[112 + 4 * q + r]);
-    }
-
-    // ---------------- d phi / d x
-    v4f e2[2], e1[2], ab;
-    float gx[3] = {0.f, 0.f, 0.f};
-    if (need_g) {
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) e2[b][r] = h2[b][r] > 0.f ? sm.w3row0[16 * b + 4 * q + r] : 0.f;
-      layer<BF, 2, 2>(sm, T_L2T, e2, e1, lane);
-#pragma unroll
-      for (int b = 0; b < 2; ++b) e1[b] = relu_mask(e1[b], h1[b]);
-      layer<BF, 1, 2>(sm, T_L1T, e1, &ab, lane);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        float v = ab[0] * G[0][a] + ab[1] * G[1][a] + ab[2] * G[2][a] + ab[3] * G[3][a];
-        v += __shfl_xor(v, 16, 64);
-        v += __shfl_xor(v, 32, 64);
-        gx[a] = v;
-      }
-    }
-
-    if (!BWD) {
-      if (MODE == 0) {
-        if (q == 0 && live) {
-          *reinterpret_cast<float4*>(A.out4 + 4 * (size_t)item) = make_float4(ob[0], cb[0], cb[1], cb[2]);
-          if (A.need_gx) {
-            const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
-            A.eik[item] = (1.f - n) * (1.f - n);
-          }
-        }
-      } else {
-        // pair partner is lane j ^ 8 of the same level group
-        float d0 = gx[0] - __shfl_xor(gx[0], 8, 64);
-        float d1 = gx[1] - __shfl_xor(gx[1], 8, 64);
-        float d2 = gx[2] - __shfl_xor(gx[2], 8, 64);
-        const bool pv = valid && __shfl_xor((int)valid, 8, 64);
-        if (q == 0 && j < 8 && pv) smooth_acc += d0 * d0 + d1 * d1 + d2 * d2;
-      }
-      continue;
-    }
-
-    // ================================================================ backward
-    float gv[3] = {0.f, 0.f, 0.f};   // dL / d(grad phi)
-    if (MODE == 0) {
-      float4 sd = make_float4(0.f, 0.f, 0.f, 0.f);
-      float ew = 0.f;
-      if (live && valid) {
-        sd = *reinterpret_cast<const float4*>(A.seed4 + 4 * (size_t)item);
-        if (A.need_gx) ew = A.eikw[item];
-      }
-      if (A.need_gx && ew != 0.f) {
-        const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
-        const float c = n > 0.f ? ew * 2.f * (n - 1.f) / n : 0.f;
-        gv[0] = c * gx[0]; gv[1] = c * gx[1]; gv[2] = c * gx[2];
-      }
-      // colour: dL/d(pre-sigmoid) for rows 0..2 held by level-group 0
-      v4f dc2 = v4f{0, 0, 0, 0};
-      if (q == 0) {
-        dc2[0] = sd.y * cb[0] * (1.f - cb[0]);
-        dc2[1] = sd.z * cb[1] * (1.f - cb[1]);
-        dc2[2] = sd.w * cb[2] * (1.f - cb[2]);
-      }
-      v4f dhc[2], dob;
-      layer<BF, 2, 1>(sm, T_C2T, &dc2, dhc, lane);
-#pragma unroll
-      for (int b = 0; b < 2; ++b) dhc[b] = relu_mask(dhc[b], hc[b]);
-      layer<BF, 1, 2>(sm, T_C1T, dhc, &dob, lane);
-      if (q == 0) dob[0] += sd.x;
-      v4f dh2[2], dh1[2], dz;
-      layer<BF, 2, 1>(sm, T_L3T, &dob, dh2, lane);
-#pragma unroll
-      for (int b = 0; b < 2; ++b) dh2[b] = relu_mask(dh2[b], h2[b]);
-      layer<BF, 2, 2>(sm, T_L2T, dh2, dh1, lane);
-#pragma unroll
-      for (int b = 0; b < 2; ++b) dh1[b] = relu_mask(dh1[b], h1[b]);
-      layer<BF, 1, 2>(sm, T_L1T, dh1, &dz, lane);
-
-      // weight gradients (sums over the tile's samples, the MFMA K axis)
-      float4 tX[2], tY[2];
-      // U2 and c2: U2[c][k] = sum_s dc2[c][s] hc[k][s] goes to column 10 + 3b + c
-      // of aS (row k - 16b), with hc as the A operand and dc2 row c as the B
-      // operand of exactly those columns
-      rows_to_lanes<2>(scrA, hc, tX, q, j);
-      rows_to_lanes<1>(scrB, &dc2, tY, q, j);
-      colsum_into(tY[0], 5, aS, j);
-      {
-        const int c = j >= 13 ? j - 13 : (j >= 10 ? j - 10 : 0);
-        const float4 d = *reinterpret_cast<const float4*>(scrB + c * RSR + 4 * q);
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const bool on = j >= 10 + 3 * b && j < 13 + 3 * b;
-          aS = mfma4(tX[b].x, on ? d.x : 0.f, aS);
-          aS = mfma4(tX[b].y, on ? d.y : 0.f, aS);
-          aS = mfma4(tX[b].z, on ? d.z : 0.f, aS);
-          aS = mfma4(tX[b].w, on ? d.w : 0.f, aS);
-        }
-      }
-      // U1 and c1: o-index 0 (phi) does not feed the colour decoder; its
-      // operand row is replaced by ones, so column 0 of aU1 sums dhc (= dc1)
-      rows_to_lanes<2>(scrA, dhc, tX, q, j);
-      rows_to_lanes<1>(scrB, &ob, tY, q, j);
-      if (j == 0) tY[0] = make_float4(1.f, 1.f, 1.f, 1.f);
-      outer_lanes<BF, 2, 1>(tX, tY, aU1);
-      // W3 and b3
-      rows_to_lanes<1>(scrA, &dob, tX, q, j);
-      rows_to_lanes<2>(scrB, h2, tY, q, j);
-      outer_lanes<BF, 1, 2>(tX, tY, aW3);
-      colsum_into(tX[0], 4, aS, j);
-      // W2 and b2
-      rows_to_lanes<2>(scrA, dh2, tX, q, j);
-      rows_to_lanes<2>(scrB, h1, tY, q, j);
-      outer_lanes<BF, 2, 2>(tX, tY, aW2);
-      colsum_into(tX[0], 2, aS, j);
-      colsum_into(tX[1], 3, aS, j);
-      // W1 and b1
-      rows_to_lanes<2>(scrA, dh1, tX, q, j);
-      rows_to_lanes<1>(scrB, &zb, tY, q, j);
-      outer_lanes<BF, 2, 1>(tX, tY, aW1);
-      colsum_into(tX[0], 0, aS, j);
-      colsum_into(tX[1], 1, aS, j);
-
-      const float dzl[4] = {dz[0], dz[1], dz[2], dz[3]};
-      if (A.need_gx) {
-        // second-order terms of the Eikonal residual
-        v4f qv;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) qv[k] = gv[0] * G[k][0] + gv[1] * G[k][1] + gv[2] * G[k][2];
-        v4f r1[2], w2r1[2];
-        layer<BF, 2, 1>(sm, T_L1, &qv, r1, lane);
-#pragma unroll
-        for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
-        layer<BF, 2, 2>(sm, T_L2, r1, w2r1, lane);
-#pragma unroll
-        for (int b = 0; b < 2; ++b) w2r1[b] = relu_mask(w2r1[b], h2[b]);
-        float4 tX[2], tY[2];
-        rows_to_lanes<2>(scrA, w2r1, tX, q, j);
-        colsum_into(tX[0], 6, aS, j);
-        colsum_into(tX[1], 7, aS, j);
-        rows_to_lanes<2>(scrA, e2, tX, q, j);
-        rows_to_lanes<2>(scrB, r1, tY, q, j);
-        outer_lanes<BF, 2, 2>(tX, tY, aW2);
-        rows_to_lanes<2>(scrA, e1, tX, q, j);
-        rows_to_lanes<1>(scrB, &qv, tY, q, j);
-        outer_lanes<BF, 2, 1>(tX, tY, aW1);
-        const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
-        scatter<true, true>(A, priv, stage, lane, q, j, ls, valid, dzl, al, gv);
-      } else {
-        const float al[4] = {0, 0, 0, 0};
-        scatter<true, false>(A, priv, stage, lane, q, j, ls, valid, dzl, al, gv);
-      }
-    } else {
-      // smoothness pair: d|g(x) - g(x+eps)|^2 / dg at either point is
-      // 2 (own gradient - partner's gradient); smooth_coef carries the 2.
-      const bool pv = valid && __shfl_xor((int)valid, 8, 64);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const float d = gx[a] - __shfl_xor(gx[a], 8, 64);
-        gv[a] = pv ? A.smooth_coef * d : 0.f;
-      }
-      v4f qv;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) qv[k] = gv[0] * G[k][0] + gv[1] * G[k][1] + gv[2] * G[k][2];
-      v4f r1[2], w2r1[2];
-      layer<BF, 2, 1>(sm, T_L1, &qv, r1, lane);
-#pragma unroll
-      for (int b = 0; b < 2; ++b) r1[b] = relu_mask(r1[b], h1[b]);
-      layer<BF, 2, 2>(sm, T_L2, r1, w2r1, lane);
-#pragma unroll
-      for (int b = 0; b < 2; ++b) w2r1[b] = relu_mask(w2r1[b], h2[b]);
-      float4 tX[2], tY[2];
-      rows_to_lanes<2>(scrA, w2r1, tX, q, j);
-      colsum_into(tX[0], 6, aS, j);
-      colsum_into(tX[1], 7, aS, j);
-      rows_to_lanes<2>(scrA, e2, tX, q, j);
-      rows_to_lanes<2>(scrB, r1, tY, q, j);
-      outer_lanes<BF, 2, 2>(tX, tY, aW2);
-      rows_to_lanes<2>(scrA, e1, tX, q, j);
-      rows_to_lanes<1>(scrB, &qv, tY, q, j);
-      outer_lanes<BF, 2, 1>(tX, tY, aW1);
-      const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
-      const float dzl[4] = {0, 0, 0, 0};
-      scatter<false, true>(A, priv, stage, lane, q, j, ls, pv, dzl, al, gv);
-    }
+    if (tile < n_pair_tiles)
+      field_tile<1, BWD, BF>(A, sm, tile, total, lane, q, j, scrA, scrB, stage, priv, aW1, aW2, aW3, aU1, aS,
+                             smooth_acc);
+    else
+      field_tile<0, BWD, BF>(A, sm, tile - n_pair_tiles, total, lane, q, j, scrA, scrB, stage, priv, aW1, aW2, aW3,
+                             aU1, aS, smooth_acc);
   }
 
-  if (!BWD) {
-    if (MODE == 1) {
+  if constexpr (!BWD) {
+    if (A.S > 0) {
       // block partial of the smoothness sum (fixed order: lanes, then waves)
       float v = wave_sum(smooth_acc);
       __syncthreads();
@@ -602,8 +620,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
 }
 
-int field_blocks(int n_items, int per_tile) {
-  const int tiles = (n_items + per_tile - 1) / per_tile;
+// blocks of a field launch over `total` ray samples (16 per tile) and `pairs`
+// smoothness pairs (8 per tile); at most 1024 (the workspace's partial rows)
+int field_blocks(int total, int pairs) {
+  const int tiles = (total + 15) / 16 + (pairs + 7) / 8;
   int blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 1024) blocks = 1024;
   return blocks < 1 ? 1 : blocks;
@@ -666,30 +686,20 @@ void plan_privatised_levels(FieldArgs& a, int counts[4]) {
 
 int priv_max_floats() { return kPrivMaxFloats; }
 
-hipError_t launch_field(const FieldArgs& a, int mode, bool bwd, int blocks, hipStream_t st) {
-  const bool bf = a.grid_bf16 != nullptr;
-  const size_t smem = (size_t)(bf ? smem_bytes<true>() : smem_bytes<false>()) +
-                      (bwd ? (size_t)a.priv_floats * sizeof(float) : 0);
-  const dim3 g(blocks), b(kBlock);
-#define GS_LAUNCH(M, B, F)                                                                              \
-  do {                                                                                                   \
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<M, B, F>),                           \
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);                          \
-    hipLaunchKernelGGL((field_kernel<M, B, F>), g, b, smem, st, a);                                      \
-  } while (0)
-  if (!bf) {
-    if (mode == 0 && !bwd) GS_LAUNCH(0, false, false);
-    else if (mode == 0) GS_LAUNCH(0, true, false);
-    else if (!bwd) GS_LAUNCH(1, false, false);
-    else GS_LAUNCH(1, true, false);
-  } else {
-    if (mode == 0 && !bwd) GS_LAUNCH(0, false, true);
-    else if (mode == 0) GS_LAUNCH(0, true, true);
-    else if (!bwd) GS_LAUNCH(1, false, true);
-    else GS_LAUNCH(1, true, true);
-  }
-#undef GS_LAUNCH
+template <bool BWD, bool BF>
+static hipError_t launch_field_t(const FieldArgs& a, int blocks, hipStream_t st) {
+  const size_t smem = (size_t)smem_bytes<BF, BWD>() + (BWD ? (size_t)a.priv_floats * sizeof(float) : 0);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<BWD, BF>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((field_kernel<BWD, BF>), dim3(blocks), dim3(kBlock), smem, st, a);
   return hipGetLastError();
+}
+
+hipError_t launch_field(const FieldArgs& a, bool bwd, int blocks, hipStream_t st) {
+  const bool bf = a.grid_bf16 != nullptr;
+  if (bwd) return bf ? launch_field_t<true, true>(a, blocks, st) : launch_field_t<true, false>(a, blocks, st);
+  return bf ? launch_field_t<false, true>(a, blocks, st) : launch_field_t<false, false>(a, blocks, st);
 }
 
 }  // namespace gs

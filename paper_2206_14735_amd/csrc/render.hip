@@ -394,42 +394,75 @@ hipError_t launch_colsum(const float* part, int rows, int cols, float* tmp, floa
 }
 
 // ---------------------------------------------------------------- Adam
-__global__ __launch_bounds__(256) void adam_kernel(float4* __restrict__ gp, float4* __restrict__ gg,
-                                                   float4* __restrict__ gm, float4* __restrict__ gv,
-                                                   uint2* __restrict__ gbf, long long n4g,
-                                                   float4* __restrict__ mp, float4* __restrict__ mg,
-                                                   float4* __restrict__ mm, float4* __restrict__ mv,
-                                                   int n4m, float lr_g, float lr_m, float b1, float b2,
-                                                   float eps, float inv_bc1, float inv_sqrt_bc2,
-                                                   float inv_scale) {
-  const long long n4 = n4g + n4m;
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
-    const bool isg = i < n4g;
-    const long long k = isg ? i : i - n4g;
-    float4* P = isg ? gp : mp;
-    float4* Gr = isg ? gg : mg;
-    float4* Mo = isg ? gm : mm;
-    float4* Vo = isg ? gv : mv;
-    const float lr = isg ? lr_g : lr_m;
-    float4 p = P[k], g = Gr[k], m = Mo[k], v = Vo[k];
-    float pa[4] = {p.x, p.y, p.z, p.w}, ga[4] = {g.x, g.y, g.z, g.w};
-    float ma[4] = {m.x, m.y, m.z, m.w}, va[4] = {v.x, v.y, v.z, v.w};
+// Streaming accesses: every parameter, gradient and moment is touched once
+// per step, so the loads and stores bypass the caches' retention (non-temporal).
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_stream(const float4* a) {
+  const f4v x = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(a));
+  return make_float4(x[0], x[1], x[2], x[3]);
+}
+__device__ __forceinline__ void st_stream(float4 v, float4* a) {
+  const f4v x = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(a));
+}
+
+struct AdamGroup {
+  float4* p;
+  float4* g;
+  float4* m;
+  float4* v;
+  uint2* bf;   // optional bfloat16 mirror of p (4 values per entry)
+  long long n4;
+  float lr;
+};
+
+// Two float4 per thread and pass, both loaded before either is updated.  The
+// grid group comes first in the flattened index, then the decoder group.
+constexpr int kAdamUnroll = 2;
+__global__ __launch_bounds__(256) void adam_kernel(AdamGroup G0, AdamGroup G1, float b1, float b2, float eps,
+                                                   float inv_bc1, float inv_sqrt_bc2, float inv_scale) {
+  const long long n4 = G0.n4 + G1.n4;
+  const long long stride = (long long)gridDim.x * 256 * kAdamUnroll;
+  for (long long base = (long long)blockIdx.x * 256 * kAdamUnroll + threadIdx.x; base < n4; base += stride) {
+    float4 p[kAdamUnroll], g[kAdamUnroll], m[kAdamUnroll], v[kAdamUnroll];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const float gg_ = ga[c] * inv_scale;
-      ma[c] = b1 * ma[c] + (1.f - b1) * gg_;
-      va[c] = b2 * va[c] + (1.f - b2) * gg_ * gg_;
-      const float den = sqrtf(va[c]) * inv_sqrt_bc2 + eps;
-      pa[c] -= lr * (ma[c] * inv_bc1) / den;
+    for (int u = 0; u < kAdamUnroll; ++u) {
+      const long long i = base + (long long)u * 256;
+      if (i < n4) {
+        const AdamGroup& Gr = i < G0.n4 ? G0 : G1;
+        const long long k = i < G0.n4 ? i : i - G0.n4;
+        p[u] = ld_stream(Gr.p + k);
+        g[u] = ld_stream(Gr.g + k);
+        m[u] = ld_stream(Gr.m + k);
+        v[u] = ld_stream(Gr.v + k);
+      }
     }
-    P[k] = make_float4(pa[0], pa[1], pa[2], pa[3]);
-    Mo[k] = make_float4(ma[0], ma[1], ma[2], ma[3]);
-    Vo[k] = make_float4(va[0], va[1], va[2], va[3]);
-    Gr[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (isg && gbf) {
-      const uint32_t lo = (uint32_t)f2bf(pa[0]) | ((uint32_t)f2bf(pa[1]) << 16);
-      const uint32_t hi = (uint32_t)f2bf(pa[2]) | ((uint32_t)f2bf(pa[3]) << 16);
-      gbf[k] = make_uint2(lo, hi);
+#pragma unroll
+    for (int u = 0; u < kAdamUnroll; ++u) {
+      const long long i = base + (long long)u * 256;
+      if (i < n4) {
+        const AdamGroup& Gr = i < G0.n4 ? G0 : G1;
+        const long long k = i < G0.n4 ? i : i - G0.n4;
+        float pa[4] = {p[u].x, p[u].y, p[u].z, p[u].w}, ga[4] = {g[u].x, g[u].y, g[u].z, g[u].w};
+        float ma[4] = {m[u].x, m[u].y, m[u].z, m[u].w}, va[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float gs_ = ga[c] * inv_scale;
+          ma[c] = b1 * ma[c] + (1.f - b1) * gs_;
+          va[c] = b2 * va[c] + (1.f - b2) * gs_ * gs_;
+          const float den = sqrtf(va[c]) * inv_sqrt_bc2 + eps;
+          pa[c] -= Gr.lr * (ma[c] * inv_bc1) / den;
+        }
+        st_stream(make_float4(pa[0], pa[1], pa[2], pa[3]), Gr.p + k);
+        st_stream(make_float4(ma[0], ma[1], ma[2], ma[3]), Gr.m + k);
+        st_stream(make_float4(va[0], va[1], va[2], va[3]), Gr.v + k);
+        st_stream(make_float4(0.f, 0.f, 0.f, 0.f), Gr.g + k);
+        if (Gr.bf) {
+          const uint32_t lo = (uint32_t)f2bf(pa[0]) | ((uint32_t)f2bf(pa[1]) << 16);
+          const uint32_t hi = (uint32_t)f2bf(pa[2]) | ((uint32_t)f2bf(pa[3]) << 16);
+          Gr.bf[k] = make_uint2(lo, hi);
+        }
+      }
     }
   }
 }
@@ -486,16 +519,18 @@ hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream
   const int tail = s.mlp_numel - 4 * n4m;
   const double bc1 = 1.0 - pow((double)c.beta1, (double)c.step);
   const double bc2 = 1.0 - pow((double)c.beta2, (double)c.step);
-  long long blocks = (n4g + n4m + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  const AdamGroup G0{reinterpret_cast<float4*>(s.grid), reinterpret_cast<float4*>(s.grid_grad),
+                     reinterpret_cast<float4*>(s.grid_m), reinterpret_cast<float4*>(s.grid_v),
+                     reinterpret_cast<uint2*>(s.grid_bf16), n4g, c.lr_grid};
+  const AdamGroup G1{reinterpret_cast<float4*>(s.mlp), reinterpret_cast<float4*>(s.mlp_grad),
+                     reinterpret_cast<float4*>(s.mlp_m), reinterpret_cast<float4*>(s.mlp_v), nullptr, n4m, c.lr_mlp};
+  // one pass: each thread takes kAdamUnroll float4 (the loop covers larger sizes)
+  long long blocks = (n4g + n4m + 256 * kAdamUnroll - 1) / (256 * kAdamUnroll);
+  if (blocks > (1 << 20)) blocks = 1 << 20;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<float4*>(s.grid),
-                     reinterpret_cast<float4*>(s.grid_grad), reinterpret_cast<float4*>(s.grid_m),
-                     reinterpret_cast<float4*>(s.grid_v), reinterpret_cast<uint2*>(s.grid_bf16), n4g,
-                     reinterpret_cast<float4*>(s.mlp), reinterpret_cast<float4*>(s.mlp_grad),
-                     reinterpret_cast<float4*>(s.mlp_m), reinterpret_cast<float4*>(s.mlp_v), n4m, c.lr_grid,
-                     c.lr_mlp, c.beta1, c.beta2, c.eps, (float)(1.0 / bc1), (float)(1.0 / sqrt(bc2)),
-                     c.inv_loss_scale);
+  if (n4g + n4m > 0)
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, st, G0, G1, c.beta1, c.beta2, c.eps,
+                       (float)(1.0 / bc1), (float)(1.0 / sqrt(bc2)), c.inv_loss_scale);
   if (tail > 0) {
     const size_t o = 4 * (size_t)n4m;
     hipLaunchKernelGGL(adam_tail_kernel, dim3(1), dim3(64), 0, st, s.mlp + o, s.mlp_grad + o, s.mlp_m + o,

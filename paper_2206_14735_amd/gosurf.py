@@ -396,7 +396,7 @@ def gosurf_refresh_bf16(grid, grid_bf16, stream=None):
                                                             _stream(stream)))
 
 
-KERNEL_FIELD_FWD, KERNEL_FIELD_BWD, KERNEL_SMOOTH_BWD, KERNEL_ADAM = 1, 2, 3, 4
+KERNEL_FIELD_FWD, KERNEL_FIELD_BWD, KERNEL_ADAM = 1, 2, 4
 
 
 def gosurf_time_kernel(kernel, start=None, stop=None):
