@@ -121,6 +121,18 @@ __device__ __forceinline__ float dpp_f(float v) {
 constexpr int kRowShl1 = 0x101, kRowShl2 = 0x102, kRowShl4 = 0x104, kRowShl8 = 0x108;  // lane j <- j + d
 constexpr int kRowShr1 = 0x111;                                                        // lane j <- j - 1
 
+// Float atomics with the address space stated: a generic (flat) atomic would
+// also count against the LDS wait counter, so every LDS fence after a scatter
+// would wait for the scatter's atomics in memory.
+typedef __attribute__((address_space(1))) float global_float;
+typedef __attribute__((address_space(3))) float lds_float;
+__device__ __forceinline__ void atomic_add_global(float* p, float v) {
+  __hip_atomic_fetch_add((global_float*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_add_lds(float* p, float v) {
+  __hip_atomic_fetch_add((lds_float*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -184,9 +184,9 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const S
       if ((A.priv_mask >> lq) & 1) {
         const int po = lq == 0 ? A.priv_off[0] : lq == 1 ? A.priv_off[1] : lq == 2 ? A.priv_off[2] : A.priv_off[3];
         const long long go = lq == 0 ? A.g.off[0] : lq == 1 ? A.g.off[1] : lq == 2 ? A.g.off[2] : A.g.off[3];
-        atomicAdd(priv + po + (int)(row - go) * 4 + f, v);
+        atomic_add_lds(priv + po + (int)(row - go) * 4 + f, v);
       } else {
-        atomicAdd(A.grad_grid + row * 4 + f, v);
+        atomic_add_global(A.grad_grid + row * 4 + f, v);
       }
     }
   }
