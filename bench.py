@@ -9,7 +9,9 @@ device before timing; the timed region contains only library calls.
 
 Prints one JSON line: ray-samples/s (rays x samples per ray / step time),
 the roofline of the dominant kernel measured with HIP events on the launch
-stream, and the FP64 oracle timed on a bounded sample on the host cores.
+stream, the FP64 oracle timed on a bounded sample on the host cores, and a
+comparison of plain FP32 steps with BF16 + learned-proposal steps at 65536
+rays on the same trained field (iterations/s and rendered depth error).
 """
 import argparse
 import json
@@ -36,6 +38,11 @@ def parse():
     ap.add_argument("--cpu-rays", type=int, default=512)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for memory counters)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain FP32 vs BF16 + proposal comparison")
+    ap.add_argument("--compare-pretrain", type=int, default=3000,
+                    help="plain steps that train the field before the comparison")
+    ap.add_argument("--compare-steps", type=int, default=10, help="timed steps of each compared variant")
     return ap.parse_args()
 
 
@@ -104,6 +111,111 @@ def cpu_baseline(w, frames_cpu, grid, mlp, n_rays):
             "sample": f"{n_rays} rays x {w.n_samples} samples + {S} smoothness pairs fwd+bwd over the full "
                       f"grid ({t_fb:.1f} s), scaled by {w.M}/{n_rays}, plus one dense Adam step over all "
                       f"{grid.numel() + mlp.numel()} parameters ({t_adam:.1f} s)"}
+
+
+def compare(a, G, synth, Reconstruction, torch):
+    """Plain FP32 against BF16 + learned proposal at the proposal workload's
+    batch (65536 rays): the same trained field, iterations/s of whole steps
+    and the rendered depth error of each against the noise-free depth.
+
+    The field is trained by plain FP32 steps (6144 rays x (64 + 32)); about
+    49k rays' weight distributions are then logged and the proposal trained
+    on them; plain rays get 64 + 32 samples, confident proposal rays 24 in the
+    predicted interval and the others the plain 96."""
+    from paper_2206_14735_amd.proposal import ProposalLog, ProposalTrainer
+    wp = synth.configs.ROOM_PROPOSAL
+    lay = wp.layout()
+    t0 = time.time()
+    frames, _ = synth.room_frames(wp.n_frames, H=wp.H, W=wp.W, f=wp.f, seed=1, device="cuda")
+    torch.cuda.synchronize()
+    print(f"# compare: {wp.n_frames} frames in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    span = G.SPAN_BOX
+    base = Reconstruction(lay, frames, 64, 32, 6144, 16384, span, wp.near, wp.far, wp.trunc, seed=0)
+    t0 = time.time()
+    for _ in range(a.compare_pretrain):
+        base.step()
+    torch.cuda.synchronize()
+    print(f"# compare: {a.compare_pretrain} plain steps in {time.time() - t0:.1f} s, losses {base.losses()}",
+          file=sys.stderr, flush=True)
+    logger = Reconstruction(lay, frames, 64, 32, 4096, 0, span, wp.near, wp.far, wp.trunc, seed=7,
+                            grid=base.grid.clone(), mlp=base.mlp.clone())
+    log = ProposalLog()
+    for k in range(12):
+        logger.it = 50_000 + k
+        logger.sample()
+        log.add(logger, widen=0.05)
+    del logger
+    trainer = ProposalTrainer(base.model, base.cfg, synth.init_proposal(1), lr=3e-3, batch=8192, cover_tol=0.02)
+    t0 = time.time()
+    ploss = trainer.fit(base.grid, log, steps=12000)
+    torch.cuda.synchronize()
+    print(f"# compare: proposal trained on {log.tensors()[0].shape[0]} rays in {time.time() - t0:.1f} s "
+          f"(loss {ploss:.4f})", file=sys.stderr, flush=True)
+
+    M, S = wp.M, wp.S
+    n_prop = wp.extra["proposal_samples"]
+    thr = wp.extra["conf_threshold"]
+    dgt = frames.depth_gt.reshape(-1)
+
+    def make(bf16, proposal):
+        rec = Reconstruction(lay, frames, 64, 32, M, S, span, wp.near, wp.far, wp.trunc, seed=3,
+                             precision=G.BF16 if bf16 else G.FP32, loss_scale=wp.loss_scale if bf16 else 1.0,
+                             grid=base.grid.clone(), mlp=base.mlp.clone())
+        rec.it = base.it
+        if proposal is not None:
+            rec.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr)
+        return rec
+
+    def depth_error(rec, n_batches=4):
+        errs, samples, conf = [], [], []
+        saved_it = rec.it
+        for k in range(n_batches):
+            rec.it = 200_000 + k
+            rec.sample()
+            rec.forward()
+            ok = rec.batch.depth > 0
+            errs.append((rec.fwd.depth_hat[ok] - dgt[rec.batch.pixel][ok]).abs())
+            samples.append(rec.batch.n_samples() / M)
+            if rec.batch.prop is not None:
+                conf.append((rec.batch.prop[:, 2] >= thr).float().mean().item())
+        rec.it = saved_it
+        e = torch.cat(errs)
+        out = {"mean": round(1e3 * e.mean().item(), 3), "median": round(1e3 * e.median().item(), 3)}
+        return out, float(sum(samples) / len(samples)), (float(sum(conf) / len(conf)) if conf else None)
+
+    def timed(rec, steps, warmup=3):
+        for _ in range(warmup):
+            rec.step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            rec.step()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / steps
+
+    res = {}
+    for name, bf16, prop in (("plain_fp32", False, None), ("bf16_proposal", True, trainer.prop)):
+        rec = make(bf16, prop)
+        err, spr, conf = depth_error(rec)
+        ms = timed(rec, a.compare_steps)
+        res[name] = {"ms_per_step": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2),
+                     "samples_per_ray": round(spr, 2), "depth_l1_mm": err,
+                     "ray_samples_per_s": round(M * spr / (ms * 1e-3)),
+                     "plain_equivalent_ray_samples_per_s": round(M * 96 / (ms * 1e-3))}
+        if conf is not None:
+            res[name]["confident_fraction"] = round(conf, 4)
+        print(f"# compare {name}: {res[name]}", file=sys.stderr, flush=True)
+        del rec
+        torch.cuda.empty_cache()
+    p, b = res["plain_fp32"], res["bf16_proposal"]
+    return {
+        "workload": f"{wp.name}: {M} rays, plain 64+32 vs proposal {n_prop} (fallback 96 below confidence "
+                    f"{thr}), {S} smoothness pairs, {wp.n_frames} frames {wp.W}x{wp.H}; field trained by "
+                    f"{a.compare_pretrain} plain steps, proposal by 12000 steps on ~49k logged rays",
+        **res,
+        "iterations_speedup": round(p["ms_per_step"] / b["ms_per_step"], 3),
+        "depth_l1_gap_mm": {k: round(b["depth_l1_mm"][k] - p["depth_l1_mm"][k], 3) for k in ("mean", "median")},
+    }
 
 
 def main():
@@ -184,6 +296,8 @@ def main():
     print(f"# per kernel (ms): {kern}", file=sys.stderr, flush=True)
 
     n_par = rec.grid.numel() + rec.mlp.numel()
+    losses = rec.losses()
+    grid_numel = rec.grid.numel()
     samples_now = rec.batch.n_samples()
 
     def roofline(name, bytes_per_launch, ms, label):
@@ -223,6 +337,12 @@ def main():
         cpu = cpu_baseline(w, fr_cpu, grid, mlp, a.cpu_rays)
         print(f"# oracle baseline: {cpu['sample']}", file=sys.stderr, flush=True)
 
+    comparison = None
+    if not a.no_compare:
+        del rec
+        torch.cuda.empty_cache()
+        comparison = compare(a, G, synth, Reconstruction, torch)
+
     samples = w.M * w.n_samples
     out = {
         "metric": "ray-samples/s per fwd+bwd step, plain FP32 vs BF16+proposal at equal depth L1",
@@ -234,14 +354,15 @@ def main():
                                f"pairs, grid {'/'.join(str(v) for v in sorted(w.voxels))} m "
                                f"({n_par / 1e6:.2f} M params), {n_frames} frames {w.W}x{w.H}, {w.precision}",
                    "rays": w.M, "samples_per_ray": w.n_samples, "smoothness_pairs": w.S,
-                   "grid_params": rec.grid.numel(), "frames": n_frames},
+                   "grid_params": grid_numel, "frames": n_frames},
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
         "per_kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "roofline": roof,
         "other_rooflines": {k: v for k, v in roofs.items() if k != dominant},
         "source_digest": source_digest(),
         "cpu_baseline": cpu,
-        "losses": rec.losses(),
+        "losses": losses,
+        "comparison": comparison,
     }
     print(json.dumps(out), flush=True)
 
