@@ -495,10 +495,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   if constexpr (BF) {
     for (int e = tid; e < (T_END / 4) * 64; e += kBlock) {
       const int slot = e >> 6, l = e & 63;
-      const uint32_t lo = (uint32_t)f2bf(table_value(A.mlp, 4 * slot + 0, l)) |
-                          ((uint32_t)f2bf(table_value(A.mlp, 4 * slot + 1, l)) << 16);
-      const uint32_t hi = (uint32_t)f2bf(table_value(A.mlp, 4 * slot + 2, l)) |
-                          ((uint32_t)f2bf(table_value(A.mlp, 4 * slot + 3, l)) << 16);
+      const uint32_t lo = f2bf2(table_value(A.mlp, 4 * slot + 0, l), table_value(A.mlp, 4 * slot + 1, l));
+      const uint32_t hi = f2bf2(table_value(A.mlp, 4 * slot + 2, l), table_value(A.mlp, 4 * slot + 3, l));
       sm.tabbf[e] = make_uint2(lo, hi);
     }
   } else {

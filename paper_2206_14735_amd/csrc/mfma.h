@@ -5,10 +5,12 @@
 namespace gs {
 
 __device__ __forceinline__ v4s pack_bf16(v4f x) {
-  return v4s{(short)f2bf(x[0]), (short)f2bf(x[1]), (short)f2bf(x[2]), (short)f2bf(x[3])};
+  const uint2 u = make_uint2(f2bf2(x[0], x[1]), f2bf2(x[2], x[3]));
+  return __builtin_bit_cast(v4s, u);
 }
 __device__ __forceinline__ v4s pack_bf16(float4 x) {
-  return v4s{(short)f2bf(x.x), (short)f2bf(x.y), (short)f2bf(x.z), (short)f2bf(x.w)};
+  const uint2 u = make_uint2(f2bf2(x.x, x.y), f2bf2(x.z, x.w));
+  return __builtin_bit_cast(v4s, u);
 }
 __device__ __forceinline__ v4s as_v4s(uint2 u) {
   v4s r;

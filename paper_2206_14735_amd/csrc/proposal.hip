@@ -323,27 +323,49 @@ __global__ __launch_bounds__(256) void proposal_targets_kernel(TargetArgs A) {
 }
 
 // samples per ray from the confidences, and their exclusive prefix sum (one block)
+// Segment offsets of the proposal-driven batch: ray m gets n_prop samples if
+// its confidence reaches thr, else n_plain.  One block scans chunks of 8192
+// rays: lengths are read coalesced into LDS, each thread sums 8 consecutive
+// rays, the 1024 partial sums are scanned in LDS, and the offsets go back out
+// coalesced; a running carry links the chunks.
+constexpr int kSegChunk = 8192;
 __global__ __launch_bounds__(1024) void proposal_seg_kernel(const float* __restrict__ prop3, int M, float thr,
                                                             int n_prop, int n_plain, int* __restrict__ seg) {
+  __shared__ int len[kSegChunk];
   __shared__ int part[1024];
-  const int per = (M + 1023) / 1024;
-  const int b0 = threadIdx.x * per;
-  int s = 0;
-  for (int m = b0; m < b0 + per && m < M; ++m) s += prop3[3 * m + 2] >= thr ? n_prop : n_plain;
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+  const int tid = threadIdx.x;
+  constexpr int per = kSegChunk / 1024;
+  int carry = 0;
+  for (int c0 = 0; c0 < M; c0 += kSegChunk) {
+    const int n = min(kSegChunk, M - c0);
+    for (int m = tid; m < kSegChunk; m += 1024)
+      len[m] = m < n ? (prop3[3 * (size_t)(c0 + m) + 2] >= thr ? n_prop : n_plain) : 0;
     __syncthreads();
-    part[threadIdx.x] += v;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) s += len[tid * per + k];
+    part[tid] = s;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int v = tid >= d ? part[tid - d] : 0;
+      __syncthreads();
+      part[tid] += v;
+      __syncthreads();
+    }
+    int run = carry + part[tid] - s;   // exclusive prefix of this thread's first ray
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+      const int l = len[tid * per + k];
+      len[tid * per + k] = run;
+      run += l;
+    }
+    const int chunk_total = part[1023];
+    __syncthreads();
+    for (int m = tid; m < n; m += 1024) seg[c0 + m] = len[m];
+    carry += chunk_total;
     __syncthreads();
   }
-  int run = part[threadIdx.x] - s;
-  for (int m = b0; m < b0 + per && m < M; ++m) {
-    seg[m] = run;
-    run += prop3[3 * m + 2] >= thr ? n_prop : n_plain;
-  }
-  if (threadIdx.x == 1023) seg[M] = part[1023];
+  if (tid == 0) seg[M] = carry;
 }
 
 int proposal_blocks(int M) {

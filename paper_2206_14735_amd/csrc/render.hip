@@ -458,8 +458,8 @@ __global__ __launch_bounds__(256) void adam_kernel(AdamGroup G0, AdamGroup G1, f
         st_stream(make_float4(va[0], va[1], va[2], va[3]), Gr.v + k);
         st_stream(make_float4(0.f, 0.f, 0.f, 0.f), Gr.g + k);
         if (Gr.bf) {
-          const uint32_t lo = (uint32_t)f2bf(pa[0]) | ((uint32_t)f2bf(pa[1]) << 16);
-          const uint32_t hi = (uint32_t)f2bf(pa[2]) | ((uint32_t)f2bf(pa[3]) << 16);
+          const uint32_t lo = f2bf2(pa[0], pa[1]);
+          const uint32_t hi = f2bf2(pa[2], pa[3]);
           Gr.bf[k] = make_uint2(lo, hi);
         }
       }
@@ -485,8 +485,7 @@ __global__ __launch_bounds__(256) void to_bf16_kernel(const float4* __restrict__
                                                       long long n4) {
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
     const float4 v = src[i];
-    dst[i] = make_uint2((uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16),
-                        (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16));
+    dst[i] = make_uint2(f2bf2(v.x, v.y), f2bf2(v.z, v.w));
   }
 }
 

@@ -53,8 +53,8 @@ struct UniformStream {
 
 // One wave per ray.  Every sample value is computed by one lane; its place
 // in the merged order is its index in its own list plus the number of values
-// of the other list that precede it (stratified first on ties), counted with
-// the same float32 values on every lane, so the ranks form a permutation.
+// of the other list that precede it (stratified first on ties), counted on the
+// same float32 values by every lane, so the ranks form a permutation.
 // RAY: pick the pixel and write the ray; GEN: write the ray's samples (with a
 // proposal, confident rays get n_prop stratified samples in [near, far] and
 // their first sample comes from the precomputed seg).
@@ -114,22 +114,42 @@ __global__ __launch_bounds__(256) void sample_rays_kernel(SampleArgs A) {
       bv[c] = lo + ((float)i + u01(x)) * dn;
     }
   }
-  // ranks: stratified value a_i precedes near value b_j iff a_i <= b_j
+  // ranks: stratified value a_i precedes near value b_j iff a_i <= b_j.  Both
+  // lists are non-decreasing in float32 (each value is a monotone rounding of
+  // an increasing exact value), so a binary search over the other list in LDS
+  // gives the same counts as comparing with every value.
   int ra[kChunks], rb[kChunks];
+  __shared__ float lists[4][2][kChunks * 64];   // per wave: the ray's two lists
+  float* la = lists[threadIdx.x >> 6][0];
+  float* lb = lists[threadIdx.x >> 6][1];
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) { ra[c] = 64 * c + lane; rb[c] = 64 * c + lane; }
+  for (int c = 0; c < kChunks; ++c) {
+    const int i = 64 * c + lane;
+    if (i < ns) la[i] = av[c];
+    if (i < nn) lb[i] = bv[c];
+  }
+  wave_lds_fence();
 #pragma unroll
-  for (int c2 = 0; c2 < kChunks; ++c2) {
-    const int cnt_b = nn - 64 * c2, cnt_a = (nn > 0 ? ns : 0) - 64 * c2;
-    for (int l2 = 0; l2 < (cnt_b < 64 ? cnt_b : 64); ++l2) {
-      const float b = __shfl(bv[c2], l2, 64);
-#pragma unroll
-      for (int c = 0; c < kChunks; ++c) ra[c] += (b < av[c]) ? 1 : 0;
+  for (int c = 0; c < kChunks; ++c) {
+    const int i = 64 * c + lane;
+    ra[c] = rb[c] = i;
+    if (i < ns) {   // near values strictly below a_i
+      int lo_ = 0, hi_ = nn;
+      while (lo_ < hi_) {
+        const int mid = (lo_ + hi_) >> 1;
+        if (lb[mid] < av[c]) lo_ = mid + 1;
+        else hi_ = mid;
+      }
+      ra[c] += lo_;
     }
-    for (int l2 = 0; l2 < (cnt_a < 64 ? cnt_a : 64); ++l2) {
-      const float a = __shfl(av[c2], l2, 64);
-#pragma unroll
-      for (int c = 0; c < kChunks; ++c) rb[c] += (a <= bv[c]) ? 1 : 0;
+    if (i < nn) {   // stratified values at or below b_j
+      int lo_ = 0, hi_ = ns;
+      while (lo_ < hi_) {
+        const int mid = (lo_ + hi_) >> 1;
+        if (la[mid] <= bv[c]) lo_ = mid + 1;
+        else hi_ = mid;
+      }
+      rb[c] += lo_;
     }
   }
 #pragma unroll
