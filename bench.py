@@ -40,9 +40,9 @@ def parse():
                     help="also run one plain 1 GiB device copy (reference for memory counters)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP32 vs BF16 + proposal comparison")
-    ap.add_argument("--compare-pretrain", type=int, default=3000,
-                    help="plain steps that train the field before the comparison")
-    ap.add_argument("--compare-steps", type=int, default=10, help="timed steps of each compared variant")
+    ap.add_argument("--compare-phase1", type=int, default=300,
+                    help="shared plain FP32 steps (65536 rays) before the two continuations")
+    ap.add_argument("--compare-phase2", type=int, default=300, help="steps of each continuation (timed)")
     return ap.parse_args()
 
 
@@ -114,107 +114,161 @@ def cpu_baseline(w, frames_cpu, grid, mlp, n_rays):
 
 
 def compare(a, G, synth, Reconstruction, torch):
-    """Plain FP32 against BF16 + learned proposal at the proposal workload's
-    batch (65536 rays): the same trained field, iterations/s of whole steps
-    and the rendered depth error of each against the noise-free depth.
+    """Plain FP32 against BF16 + learned proposal on the proposal workload
+    (65536 rays per step, 2000 frames).
 
-    The field is trained by plain FP32 steps (6144 rays x (64 + 32)); about
-    49k rays' weight distributions are then logged and the proposal trained
-    on them; plain rays get 64 + 32 samples, confident proposal rays 24 in the
-    predicted interval and the others the plain 96."""
+    Protocol: plain FP32 steps train the field (phase 1); about 49k rays'
+    weight distributions are logged from it and the proposal is trained on
+    them; then the same state continues for the same number of steps once
+    with plain FP32 steps and once with BF16 + proposal steps (confident rays:
+    24 samples in the predicted interval, the others the plain 64 + 32).
+    Reported: iterations/s of the two continuations, the depth error of the
+    two resulting fields rendered by the same plain FP32 renderer (the
+    reconstruction error the proposal adds), and the depth error of the
+    proposal-sampled render itself."""
     from paper_2206_14735_amd.proposal import ProposalLog, ProposalTrainer
     wp = synth.configs.ROOM_PROPOSAL
     lay = wp.layout()
+    M, S = wp.M, wp.S
+    n_prop = wp.extra["proposal_samples"]
+    n_free = wp.extra["free_samples"]
+    depth_check = wp.extra["depth_check"]
+    thr = wp.extra["conf_threshold"]
+    cover_tol = wp.extra["cover_tol"]
+    span = G.SPAN_BOX
     t0 = time.time()
     frames, _ = synth.room_frames(wp.n_frames, H=wp.H, W=wp.W, f=wp.f, seed=1, device="cuda")
     torch.cuda.synchronize()
     print(f"# compare: {wp.n_frames} frames in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    span = G.SPAN_BOX
-    base = Reconstruction(lay, frames, 64, 32, 6144, 16384, span, wp.near, wp.far, wp.trunc, seed=0)
+    dgt = frames.depth_gt.reshape(-1)
+
+    def new_rec(bf16, seed, src=None):
+        rec = Reconstruction(lay, frames, 64, 32, M, S, span, wp.near, wp.far, wp.trunc, seed=seed,
+                             precision=G.BF16 if bf16 else G.FP32, loss_scale=wp.loss_scale if bf16 else 1.0,
+                             grid=None if src is None else src.grid.clone(),
+                             mlp=None if src is None else src.mlp.clone())
+        if src is not None:
+            for n in ("grid_m", "grid_v", "mlp_m", "mlp_v"):
+                getattr(rec, n).copy_(getattr(src, n))
+            rec.it = src.it
+            if bf16:
+                G.gosurf_refresh_bf16(rec.grid, rec.grid_bf16)
+        return rec
+
+    # phase 1: plain FP32 training
+    base = new_rec(False, 0)
     t0 = time.time()
-    for _ in range(a.compare_pretrain):
+    for _ in range(a.compare_phase1):
         base.step()
     torch.cuda.synchronize()
-    print(f"# compare: {a.compare_pretrain} plain steps in {time.time() - t0:.1f} s, losses {base.losses()}",
-          file=sys.stderr, flush=True)
+    print(f"# compare: phase 1, {a.compare_phase1} plain steps in {time.time() - t0:.1f} s, losses "
+          f"{base.losses()}", file=sys.stderr, flush=True)
+
+    # proposal: log weights of plain forwards, train on the device
     logger = Reconstruction(lay, frames, 64, 32, 4096, 0, span, wp.near, wp.far, wp.trunc, seed=7,
-                            grid=base.grid.clone(), mlp=base.mlp.clone())
+                            grid=base.grid, mlp=base.mlp)
     log = ProposalLog()
     for k in range(12):
         logger.it = 50_000 + k
         logger.sample()
         log.add(logger, widen=0.05)
     del logger
-    trainer = ProposalTrainer(base.model, base.cfg, synth.init_proposal(1), lr=3e-3, batch=8192, cover_tol=0.02)
+    trainer = ProposalTrainer(base.model, base.cfg, synth.init_proposal(1), lr=3e-3, batch=8192,
+                              cover_tol=cover_tol)
     t0 = time.time()
     ploss = trainer.fit(base.grid, log, steps=12000)
     torch.cuda.synchronize()
-    print(f"# compare: proposal trained on {log.tensors()[0].shape[0]} rays in {time.time() - t0:.1f} s "
-          f"(loss {ploss:.4f})", file=sys.stderr, flush=True)
+    n_logged = log.tensors()[0].shape[0]
+    print(f"# compare: proposal trained on {n_logged} rays in {time.time() - t0:.1f} s (loss {ploss:.4f})",
+          file=sys.stderr, flush=True)
 
-    M, S = wp.M, wp.S
-    n_prop = wp.extra["proposal_samples"]
-    thr = wp.extra["conf_threshold"]
-    dgt = frames.depth_gt.reshape(-1)
+    evaluator = Reconstruction(lay, frames, 64, 32, M, 0, span, wp.near, wp.far, wp.trunc, seed=11,
+                               grid=base.grid, mlp=base.mlp)
 
-    def make(bf16, proposal):
-        rec = Reconstruction(lay, frames, 64, 32, M, S, span, wp.near, wp.far, wp.trunc, seed=3,
-                             precision=G.BF16 if bf16 else G.FP32, loss_scale=wp.loss_scale if bf16 else 1.0,
-                             grid=base.grid.clone(), mlp=base.mlp.clone())
-        rec.it = base.it
-        if proposal is not None:
-            rec.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr)
-        return rec
-
-    def depth_error(rec, n_batches=4):
-        errs, samples, conf = [], [], []
-        saved_it = rec.it
+    def depth_error(grid, mlp, proposal=None, n_batches=4):
+        """Rendered depth against the noise-free depth on rays with observed depth."""
+        evaluator.grid, evaluator.mlp = grid, mlp
+        evaluator.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr, n_free=n_free,
+                               depth_check=depth_check)
+        errs, spr, conf = [], [], []
         for k in range(n_batches):
-            rec.it = 200_000 + k
-            rec.sample()
-            rec.forward()
-            ok = rec.batch.depth > 0
-            errs.append((rec.fwd.depth_hat[ok] - dgt[rec.batch.pixel][ok]).abs())
-            samples.append(rec.batch.n_samples() / M)
-            if rec.batch.prop is not None:
-                conf.append((rec.batch.prop[:, 2] >= thr).float().mean().item())
-        rec.it = saved_it
+            evaluator.it = 300_000 + k
+            evaluator.sample()
+            evaluator.forward()
+            ok = evaluator.batch.depth > 0
+            errs.append((evaluator.fwd.depth_hat[ok] - dgt[evaluator.batch.pixel][ok]).abs())
+            spr.append(evaluator.batch.n_samples() / M)
+            if proposal is not None:
+                conf.append((evaluator.batch.prop[:, 2] >= thr).float().mean().item())
         e = torch.cat(errs)
-        out = {"mean": round(1e3 * e.mean().item(), 3), "median": round(1e3 * e.median().item(), 3)}
-        return out, float(sum(samples) / len(samples)), (float(sum(conf) / len(conf)) if conf else None)
+        out = {"depth_l1_mm": {"mean": round(1e3 * e.mean().item(), 3), "median": round(1e3 * e.median().item(), 3)},
+               "samples_per_ray": round(sum(spr) / len(spr), 2)}
+        if conf:
+            out["confident_fraction"] = round(sum(conf) / len(conf), 4)
+        return out
 
-    def timed(rec, steps, warmup=3):
-        for _ in range(warmup):
+    def run(rec, steps):
+        for _ in range(3):
             rec.step()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(steps):
+        spr = 0.0
+        for k in range(steps):
             rec.step()
         torch.cuda.synchronize()
-        return 1e3 * (time.perf_counter() - t) / steps
+        ms = 1e3 * (time.perf_counter() - t) / steps
+        # per-call split over a few further steps (HIP events on the launch stream)
+        st = torch.cuda.current_stream()
+        names = ("sample_rays", "forward", "backward", "adam_step")
+        acc = dict.fromkeys(names, 0.0)
+        n = 5
+        for _ in range(n):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record(st)
+            rec.sample()
+            ev[1].record(st)
+            rec.forward()
+            ev[2].record(st)
+            spr += rec.batch.n_samples() / M
+            rec.backward()
+            ev[3].record(st)
+            rec.adam()
+            ev[4].record(st)
+            rec.it += 1
+            torch.cuda.synchronize()
+            for i, nm in enumerate(names):
+                acc[nm] += ev[i].elapsed_time(ev[i + 1]) / n
+        return ms, {k: round(v, 4) for k, v in acc.items()}, spr / n
 
     res = {}
     for name, bf16, prop in (("plain_fp32", False, None), ("bf16_proposal", True, trainer.prop)):
-        rec = make(bf16, prop)
-        err, spr, conf = depth_error(rec)
-        ms = timed(rec, a.compare_steps)
-        res[name] = {"ms_per_step": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2),
-                     "samples_per_ray": round(spr, 2), "depth_l1_mm": err,
-                     "ray_samples_per_s": round(M * spr / (ms * 1e-3)),
-                     "plain_equivalent_ray_samples_per_s": round(M * 96 / (ms * 1e-3))}
-        if conf is not None:
-            res[name]["confident_fraction"] = round(conf, 4)
-        print(f"# compare {name}: {res[name]}", file=sys.stderr, flush=True)
+        rec = new_rec(bf16, 3, base)
+        if prop is not None:
+            rec.use_proposal(prop, n_proposal=n_prop, conf_threshold=thr, n_free=n_free, depth_check=depth_check)
+        t0 = time.time()
+        ms, per_call, spr = run(rec, a.compare_phase2)
+        r = {"ms_per_step": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2), "per_call_ms": per_call,
+             "samples_per_ray": round(spr, 2), "ray_samples_per_s": round(M * spr / (ms * 1e-3)),
+             "plain_equivalent_ray_samples_per_s": round(M * 96 / (ms * 1e-3)),
+             "field": depth_error(rec.grid, rec.mlp)}
+        if prop is not None:
+            r["proposal_render"] = depth_error(rec.grid, rec.mlp, prop)
+        res[name] = r
+        print(f"# compare {name}: {r} ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
         del rec
         torch.cuda.empty_cache()
     p, b = res["plain_fp32"], res["bf16_proposal"]
+    fp, fb = p["field"]["depth_l1_mm"], b["field"]["depth_l1_mm"]
     return {
-        "workload": f"{wp.name}: {M} rays, plain 64+32 vs proposal {n_prop} (fallback 96 below confidence "
-                    f"{thr}), {S} smoothness pairs, {wp.n_frames} frames {wp.W}x{wp.H}; field trained by "
-                    f"{a.compare_pretrain} plain steps, proposal by 12000 steps on ~49k logged rays",
+        "workload": f"{wp.name}: {M} rays per step, plain 64+32 vs proposal {n_prop} in the interval + "
+                    f"{n_free} on the free space before it per confident ray (confidence >= {thr}"
+                    f"{' and the observed depth inside the interval' if depth_check else ''}, else plain "
+                    f"64+32), {S} smoothness pairs, {wp.n_frames} frames "
+                    f"{wp.W}x{wp.H}; {a.compare_phase1} shared plain steps, then {a.compare_phase2} steps of "
+                    f"each; proposal trained for 12000 steps on {n_logged} logged rays",
         **res,
         "iterations_speedup": round(p["ms_per_step"] / b["ms_per_step"], 3),
-        "depth_l1_gap_mm": {k: round(b["depth_l1_mm"][k] - p["depth_l1_mm"][k], 3) for k in ("mean", "median")},
+        "field_depth_l1_gap_mm": {k: round(fb[k] - fp[k], 3) for k in ("mean", "median")},
     }
 
 

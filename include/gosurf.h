@@ -135,12 +135,17 @@ typedef struct {
   /* Learned proposal (optional).  With proposal != NULL each ray first gets
      (near, far, confidence) from the proposal network (see
      gosurf_proposal_forward); rays with confidence >= conf_threshold get
-     n_proposal stratified samples in [near, far], the others fall back to the
-     plain n_strat + n_near samples.  Rays then have different lengths. */
+     n_free stratified samples on [t_lo, near] (the span before the interval,
+     near-depth jitter stream) followed by n_proposal stratified samples in
+     [near, far] (stratified stream); the others fall back to the plain
+     n_strat + n_near samples.  Rays then have different lengths. */
   const float* proposal;   /* [GOSURF_PROPOSAL_NUMEL] network parameters, or NULL */
   const float* grid;       /* float32 grid features read by the proposal (its level 1) */
-  int32_t n_proposal;      /* samples per confident ray (>= 1) */
+  int32_t n_proposal;      /* interval samples per confident ray (>= 1) */
   float conf_threshold;
+  int32_t n_free;          /* free-space samples per confident ray before its interval (>= 0) */
+  int32_t depth_check;     /* nonzero: a ray with observed depth D > 0 keeps its interval only if
+                              near <= D <= far (else plain samples; needs conf_threshold > 0) */
 } gosurf_sample_cfg;
 
 /* A ray batch.  Written by gosurf_sample_rays, read by forward/backward.
@@ -161,7 +166,8 @@ typedef struct {
   float* xs;            /* [S][3] smoothness points */
   float* eps;           /* [S][3] perturbations; the pair is (x, x + eps rounded to float32) */
   int64_t* pixel;       /* [M] flat pixel index of each ray (output only; may be NULL) */
-  float* prop;          /* [M][3] proposal near, far, confidence (written with a proposal) */
+  float* prop;          /* [M][3] proposal near, far, confidence (written with a proposal; the
+                           confidence is negated where the depth check rejected the interval) */
 } gosurf_ray_batch;
 
 /* Loss configuration (Sec. 3.3-3.5 and implementation details). */
@@ -225,7 +231,7 @@ gosurf_status gosurf_time_kernel(int32_t kernel, void* start_event, void* stop_e
 const char* gosurf_last_error(void);
 
 /* Sample capacity of a batch drawn with `cfg`: M * (n_strat + n_near), or
-   M * max(n_strat + n_near, n_proposal) with a proposal (the actual count is
+   M * max(n_strat + n_near, n_free + n_proposal) with a proposal (the actual count is
    then seg[M], on the device). */
 int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg);
 

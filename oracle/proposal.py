@@ -14,6 +14,9 @@ Eq. volume_rendering).  Its definition, written out step by step:
   as P1[64][38] q1[64] P2[64][64] q2[64] P3[3][64] q3[3];
 * interval: near = t_lo + (t_hi - t_lo) sigmoid(o_0),
   far = near + (t_hi - near) sigmoid(o_1), confidence = sigmoid(o_2);
+* sampling: a ray whose confidence reaches the threshold gets n_free
+  stratified samples on [t_lo, near] and n_prop in [near, far]; the others
+  keep the plain samples;
 * targets from a logged ray with weights w_i at depths t_i: p_i = w_i / sum w,
   the t-quantiles at 0.5 % and 99.5 % of the piecewise-linear CDF through
   (t_0, p_0), (t_1, p_0 + p_1), ..., widened by `widen` on both sides and
@@ -178,3 +181,11 @@ def proposal_samples(near, far, n, u):
     """n stratified samples in [near, far] from uniforms u [M, n]."""
     k = np.arange(n)
     return near[:, None] + (k[None, :] + u) * (far - near)[:, None] / n
+
+
+def confident_ray_samples(t_lo, near, far, n_free, n_prop, u_free, u_prop):
+    """Samples of a confident ray: n_free stratified on the free space
+    [t_lo, near] before the interval (the free-space and Eikonal terms keep
+    their samples there), then n_prop stratified in [near, far]."""
+    return np.concatenate([proposal_samples(t_lo, near, n_free, u_free),
+                           proposal_samples(near, far, n_prop, u_prop)], axis=1)

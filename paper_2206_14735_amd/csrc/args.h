@@ -124,11 +124,13 @@ struct SampleArgs {
   float* eps;
   long long* pixel;
   // proposal-driven sampling: per-ray (near, far, confidence); rays with
-  // confidence >= conf_thr get n_prop samples in [near, far], the others the
-  // plain n_strat + n_near; seg is then filled beforehand by the scan
+  // confidence >= conf_thr get n_free samples on [t_lo, near] and n_prop in
+  // [near, far], the others the plain n_strat + n_near; seg is then filled
+  // beforehand by the scan
   const float* prop3;
   float conf_thr;
   int n_prop;
+  int n_free;
 };
 
 }  // namespace gs

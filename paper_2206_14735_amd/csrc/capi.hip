@@ -20,9 +20,9 @@ int priv_max_floats();
 int field_blocks(int total, int pairs);
 hipError_t launch_render(const RenderArgs& a, bool bwd, hipStream_t st);
 hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smooth_partial, int n_sp, int S,
-                              const float lam[6], float* losses, hipStream_t st);
+                              const float lam[6], float* losses, float* ray_part, hipStream_t st);
 hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
-                              float* tmp, hipStream_t st);
+                              float* tmp, float* ray_part, hipStream_t st);
 hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st);
 hipError_t launch_sample(const SampleArgs& a, hipStream_t st);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t st);
@@ -30,8 +30,8 @@ hipError_t launch_sample_rays_only(const SampleArgs& a, hipStream_t st);
 hipError_t launch_sample_gen_only(const SampleArgs& a, hipStream_t st);
 hipError_t launch_proposal(const PropArgs& a, bool train, int blocks, hipStream_t st);
 hipError_t launch_proposal_targets(const TargetArgs& a, hipStream_t st);
-hipError_t launch_proposal_seg(const float* prop3, int M, float thr, int n_prop, int n_plain, int* seg,
-                               hipStream_t st);
+hipError_t launch_proposal_seg(float* prop3, const float* depth, int depth_check, int M, float thr, int n_prop,
+                               int n_plain, int* seg, int* block_total, hipStream_t st);
 int proposal_blocks(int M);
 int proposal_numel();
 hipError_t launch_colsum(const float* part, int rows, int cols, float* tmp, float* add_dst, int n_add,
@@ -123,6 +123,7 @@ struct Workspace {
   float* mlp_partial;     // [2048][kMlpNumel]
   float* priv_partial;    // [2048][priv_max_floats]
   float* colsum_tmp;      // [64][max(kMlpNumel, priv_max_floats)]
+  float* ray_part;        // [64][8] block partials of sums over rays
   size_t bytes;
 };
 
@@ -138,6 +139,7 @@ Workspace layout(char* base, int M, int total, int S) {
   w.ray_dv = reinterpret_cast<float*>(take(sizeof(float) * (size_t)M));
   w.mlp_partial = reinterpret_cast<float*>(take(sizeof(float) * 2048 * (size_t)gs::kMlpNumel));
   w.priv_partial = reinterpret_cast<float*>(take(sizeof(float) * 2048 * (size_t)gs::priv_max_floats()));
+  w.ray_part = reinterpret_cast<float*>(take(sizeof(float) * 64 * 8));
   w.colsum_tmp = reinterpret_cast<float*>(
       take(sizeof(float) * 64 * (size_t)(gs::priv_max_floats() > gs::kMlpNumel ? gs::priv_max_floats() : gs::kMlpNumel)));
   w.bytes = off;
@@ -197,7 +199,7 @@ gosurf_status gosurf_time_kernel(int32_t kernel, void* start_event, void* stop_e
 int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg) {
   if (!cfg) return -1;
   int64_t n = cfg->n_strat + cfg->n_near;
-  if (cfg->proposal && cfg->n_proposal > n) n = cfg->n_proposal;
+  if (cfg->proposal && cfg->n_free + cfg->n_proposal > n) n = cfg->n_free + cfg->n_proposal;
   return (int64_t)cfg->M * n;
 }
 
@@ -227,10 +229,12 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
   if (c->proposal) {
     if (!c->grid) return fail(GOSURF_ERR_NULL, "the proposal needs the grid");
     if (!out->prop) return fail(GOSURF_ERR_NULL, "out.prop must hold [M][3] with a proposal");
-    if (c->n_proposal < 1 || c->n_proposal > GOSURF_MAX_SAMPLES_PER_RAY)
-      return fail(GOSURF_ERR_SHAPE, "n_proposal = %d must lie in [1, %d]", c->n_proposal,
-                  GOSURF_MAX_SAMPLES_PER_RAY);
+    if (c->n_proposal < 1 || c->n_free < 0 || c->n_free + c->n_proposal > GOSURF_MAX_SAMPLES_PER_RAY)
+      return fail(GOSURF_ERR_SHAPE, "need n_proposal >= 1, n_free >= 0 and n_free + n_proposal = %d <= %d",
+                  c->n_free + c->n_proposal, GOSURF_MAX_SAMPLES_PER_RAY);
     if (!std::isfinite(c->conf_threshold)) return fail(GOSURF_ERR_VALUE, "conf_threshold must be finite");
+    if (c->depth_check && !(c->conf_threshold > 0.f))
+      return fail(GOSURF_ERR_VALUE, "the depth check needs conf_threshold > 0");
   }
   if (out->M != c->M || out->total != total || out->S != c->S)
     return fail(GOSURF_ERR_SHAPE, "out sizes (M=%d total=%d S=%d) do not match cfg (M=%d total=%lld S=%d)",
@@ -265,11 +269,12 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
   pa.span_mode = c->span_mode; pa.near_t = c->near_t; pa.far_t = c->far_t; pa.out3 = out->prop;
   if ((st = hip_check(gs::launch_proposal(pa, false, gs::proposal_blocks(c->M), s), "proposal")) != GOSURF_OK)
     return st;
-  if ((st = hip_check(gs::launch_proposal_seg(out->prop, c->M, c->conf_threshold, c->n_proposal,
-                                              c->n_strat + c->n_near, out->seg, s),
+  if ((st = hip_check(gs::launch_proposal_seg(out->prop, out->depth, c->depth_check, c->M, c->conf_threshold,
+                                              c->n_free + c->n_proposal,
+                                              c->n_strat + c->n_near, out->seg, out->ray_of, s),
                       "proposal seg")) != GOSURF_OK)
     return st;
-  a.prop3 = out->prop; a.conf_thr = c->conf_threshold; a.n_prop = c->n_proposal;
+  a.prop3 = out->prop; a.conf_thr = c->conf_threshold; a.n_prop = c->n_proposal; a.n_free = c->n_free;
   if ((st = hip_check(gs::launch_sample_gen_only(a, s), "proposal samples")) != GOSURF_OK) return st;
   return ok();
 }
@@ -315,7 +320,7 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   ra.ray_partial = w.ray_partial;
   if ((st = hip_check(gs::launch_render(ra, false, s), "render fwd")) != GOSURF_OK) return st;
   if ((st = hip_check(gs::launch_loss_reduce(w.ray_partial, b->M, w.smooth_partial, n_sp, b->S, loss->lambda,
-                                             out->losses, s),
+                                             out->losses, w.ray_part, s),
                       "loss reduce")) != GOSURF_OK)
     return st;
   return ok();
@@ -368,7 +373,8 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   mark(GOSURF_KERNEL_FIELD_BWD, false, s);
   if ((st = hip_check(gs::launch_priv_reduce(fa, nb, counts, w.colsum_tmp, s), "level reduce")) != GOSURF_OK)
     return st;
-  if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nb, w.ray_dv, b->M, grads->mlp, w.colsum_tmp, s),
+  if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nb, w.ray_dv, b->M, grads->mlp, w.colsum_tmp,
+                                             w.ray_part, s),
                       "grad reduce")) != GOSURF_OK)
     return st;
   return ok();

@@ -324,48 +324,80 @@ __global__ __launch_bounds__(256) void proposal_targets_kernel(TargetArgs A) {
 
 // samples per ray from the confidences, and their exclusive prefix sum (one block)
 // Segment offsets of the proposal-driven batch: ray m gets n_prop samples if
-// its confidence reaches thr, else n_plain.  One block scans chunks of 8192
-// rays: lengths are read coalesced into LDS, each thread sums 8 consecutive
-// rays, the 1024 partial sums are scanned in LDS, and the offsets go back out
-// coalesced; a running carry links the chunks.
+// its confidence reaches thr, else n_plain.  With depth_check, a ray with an
+// observed depth D > 0 keeps its interval only if near <= D <= far; a rejected
+// ray's confidence is negated in prop3 (thr > 0), which the sample generator
+// reads.  Block b scans rays [8192 b, 8192 (b + 1)): lengths are read
+// coalesced into LDS, each thread sums 8 consecutive rays, the 1024 partial
+// sums are scanned in LDS and the chunk-local offsets written out coalesced
+// with the chunk total in block_total[b]; a second pass adds the totals of
+// the preceding chunks.
 constexpr int kSegChunk = 8192;
-__global__ __launch_bounds__(1024) void proposal_seg_kernel(const float* __restrict__ prop3, int M, float thr,
-                                                            int n_prop, int n_plain, int* __restrict__ seg) {
+__global__ __launch_bounds__(1024) void proposal_seg_local_kernel(float* __restrict__ prop3,
+                                                                  const float* __restrict__ depth, int depth_check,
+                                                                  int M, float thr, int n_prop, int n_plain,
+                                                                  int* __restrict__ seg, int* __restrict__ block_total) {
   __shared__ int len[kSegChunk];
   __shared__ int part[1024];
   const int tid = threadIdx.x;
   constexpr int per = kSegChunk / 1024;
-  int carry = 0;
-  for (int c0 = 0; c0 < M; c0 += kSegChunk) {
-    const int n = min(kSegChunk, M - c0);
-    for (int m = tid; m < kSegChunk; m += 1024)
-      len[m] = m < n ? (prop3[3 * (size_t)(c0 + m) + 2] >= thr ? n_prop : n_plain) : 0;
-    __syncthreads();
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < per; ++k) s += len[tid * per + k];
-    part[tid] = s;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-      const int v = tid >= d ? part[tid - d] : 0;
-      __syncthreads();
-      part[tid] += v;
-      __syncthreads();
+  const int c0 = blockIdx.x * kSegChunk;
+  const int n = min(kSegChunk, M - c0);
+  for (int m = tid; m < kSegChunk; m += 1024) {
+    int l = 0;
+    if (m < n) {
+      const size_t k = (size_t)(c0 + m);
+      const float conf = prop3[3 * k + 2];
+      bool acc = conf >= thr;
+      if (acc && depth_check) {
+        const float D = depth[k];
+        if (D > 0.f && !(prop3[3 * k] <= D && D <= prop3[3 * k + 1])) {
+          acc = false;
+          prop3[3 * k + 2] = -conf;
+        }
+      }
+      l = acc ? n_prop : n_plain;
     }
-    int run = carry + part[tid] - s;   // exclusive prefix of this thread's first ray
+    len[m] = l;
+  }
+  __syncthreads();
+  int s = 0;
 #pragma unroll
-    for (int k = 0; k < per; ++k) {
-      const int l = len[tid * per + k];
-      len[tid * per + k] = run;
-      run += l;
-    }
-    const int chunk_total = part[1023];
+  for (int k = 0; k < per; ++k) s += len[tid * per + k];
+  part[tid] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int v = tid >= d ? part[tid - d] : 0;
     __syncthreads();
-    for (int m = tid; m < n; m += 1024) seg[c0 + m] = len[m];
-    carry += chunk_total;
+    part[tid] += v;
     __syncthreads();
   }
-  if (tid == 0) seg[M] = carry;
+  int run = part[tid] - s;   // exclusive prefix of this thread's first ray in the chunk
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    const int l = len[tid * per + k];
+    len[tid * per + k] = run;
+    run += l;
+  }
+  __syncthreads();
+  for (int m = tid; m < n; m += 1024) seg[c0 + m] = len[m];
+  if (tid == 0) block_total[blockIdx.x] = part[1023];
+}
+
+__global__ __launch_bounds__(1024) void proposal_seg_add_kernel(int M, int* __restrict__ seg,
+                                                                const int* __restrict__ block_total) {
+  __shared__ int off;
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int b = 0; b < (int)blockIdx.x; ++b) o += block_total[b];
+    off = o;
+    if (blockIdx.x == gridDim.x - 1) seg[M] = o + block_total[blockIdx.x];
+  }
+  __syncthreads();
+  const int c0 = blockIdx.x * kSegChunk;
+  const int n = min(kSegChunk, M - c0);
+  if (blockIdx.x > 0)
+    for (int m = threadIdx.x; m < n; m += 1024) seg[c0 + m] += off;
 }
 
 int proposal_blocks(int M) {
@@ -394,9 +426,14 @@ hipError_t launch_proposal_targets(const TargetArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_proposal_seg(const float* prop3, int M, float thr, int n_prop, int n_plain, int* seg,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(proposal_seg_kernel, dim3(1), dim3(1024), 0, st, prop3, M, thr, n_prop, n_plain, seg);
+// block_total: scratch of ceil(M / 8192) ints (the batch's ray_of, which the
+// sample generator overwrites afterwards)
+hipError_t launch_proposal_seg(float* prop3, const float* depth, int depth_check, int M, float thr, int n_prop,
+                               int n_plain, int* seg, int* block_total, hipStream_t st) {
+  const int nb = (M + kSegChunk - 1) / kSegChunk;
+  hipLaunchKernelGGL(proposal_seg_local_kernel, dim3(nb), dim3(1024), 0, st, prop3, depth, depth_check, M, thr,
+                     n_prop, n_plain, seg, block_total);
+  hipLaunchKernelGGL(proposal_seg_add_kernel, dim3(nb), dim3(1024), 0, st, M, seg, block_total);
   return hipGetLastError();
 }
 

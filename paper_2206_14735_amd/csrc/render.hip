@@ -261,26 +261,47 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
 }
 
 // ---------------------------------------------------------------- reductions (fixed order)
-__global__ __launch_bounds__(256) void loss_reduce_kernel(const float* __restrict__ ray_partial, int M,
-                                                          const float* __restrict__ smooth_partial, int n_sp,
-                                                          int S, float l0, float l1, float l2, float l3,
-                                                          float l4, float l5, float* __restrict__ losses) {
-  __shared__ float red[6][256];
-  float acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int m = threadIdx.x; m < M; m += 256) {
-    const float* p = ray_partial + 8 * (size_t)m;
-    acc[0] += p[0]; acc[1] += p[1]; acc[2] += p[2]; acc[3] += p[3]; acc[4] += p[4]; acc[5] += p[5];
-  }
-  float sm = 0.f;
-  for (int i = threadIdx.x; i < n_sp; i += 256) sm += smooth_partial[i];
-  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+// Sums over rays in two fixed-order stages.  Stage 1: block b adds columns
+// 0..NCOL-1 of rays b*256 + t, b*256 + t + 256*gridDim, ... per thread, then
+// over its 256 threads in a fixed tree, into part[b][0..NCOL-1] (rows of 8).
+constexpr int kRaySumBlocks = 64;
+template <int NCOL>
+__global__ __launch_bounds__(256) void ray_sum_stage1_kernel(const float* __restrict__ x, int M, int stride,
+                                                             float* __restrict__ part) {
+  __shared__ float red[NCOL][256];
+  float acc[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) acc[c] = 0.f;
+  for (int m = blockIdx.x * 256 + threadIdx.x; m < M; m += gridDim.x * 256)
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) acc[c] += x[(size_t)m * stride + c];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) red[c][threadIdx.x] = acc[c];
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w)
-      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
     __syncthreads();
   }
+  if (threadIdx.x < NCOL) part[8 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+int ray_sum_blocks(int M) {
+  const int b = (M + 255) / 256;
+  return b < 1 ? 1 : (b > kRaySumBlocks ? kRaySumBlocks : b);
+}
+
+// Stage 2 of the loss: the block partials of the six per-ray columns (rgb,
+// depth, sdf, fs, eik, rays with depth) in block order, the smoothness block
+// partials in a fixed tree; then the set means and the weighted total.
+__global__ __launch_bounds__(256) void loss_final_kernel(const float* __restrict__ part, int nb,
+                                                         const float* __restrict__ smooth_partial, int n_sp, int M,
+                                                         int S, float l0, float l1, float l2, float l3, float l4,
+                                                         float l5, float* __restrict__ losses) {
   __shared__ float sred[256];
+  float sm = 0.f;
+  for (int i = threadIdx.x; i < n_sp; i += 256) sm += smooth_partial[i];
   sred[threadIdx.x] = sm;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -288,10 +309,13 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const float* __restric
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    float col[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < nb; ++b)
+      for (int c = 0; c < 6; ++c) col[c] += part[8 * b + c];
     const float invM = 1.f / (float)M;
-    const float nd = red[5][0];
-    const float L[6] = {red[0][0] * invM, nd > 0.f ? red[1][0] / nd : 0.f, red[2][0] * invM,
-                        red[3][0] * invM, red[4][0] * invM, S > 0 ? sred[0] / (float)S : 0.f};
+    const float nd = col[5];
+    const float L[6] = {col[0] * invM, nd > 0.f ? col[1] / nd : 0.f, col[2] * invM,
+                        col[3] * invM, col[4] * invM, S > 0 ? sred[0] / (float)S : 0.f};
     const float lam[6] = {l0, l1, l2, l3, l4, l5};
     float tot = 0.f;
     for (int k = 0; k < 6; ++k) { losses[k] = L[k]; tot += lam[k] * L[k]; }
@@ -327,34 +351,19 @@ __device__ __forceinline__ float colsum_stage2(const float* __restrict__ tmp, in
   return s;
 }
 
-// grads.mlp += column sums (all entries but v)
-__global__ __launch_bounds__(256) void grad_stage2_kernel(const float* __restrict__ tmp,
-                                                          float* __restrict__ grad_mlp) {
+// grads.mlp += column sums; entry v gets the per-ray dL/dv sums instead (the
+// nb block partials of ray_sum_stage1, in block order)
+__global__ __launch_bounds__(256) void grad_stage2_kernel(const float* __restrict__ tmp, const float* __restrict__ dv_part,
+                                                          int nb, float* __restrict__ grad_mlp) {
   const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= kMlpNumel || e == oV) return;
+  if (e >= kMlpNumel) return;
+  if (e == oV) {
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += dv_part[8 * b];
+    grad_mlp[oV] += s;
+    return;
+  }
   grad_mlp[e] += colsum_stage2(tmp, kMlpNumel, e);
-}
-
-// grads.mlp[v] += sum over rays of the per-ray dL/dv terms (fixed order)
-__global__ __launch_bounds__(1024) void dv_reduce_kernel(const float* __restrict__ ray_dv, int M,
-                                                         float* __restrict__ grad_mlp) {
-  __shared__ float red[1024];
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  int m = threadIdx.x;
-  for (; m + 3 * 1024 < M; m += 4 * 1024) {
-    s0 += ray_dv[m];
-    s1 += ray_dv[m + 1024];
-    s2 += ray_dv[m + 2048];
-    s3 += ray_dv[m + 3072];
-  }
-  for (; m < M; m += 1024) s0 += ray_dv[m];
-  red[threadIdx.x] = (s0 + s1) + (s2 + s3);
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) grad_mlp[oV] += red[0];
 }
 
 hipError_t launch_colsum_stage1(const float* part, int rows, int cols, float* tmp, hipStream_t st) {
@@ -363,11 +372,13 @@ hipError_t launch_colsum_stage1(const float* part, int rows, int cols, float* tm
 }
 
 hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
-                              float* tmp, hipStream_t st) {
+                              float* tmp, float* ray_part, hipStream_t st) {
   hipError_t e = launch_colsum_stage1(partial, n_part, kMlpNumel, tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(grad_stage2_kernel, dim3((kMlpNumel + 255) / 256), dim3(256), 0, st, tmp, grad_mlp);
-  hipLaunchKernelGGL(dv_reduce_kernel, dim3(1), dim3(1024), 0, st, ray_dv, M, grad_mlp);
+  const int nb = ray_sum_blocks(M);
+  hipLaunchKernelGGL(ray_sum_stage1_kernel<1>, dim3(nb), dim3(256), 0, st, ray_dv, M, 1, ray_part);
+  hipLaunchKernelGGL(grad_stage2_kernel, dim3((kMlpNumel + 255) / 256), dim3(256), 0, st, tmp, ray_part, nb,
+                     grad_mlp);
   return hipGetLastError();
 }
 
@@ -475,9 +486,11 @@ hipError_t launch_render(const RenderArgs& a, bool bwd, hipStream_t st) {
 }
 
 hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smooth_partial, int n_sp, int S,
-                              const float lam[6], float* losses, hipStream_t st) {
-  hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, ray_partial, M, smooth_partial, n_sp, S,
-                     lam[0], lam[1], lam[2], lam[3], lam[4], lam[5], losses);
+                              const float lam[6], float* losses, float* ray_part, hipStream_t st) {
+  const int nb = ray_sum_blocks(M);
+  hipLaunchKernelGGL(ray_sum_stage1_kernel<6>, dim3(nb), dim3(256), 0, st, ray_partial, M, 8, ray_part);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, ray_part, nb, smooth_partial, n_sp, M, S, lam[0],
+                     lam[1], lam[2], lam[3], lam[4], lam[5], losses);
   return hipGetLastError();
 }
 

@@ -92,11 +92,20 @@ __global__ __launch_bounds__(256) void sample_rays_kernel(SampleArgs A) {
   const int n_tot = A.n_strat + A.n_near;
   const bool proposed = A.prop3 != nullptr && A.prop3[3 * m + 2] >= A.conf_thr;
   const bool two = !proposed && D > 0.f && A.n_near > 0;
-  const int ns = proposed ? A.n_prop : (two ? A.n_strat : n_tot);   // stratified count
-  const int nn = two ? A.n_near : 0;                                // near-depth count
-  if (proposed) { tn = A.prop3[3 * m]; tf = A.prop3[3 * m + 1]; }
+  // list a (stratified stream): the span, or a confident ray's interval;
+  // list b (near-depth stream): around the observed depth, or a confident
+  // ray's free space [t_lo, near] before its interval
+  const int ns = proposed ? A.n_prop : (two ? A.n_strat : n_tot);
+  const int nn = proposed ? A.n_free : (two ? A.n_near : 0);
+  float lo = D - A.trunc, dn = (2.f * A.trunc) / (float)(nn > 0 ? nn : 1);
+  if (proposed) {
+    const float pn = A.prop3[3 * m], pf = A.prop3[3 * m + 1];
+    lo = tn;
+    dn = (pn - tn) / (float)(nn > 0 ? nn : 1);
+    tn = pn;
+    tf = pf;
+  }
   const float ds = (tf - tn) / (float)ns;
-  const float lo = D - A.trunc, dn = (2.f * A.trunc) / (float)(nn > 0 ? nn : 1);
   const size_t base = A.prop3 != nullptr ? (size_t)A.seg[m] : (size_t)m * n_tot;
   float av[kChunks], bv[kChunks];
 #pragma unroll

@@ -89,14 +89,21 @@ def test_proposal_targets_match_oracle():
     assert np.max(np.abs(got[:, :2] - ref[:, :2])) < 1e-3 * dt + 1e-6
 
 
-def test_proposal_driven_sampling():
+def _uniforms(m, step, stream, n, seed):
+    w = philox4x32_10(np.stack([np.full((n + 3) // 4, m), np.full((n + 3) // 4, step),
+                                np.full((n + 3) // 4, stream), np.arange((n + 3) // 4)], -1), np.array([seed, 0]))
+    return uniform01(w.reshape(-1))[:n]
+
+
+@pytest.mark.parametrize("n_free,depth_check", [(0, False), (5, False), (5, True)])
+def test_proposal_driven_sampling(n_free, depth_check):
     G = _G()
     L, fr, b, grid, prop = _room(M=8, seed=7)
     M = 500
     model = G.make_model(L)
     cfg = G.SampleCfg(M, 16, 8, G.SPAN_BOX, 0.1, 1e9, 0.1, 0, 0.004, 99, 3)
     gd, pd = grid.cuda(), prop.cuda()
-    G.set_proposal(cfg, pd, gd, n_proposal=12, conf_threshold=0.5)
+    G.set_proposal(cfg, pd, gd, n_proposal=12, conf_threshold=0.5, n_free=n_free, depth_check=depth_check)
     batch = G.gosurf_sample_rays(model, fr.to("cuda"), cfg)
     torch.cuda.synchronize()
     p3 = batch.prop.cpu().numpy()
@@ -104,18 +111,30 @@ def test_proposal_driven_sampling():
     t = batch.t.cpu().numpy()
     conf_ok = p3[:, 2] >= 0.5
     assert 0 < conf_ok.sum() < M      # both branches exercised by the random network
-    lens = np.where(conf_ok, 12, 24)
+    D = batch.depth.cpu().numpy()
+    if depth_check:
+        # rejected: confident but the observed depth lies outside [near, far]
+        rej = p3[:, 2] <= -0.5
+        outside = (D > 0) & ~((p3[:, 0] <= D) & (D <= p3[:, 1]))
+        assert rej.sum() > 0
+        assert np.all(outside[rej]) and not np.any(outside[conf_ok])
+    else:
+        assert np.all(p3[:, 2] >= 0)
+    lens = np.where(conf_ok, n_free + 12, 24)
     assert np.array_equal(np.diff(seg), lens) and seg[0] == 0
-    # plain rays: identical to the plain sampler's rays; proposal rays: stratified in [near, far]
+    # plain rays: identical to the plain sampler's rays; confident rays: n_free
+    # stratified on [t_lo, near] (near-depth stream), then 12 in [near, far]
     plain, _, _ = osampler.sample_batch(fr, L, M, 16, 8, "aabb", 0.1, 1e9, 0.1, 0, 0.004, seed=99, step=3)
+    o, r = batch.o.cpu().numpy().astype(np.float64), batch.r.cpu().numpy().astype(np.float64)
+    t_lo, _ = OP.ray_span(o, r, L, "aabb", 0.1, 1e9)
     for m in range(M):
         tt = t[seg[m]:seg[m + 1]]
         if conf_ok[m]:
-            w = philox4x32_10(np.stack([np.full(3, m), np.full(3, 3), np.full(3, 1), np.arange(3)], -1),
-                              np.array([99, 0]))
-            u = uniform01(w.reshape(-1))[:12]
-            ref = p3[m, 0] + (np.arange(12) + u) * (p3[m, 1] - p3[m, 0]) / 12
-            assert np.allclose(tt, ref, rtol=4e-6, atol=1e-6)
+            ref = OP.confident_ray_samples(t_lo[m:m + 1], p3[m:m + 1, 0].astype(np.float64),
+                                           p3[m:m + 1, 1].astype(np.float64), n_free, 12,
+                                           _uniforms(m, 3, 2, n_free, 99)[None], _uniforms(m, 3, 1, 12, 99)[None])[0]
+            assert np.allclose(tt, ref, rtol=4e-6, atol=2e-6), m
+            assert np.all(np.diff(tt) >= 0)
         else:
             assert np.allclose(tt, plain.t[24 * m:24 * (m + 1)], rtol=4e-6, atol=1e-6)
     assert np.array_equal(batch.ray_of.cpu().numpy()[:seg[-1]], np.repeat(np.arange(M), lens))
@@ -181,3 +200,20 @@ def test_trained_proposal_beats_plain_sampling_at_equal_samples():
     assert prop["cover_confident"] > 0.95
     # fewer samples per ray on average than plain 96
     assert prop["samples"] < 0.6 * p96["samples"]
+
+
+def test_proposal_segments_span_several_chunks():
+    """The segment scan works in chunks of 8192 rays: 20000 rays (three chunks,
+    the last ragged) must give seg = exclusive prefix sums of the lengths."""
+    G = _G()
+    L, fr, b, grid, prop = _room(M=8, seed=7)
+    M = 20000
+    cfg = G.SampleCfg(M, 16, 8, G.SPAN_BOX, 0.1, 1e9, 0.1, 0, 0.004, 5, 1)
+    G.set_proposal(cfg, prop.cuda(), grid.cuda(), n_proposal=12, conf_threshold=0.5, n_free=3, depth_check=True)
+    batch = G.gosurf_sample_rays(G.make_model(L), fr.to("cuda"), cfg)
+    torch.cuda.synchronize()
+    p3 = batch.prop.cpu().numpy()
+    lens = np.where(p3[:, 2] >= 0.5, 15, 24)
+    seg = batch.seg.cpu().numpy()
+    assert seg[0] == 0 and np.array_equal(np.diff(seg), lens)
+    assert np.array_equal(batch.ray_of.cpu().numpy()[:seg[-1]], np.repeat(np.arange(M), lens))

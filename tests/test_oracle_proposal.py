@@ -129,3 +129,14 @@ def test_proposal_gradient_matches_central_differences():
         gi = float(res["grad"][i])
         bad += not (abs(fd - gi) <= 1e-5 * max(abs(gi), 1e-4))
     assert bad <= 1
+
+
+def test_confident_ray_samples_cover_free_space_then_interval():
+    t_lo, near, far = np.array([0.5]), np.array([2.0]), np.array([2.3])
+    u_free = np.array([[0.0, 0.5, 0.999]])
+    u_prop = np.array([[0.25, 0.75]])
+    t = OP.confident_ray_samples(t_lo, near, far, 3, 2, u_free, u_prop)[0]
+    # one sample per bin of width 0.5 on [0.5, 2.0], then per bin of 0.15 on [2.0, 2.3]
+    assert np.allclose(t, [0.5, 1.25, 0.5 + 2.999 * 0.5, 2.0 + 0.25 * 0.15, 2.0 + 1.75 * 0.15], atol=1e-12)
+    assert np.all(np.diff(t) > 0)
+    assert OP.confident_ray_samples(t_lo, near, far, 0, 2, np.zeros((1, 0)), u_prop).shape == (1, 2)
