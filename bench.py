@@ -69,15 +69,15 @@ def source_digest():
     return h.hexdigest()[:12]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources (else None)."""
+    on the current kernel sources and on this workload (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     data = json.load(open(path))
     entry = data.get(kernel)
-    if not entry or entry.get("source_digest") != source_digest():
+    if not entry or entry.get("source_digest") != source_digest() or entry.get("workload") != workload:
         return None
     return entry.get("bytes_per_launch")
 
@@ -356,7 +356,7 @@ def main():
 
     def roofline(name, bytes_per_launch, ms, label):
         gbs = bytes_per_launch / (ms * 1e-3) / 1e9
-        traffic = measured_traffic(name)
+        traffic = measured_traffic(name, w.name)
         return {"kernel": label, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": bytes_per_launch, "ms_per_launch": round(ms, 4)}
