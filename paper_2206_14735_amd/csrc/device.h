@@ -148,4 +148,19 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wave with every lane active, in a fixed order:
+// prefix sums inside each row of 16 lanes by DPP row shifts, then the row
+// totals carried on by row broadcasts (lane 15 into row 1 and lane 47 into
+// row 3, then lane 31 into rows 2-3); lane 63 ends with the total, which is
+// returned to every lane.  Six VALU steps instead of six LDS-crossbar shuffles.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_f<0x111>(v);   // row_shr:1
+  v += dpp_f<0x112>(v);   // row_shr:2
+  v += dpp_f<0x114>(v);   // row_shr:4
+  v += dpp_f<0x118>(v);   // row_shr:8
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));   // row_bcast:15
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));   // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 }  // namespace gs

@@ -50,8 +50,13 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
   // 1 - Phi(b)/Phi(a) = Phi(-b) * (1 - e^{-(a - b)}) with a = s phi_k, b = s phi_{k+1}:
   // no difference of nearly equal logarithms, so small opacities keep their
   // relative accuracy.
+  const int nch = (R.n + 63) >> 6;   // chunks holding samples (wave-uniform)
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
+    if (c >= nch) {
+      R.alpha[c] = 0.f;
+      continue;
+    }
     float nphi = __shfl_down(R.phi[c], 1, 64);
     int nval = __shfl_down((int)R.valid[c], 1, 64);
     if (c + 1 < kChunks) {
@@ -72,6 +77,10 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
   float carry = 1.f;
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
+    if (c >= nch) {
+      R.T[c] = R.w[c] = 0.f;
+      continue;
+    }
     float v = 1.f - R.alpha[c];
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -93,11 +102,11 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
     dd += R.w[c] * R.tt[c];
     ws += R.w[c];
   }
-  R.c_hat[0] = wave_sum(cr);
-  R.c_hat[1] = wave_sum(cg);
-  R.c_hat[2] = wave_sum(cbl);
-  R.d_hat = wave_sum(dd);
-  R.wsum = wave_sum(ws);
+  R.c_hat[0] = wave_sum_dpp(cr);
+  R.c_hat[1] = wave_sum_dpp(cg);
+  R.c_hat[2] = wave_sum_dpp(cbl);
+  R.d_hat = wave_sum_dpp(dd);
+  R.wsum = wave_sum_dpp(ws);
 }
 
 __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs A) {
@@ -124,8 +133,8 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs A) {
       nfs += 1.f;
     }
   }
-  sdf = wave_sum(sdf); fs = wave_sum(fs); ek = wave_sum(ek);
-  ntr = wave_sum(ntr); nfs = wave_sum(nfs);
+  sdf = wave_sum_dpp(sdf); fs = wave_sum_dpp(fs); ek = wave_sum_dpp(ek);
+  ntr = wave_sum_dpp(ntr); nfs = wave_sum_dpp(nfs);
   if (lane == 0) {
     A.rgb_hat[3 * m] = R.c_hat[0];
     A.rgb_hat[3 * m + 1] = R.c_hat[1];
@@ -168,8 +177,9 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
     if (fabsf(b) <= A.trunc) ntr += 1.f;
     else if (b > A.trunc) nfs += 1.f;
   }
-  ntr = wave_sum(ntr);
-  nfs = wave_sum(nfs);
+  ntr = wave_sum_dpp(ntr);
+  nfs = wave_sum_dpp(nfs);
+  const int nch = (R.n + 63) >> 6;   // chunks holding samples (wave-uniform)
 
   // dL/dw_k and the suffix recurrence Q_i = g_i alpha_i + (1 - alpha_i) Q_{i+1}
   float g[kChunks], Q[kChunks];
@@ -179,6 +189,10 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
   float carry = 0.f;   // Q just past the current chunk
 #pragma unroll
   for (int c = kChunks - 1; c >= 0; --c) {
+    if (c >= nch) {
+      Q[c] = 0.f;
+      continue;
+    }
     float a = 1.f - R.alpha[c], b = g[c] * R.alpha[c];
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -192,6 +206,10 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
   float dalpha[kChunks], act_next[kChunks];
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
+    if (c >= nch) {
+      dalpha[c] = 0.f;
+      continue;
+    }
     // R_k = Q_{k+1}
     float Rk = __shfl_down(Q[c], 1, 64);
     if (c + 1 < kChunks) {
@@ -205,6 +223,10 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
   const float s = R.s;
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
+    if (c >= nch) {
+      act_next[c] = 0.f;
+      continue;
+    }
     const int k = 64 * c + lane;
     // this interval's derivative factors (active only when alpha > 0)
     const float om = 1.f - R.alpha[c];
@@ -255,7 +277,7 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
       A.eikw[sidx] = R.valid[c] ? ew * sc : 0.f;
     }
   }
-  dv_acc = wave_sum(dv_acc);
+  dv_acc = wave_sum_dpp(dv_acc);
   // d s / d v = 10 s
   if (lane == 0) A.ray_dv[m] = dv_acc * 10.f * s * sc;
 }
