@@ -133,6 +133,7 @@ def compare(a, G, synth, Reconstruction, torch):
     n_prop = wp.extra["proposal_samples"]
     n_free = wp.extra["free_samples"]
     depth_check = wp.extra["depth_check"]
+    depth_extend = wp.extra["depth_extend"]
     thr = wp.extra["conf_threshold"]
     cover_tol = wp.extra["cover_tol"]
     span = G.SPAN_BOX
@@ -189,7 +190,7 @@ def compare(a, G, synth, Reconstruction, torch):
         """Rendered depth against the noise-free depth on rays with observed depth."""
         evaluator.grid, evaluator.mlp = grid, mlp
         evaluator.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr, n_free=n_free,
-                               depth_check=depth_check)
+                               depth_check=depth_check, depth_extend=depth_extend)
         errs, spr, conf = [], [], []
         for k in range(n_batches):
             evaluator.it = 300_000 + k
@@ -244,7 +245,8 @@ def compare(a, G, synth, Reconstruction, torch):
     for name, bf16, prop in (("plain_fp32", False, None), ("bf16_proposal", True, trainer.prop)):
         rec = new_rec(bf16, 3, base)
         if prop is not None:
-            rec.use_proposal(prop, n_proposal=n_prop, conf_threshold=thr, n_free=n_free, depth_check=depth_check)
+            rec.use_proposal(prop, n_proposal=n_prop, conf_threshold=thr, n_free=n_free, depth_check=depth_check,
+                             depth_extend=depth_extend)
         t0 = time.time()
         ms, per_call, spr = run(rec, a.compare_phase2)
         r = {"ms_per_step": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2), "per_call_ms": per_call,
@@ -262,7 +264,7 @@ def compare(a, G, synth, Reconstruction, torch):
     return {
         "workload": f"{wp.name}: {M} rays per step, plain 64+32 vs proposal {n_prop} in the interval + "
                     f"{n_free} on the free space before it per confident ray (confidence >= {thr}"
-                    f"{' and the observed depth inside the interval' if depth_check else ''}, else plain "
+                    f"{f' and the observed depth within {depth_extend} m of the interval (stretched to it)' if depth_check else ''}, else plain "
                     f"64+32), {S} smoothness pairs, {wp.n_frames} frames "
                     f"{wp.W}x{wp.H}; {a.compare_phase1} shared plain steps, then {a.compare_phase2} steps of "
                     f"each; proposal trained for 12000 steps on {n_logged} logged rays",

@@ -144,8 +144,11 @@ typedef struct {
   int32_t n_proposal;      /* interval samples per confident ray (>= 1) */
   float conf_threshold;
   int32_t n_free;          /* free-space samples per confident ray before its interval (>= 0) */
-  int32_t depth_check;     /* nonzero: a ray with observed depth D > 0 keeps its interval only if
-                              near <= D <= far (else plain samples; needs conf_threshold > 0) */
+  int32_t depth_check;     /* nonzero: a confident ray with observed depth D > 0 and D outside
+                              [near, far] has its interval extended to reach D if D lies within
+                              depth_extend of it, and falls back to plain samples otherwise
+                              (needs conf_threshold > 0) */
+  float depth_extend;      /* metres, >= 0 */
 } gosurf_sample_cfg;
 
 /* A ray batch.  Written by gosurf_sample_rays, read by forward/backward.

@@ -324,10 +324,10 @@ __global__ __launch_bounds__(256) void proposal_targets_kernel(TargetArgs A) {
 
 // samples per ray from the confidences, and their exclusive prefix sum (one block)
 // Segment offsets of the proposal-driven batch: ray m gets n_prop samples if
-// its confidence reaches thr, else n_plain.  With depth_check, a ray with an
-// observed depth D > 0 keeps its interval only if near <= D <= far; a rejected
-// ray's confidence is negated in prop3 (thr > 0), which the sample generator
-// reads.  Block b scans rays [8192 b, 8192 (b + 1)): lengths are read
+// its confidence reaches thr, else n_plain.  With depth_check, a confident ray
+// with an observed depth D > 0 outside [near, far] gets its interval extended
+// to D in prop3 if D lies within `extend` of it, and is rejected otherwise: its
+// confidence is negated in prop3 (thr > 0), which the sample generator reads.  Block b scans rays [8192 b, 8192 (b + 1)): lengths are read
 // coalesced into LDS, each thread sums 8 consecutive rays, the 1024 partial
 // sums are scanned in LDS and the chunk-local offsets written out coalesced
 // with the chunk total in block_total[b]; a second pass adds the totals of
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void proposal_targets_kernel(TargetArgs A) {
 constexpr int kSegChunk = 8192;
 __global__ __launch_bounds__(1024) void proposal_seg_local_kernel(float* __restrict__ prop3,
                                                                   const float* __restrict__ depth, int depth_check,
-                                                                  int M, float thr, int n_prop, int n_plain,
+                                                                  float extend, int M, float thr, int n_prop, int n_plain,
                                                                   int* __restrict__ seg, int* __restrict__ block_total) {
   __shared__ int len[kSegChunk];
   __shared__ int part[1024];
@@ -350,10 +350,15 @@ __global__ __launch_bounds__(1024) void proposal_seg_local_kernel(float* __restr
       const float conf = prop3[3 * k + 2];
       bool acc = conf >= thr;
       if (acc && depth_check) {
-        const float D = depth[k];
-        if (D > 0.f && !(prop3[3 * k] <= D && D <= prop3[3 * k + 1])) {
-          acc = false;
-          prop3[3 * k + 2] = -conf;
+        const float D = depth[k], nr = prop3[3 * k], fr = prop3[3 * k + 1];
+        if (D > 0.f && !(nr <= D && D <= fr)) {
+          if (nr - extend <= D && D <= fr + extend) {
+            prop3[3 * k] = fminf(nr, D);
+            prop3[3 * k + 1] = fmaxf(fr, D);
+          } else {
+            acc = false;
+            prop3[3 * k + 2] = -conf;
+          }
         }
       }
       l = acc ? n_prop : n_plain;
@@ -428,10 +433,11 @@ hipError_t launch_proposal_targets(const TargetArgs& a, hipStream_t st) {
 
 // block_total: scratch of ceil(M / 8192) ints (the batch's ray_of, which the
 // sample generator overwrites afterwards)
-hipError_t launch_proposal_seg(float* prop3, const float* depth, int depth_check, int M, float thr, int n_prop,
-                               int n_plain, int* seg, int* block_total, hipStream_t st) {
+hipError_t launch_proposal_seg(float* prop3, const float* depth, int depth_check, float extend, int M, float thr,
+                               int n_prop, int n_plain, int* seg, int* block_total, hipStream_t st) {
   const int nb = (M + kSegChunk - 1) / kSegChunk;
-  hipLaunchKernelGGL(proposal_seg_local_kernel, dim3(nb), dim3(1024), 0, st, prop3, depth, depth_check, M, thr,
+  hipLaunchKernelGGL(proposal_seg_local_kernel, dim3(nb), dim3(1024), 0, st, prop3, depth, depth_check, extend, M,
+                     thr,
                      n_prop, n_plain, seg, block_total);
   hipLaunchKernelGGL(proposal_seg_add_kernel, dim3(nb), dim3(1024), 0, st, M, seg, block_total);
   return hipGetLastError();

@@ -72,6 +72,6 @@ ROOM_PROPOSAL = Workload("room_proposal", "room", (0.03, 0.06, 0.24, 0.96), 2000
                          M=65536, n_strat=64, n_near=32, span="aabb", near=0.1, far=1e9,
                          trunc=0.1, S=16384, precision="bf16", loss_scale=1024.0,
                          extra={"proposal_samples": 24, "free_samples": 0, "conf_threshold": 0.5,
-                                "cover_tol": 0.05, "depth_check": True})
+                                "cover_tol": 0.05, "depth_check": True, "depth_extend": 0.1})
 
 ALL = {w.name: w for w in (SPHERE, ROOM, ROOM_STRESS, ROOM_BF16, ROOM_PROPOSAL)}

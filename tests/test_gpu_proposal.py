@@ -95,31 +95,45 @@ def _uniforms(m, step, stream, n, seed):
     return uniform01(w.reshape(-1))[:n]
 
 
-@pytest.mark.parametrize("n_free,depth_check", [(0, False), (5, False), (5, True)])
-def test_proposal_driven_sampling(n_free, depth_check):
+@pytest.mark.parametrize("n_free,depth_check,extend", [(0, False, 0.0), (5, False, 0.0), (5, True, 0.0),
+                                                       (0, True, 0.3)])
+def test_proposal_driven_sampling(n_free, depth_check, extend):
     G = _G()
     L, fr, b, grid, prop = _room(M=8, seed=7)
     M = 500
     model = G.make_model(L)
     cfg = G.SampleCfg(M, 16, 8, G.SPAN_BOX, 0.1, 1e9, 0.1, 0, 0.004, 99, 3)
     gd, pd = grid.cuda(), prop.cuda()
-    G.set_proposal(cfg, pd, gd, n_proposal=12, conf_threshold=0.5, n_free=n_free, depth_check=depth_check)
+    G.set_proposal(cfg, pd, gd, n_proposal=12, conf_threshold=0.5, n_free=n_free, depth_check=depth_check,
+                   depth_extend=extend)
     batch = G.gosurf_sample_rays(model, fr.to("cuda"), cfg)
     torch.cuda.synchronize()
     p3 = batch.prop.cpu().numpy()
+    from paper_2206_14735_amd.proposal import rays_view
+    raw = G.gosurf_proposal_forward(model, gd, pd, rays_view(batch.o, batch.r), cfg).cpu().numpy()
     seg = batch.seg.cpu().numpy()
     t = batch.t.cpu().numpy()
     conf_ok = p3[:, 2] >= 0.5
     assert 0 < conf_ok.sum() < M      # both branches exercised by the random network
     D = batch.depth.cpu().numpy()
+    assert np.array_equal(np.abs(p3[:, 2]), raw[:, 2])
     if depth_check:
-        # rejected: confident but the observed depth lies outside [near, far]
+        # a confident ray whose observed depth lies outside [near, far] by at
+        # most `extend` has its interval stretched to reach it; further out it
+        # is rejected (confidence negated)
+        conf0 = raw[:, 2] >= 0.5
+        inside = (raw[:, 0] <= D) & (D <= raw[:, 1])
+        near_miss = conf0 & (D > 0) & ~inside & (raw[:, 0] - extend <= D) & (D <= raw[:, 1] + extend)
+        far_miss = conf0 & (D > 0) & ~inside & ~near_miss
         rej = p3[:, 2] <= -0.5
-        outside = (D > 0) & ~((p3[:, 0] <= D) & (D <= p3[:, 1]))
-        assert rej.sum() > 0
-        assert np.all(outside[rej]) and not np.any(outside[conf_ok])
+        assert far_miss.sum() > 0 and np.array_equal(rej, far_miss)
+        assert np.array_equal(p3[near_miss, 0], np.minimum(raw[near_miss, 0], D[near_miss]))
+        assert np.array_equal(p3[near_miss, 1], np.maximum(raw[near_miss, 1], D[near_miss]))
+        assert np.array_equal(p3[~near_miss, :2], raw[~near_miss, :2])
+        if extend > 0:
+            assert near_miss.sum() > 0
     else:
-        assert np.all(p3[:, 2] >= 0)
+        assert np.array_equal(p3, raw)
     lens = np.where(conf_ok, n_free + 12, 24)
     assert np.array_equal(np.diff(seg), lens) and seg[0] == 0
     # plain rays: identical to the plain sampler's rays; confident rays: n_free
