@@ -17,7 +17,7 @@ hipError_t launch_field(const FieldArgs& a, bool bwd, int blocks, hipStream_t st
 hipError_t launch_priv_reduce(const FieldArgs& a, int n_part, const int counts[4], float* tmp, hipStream_t st);
 void plan_privatised_levels(FieldArgs& a, int counts[4]);
 int priv_max_floats();
-int field_blocks(int total, int pairs);
+int field_grid(const FieldArgs& a, bool bwd);
 hipError_t launch_render(const RenderArgs& a, bool bwd, hipStream_t st);
 hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smooth_partial, int n_sp, int S,
                               const float lam[6], float* losses, float* ray_part, hipStream_t st);
@@ -116,7 +116,7 @@ size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Workspace {
   float* ray_partial;     // [M][8]
-  float* smooth_partial;  // [1024]
+  float* smooth_partial;  // [4096]
   float* seed4;           // [total][4]
   float* eikw;            // [total]
   float* ray_dv;          // [M]
@@ -133,7 +133,7 @@ Workspace layout(char* base, int M, int total, int S) {
   size_t off = 0;
   auto take = [&](size_t n) { char* p = base ? base + off : nullptr; off += up(n); return p; };
   w.ray_partial = reinterpret_cast<float*>(take(sizeof(float) * 8 * (size_t)M));
-  w.smooth_partial = reinterpret_cast<float*>(take(sizeof(float) * 1024));
+  w.smooth_partial = reinterpret_cast<float*>(take(sizeof(float) * 4096));
   w.seed4 = reinterpret_cast<float*>(take(sizeof(float) * 4 * (size_t)total));
   w.eikw = reinterpret_cast<float*>(take(sizeof(float) * (size_t)total));
   w.ray_dv = reinterpret_cast<float*>(take(sizeof(float) * (size_t)M));
@@ -309,7 +309,8 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
   if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped
-  const int nb = gs::field_blocks(b->total, fa.S);
+  const int nb = gs::field_grid(fa, false);
+  if (nb <= 0) return fail(GOSURF_ERR_HIP, "field grid: the occupancy query failed");
   mark(GOSURF_KERNEL_FIELD_FWD, true, s);
   if ((st = hip_check(gs::launch_field(fa, false, nb, s), "field fwd")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_FIELD_FWD, false, s);
@@ -370,7 +371,8 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   int counts[4];
   gs::plan_privatised_levels(fa, counts);
   fa.priv_partial = w.priv_partial;
-  const int nb = gs::field_blocks(b->total, fa.S);
+  const int nb = gs::field_grid(fa, true);
+  if (nb <= 0) return fail(GOSURF_ERR_HIP, "field grid: the occupancy query failed");
   mark(GOSURF_KERNEL_FIELD_BWD, true, s);
   if ((st = hip_check(gs::launch_field(fa, true, nb, s), "field bwd")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_FIELD_BWD, false, s);

@@ -218,7 +218,9 @@ constexpr int smem_bytes() {
   constexpr int red = BWD ? kRedFloats * 4 : kWavesPerBlock * 4;
   return (sizeof(FieldSmem<BF, BWD>) > red) ? (int)sizeof(FieldSmem<BF, BWD>) : red;
 }
-constexpr int kPrivMaxFloats = 4096;   // LDS budget for privatised levels (1024 vertices)
+constexpr int kPrivMaxFloats = 4096;
+constexpr int kFieldMaxBlocksFwd = 4096;   // rows of the smoothness partials in the workspace
+constexpr int kFieldMaxBlocksBwd = 2048;   // rows of the decoder / level partials in the workspace   // LDS budget for privatised levels (1024 vertices)
 
 // One wave-tile: MODE 0 = 16 ray samples, MODE 1 = 8 smoothness pairs (lanes
 // j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).
@@ -618,14 +620,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
 }
 
-// blocks of a field launch over `total` ray samples (16 per tile) and `pairs`
-// smoothness pairs (8 per tile); at most 1024 (the workspace's partial rows)
-int field_blocks(int total, int pairs) {
-  const int tiles = (total + 15) / 16 + (pairs + 7) / 8;
-  int blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (blocks > 1024) blocks = 1024;
-  return blocks < 1 ? 1 : blocks;
-}
 
 // sum of the block partials of the privatised levels into the grid gradient
 // (one writer per entry, fixed block order)
@@ -685,8 +679,54 @@ void plan_privatised_levels(FieldArgs& a, int counts[4]) {
 int priv_max_floats() { return kPrivMaxFloats; }
 
 template <bool BWD, bool BF>
+static size_t field_smem(const FieldArgs& a) {
+  return (size_t)smem_bytes<BF, BWD>() + (BWD ? (size_t)a.priv_floats * sizeof(float) : 0);
+}
+
+// Blocks that are resident at once on the current device for this kernel and
+// LDS size (CUs x blocks per CU), queried once per (device, kernel, LDS size).
+template <bool BWD, bool BF>
+static int resident_blocks(size_t smem) {
+  struct Entry { int dev; size_t smem; int blocks; };
+  thread_local Entry cache[8];
+  thread_local int n_cached = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  for (int i = 0; i < n_cached; ++i)
+    if (cache[i].dev == dev && cache[i].smem == smem) return cache[i].blocks;
+  const void* fn = reinterpret_cast<const void*>(&field_kernel<BWD, BF>);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 0;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, smem) != hipSuccess) return 0;
+  const int blocks = cus * (per_cu > 0 ? per_cu : 1);
+  if (n_cached < 8) cache[n_cached++] = Entry{dev, smem, blocks};
+  return blocks;
+}
+
+// Grid of a field launch over `total` ray samples (16 per tile) and `S` pairs
+// (8 per tile): one block per 4 tiles, at most one resident round (the tile
+// loop covers the rest; a partial second round leaves the machine half
+// empty), and at most the workspace's partial rows.  0 on a HIP error.
+int field_grid(const FieldArgs& a, bool bwd) {
+  const bool bf = a.grid_bf16 != nullptr;
+  const int tiles = (a.total + 15) / 16 + (a.S + 7) / 8;
+  int blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  int resident;
+  if (bwd) resident = bf ? resident_blocks<true, true>(field_smem<true, true>(a))
+                         : resident_blocks<true, false>(field_smem<true, false>(a));
+  else resident = bf ? resident_blocks<false, true>(field_smem<false, true>(a))
+                     : resident_blocks<false, false>(field_smem<false, false>(a));
+  if (resident <= 0) return 0;
+  const int cap = bwd ? kFieldMaxBlocksBwd : kFieldMaxBlocksFwd;
+  if (blocks > resident) blocks = resident;
+  if (blocks > cap) blocks = cap;
+  return blocks < 1 ? 1 : blocks;
+}
+
+template <bool BWD, bool BF>
 static hipError_t launch_field_t(const FieldArgs& a, int blocks, hipStream_t st) {
-  const size_t smem = (size_t)smem_bytes<BF, BWD>() + (BWD ? (size_t)a.priv_floats * sizeof(float) : 0);
+  const size_t smem = field_smem<BWD, BF>(a);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<BWD, BF>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
