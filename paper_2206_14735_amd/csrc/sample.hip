@@ -174,6 +174,26 @@ __global__ __launch_bounds__(256) void sample_rays_kernel(SampleArgs A) {
   }
 }
 
+// Rays only (proposal mode, before the proposal runs): one thread per ray picks
+// the pixel and writes the ray, its colour and depth, exactly as the
+// wave-per-ray kernel does.
+__global__ __launch_bounds__(256) void sample_pixels_kernel(SampleArgs A) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= A.M) return;
+  const unsigned long long thw = (unsigned long long)A.T * A.H * A.W;
+  const U4 w0 = philox((uint32_t)m, A.step, 0u, 0u, A.k0, A.k1);
+  const unsigned long long pix = pick_pixel(w0.x, thw);
+  const PixelRay pr = pixel_ray(A, pix);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    A.o[3 * m + a] = pr.o[a];
+    A.r[3 * m + a] = pr.r[a];
+    A.rgb_out[3 * m + a] = (float)A.rgb[3 * pix + a] / 255.f;
+  }
+  A.depth_out[m] = A.depth[pix];
+  if (A.pixel) A.pixel[m] = (long long)pix;
+}
+
 // One thread per smoothness pair.
 __global__ __launch_bounds__(256) void sample_points_kernel(SampleArgs A) {
   const int p = blockIdx.x * 256 + threadIdx.x;
@@ -218,7 +238,7 @@ hipError_t launch_sample(const SampleArgs& a, hipStream_t st) {
 
 // proposal mode: rays first, then (after inference and the seg scan) samples
 hipError_t launch_sample_rays_only(const SampleArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((sample_rays_kernel<true, false>), dim3((a.M + 3) / 4), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(sample_pixels_kernel, dim3((a.M + 255) / 256), dim3(256), 0, st, a);
   if (a.S > 0) hipLaunchKernelGGL(sample_points_kernel, dim3((a.S + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();
 }
