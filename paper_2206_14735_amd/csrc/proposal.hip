@@ -47,11 +47,18 @@ __device__ float prop_table_value(const float* __restrict__ P, int slot, int l) 
   }
 }
 
+// only the training form transposes operands through the per-wave scratch
+template <bool TRAIN>
 struct PropSmem {
   float tab[PT_END * 64];
   float bias[64 + 64 + 16];
-  float scr[kWavesPerBlock][2 * 64 * RSR];
+  float scr[kWavesPerBlock][TRAIN ? 2 * 64 * RSR : 1];
 };
+template <bool TRAIN>
+constexpr size_t prop_smem_bytes() {
+  return (TRAIN && sizeof(PropSmem<TRAIN>) < (kPropNumel + 1) * sizeof(float)) ? (kPropNumel + 1) * sizeof(float)
+                                                                               : sizeof(PropSmem<TRAIN>);
+}
 
 __device__ __forceinline__ float smooth_l1_grad(float x, float beta) {
   return fabsf(x) < beta ? x / beta : (x > 0.f ? 1.f : -1.f);
@@ -67,7 +74,7 @@ __device__ __forceinline__ float smooth_l1(float x, float beta) {
 template <bool TRAIN>
 __global__ __launch_bounds__(kBlock) void proposal_kernel(PropArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  PropSmem& sm = *reinterpret_cast<PropSmem*>(smem_raw);
+  PropSmem<TRAIN>& sm = *reinterpret_cast<PropSmem<TRAIN>*>(smem_raw);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
   for (int e = tid; e < PT_END * 64; e += kBlock) sm.tab[e] = prop_table_value(A.prop, e >> 6, e & 63);
@@ -77,8 +84,8 @@ __global__ __launch_bounds__(kBlock) void proposal_kernel(PropArgs A) {
   }
   if (tid < 16) sm.bias[128 + tid] = tid < 3 ? A.prop[pQ3 + tid] : 0.f;
   __syncthreads();
-  float* scrA = sm.scr[wave];
-  float* scrB = sm.scr[wave] + 64 * RSR;
+  float* scrA = TRAIN ? sm.scr[wave] : nullptr;
+  float* scrB = TRAIN ? sm.scr[wave] + 64 * RSR : nullptr;
 
   v4f aP1[12], aP2[16], aP3[4], gq1[4], gq2[4], gq3;
   if (TRAIN) {
@@ -411,19 +418,18 @@ int proposal_blocks(int M) {
   return blocks < 1 ? 1 : blocks;
 }
 
-hipError_t launch_proposal(const PropArgs& a, bool train, int blocks, hipStream_t st) {
-  const size_t smem = sizeof(PropSmem) > (kPropNumel + 1) * sizeof(float) ? sizeof(PropSmem)
-                                                                          : (kPropNumel + 1) * sizeof(float);
-  if (train) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&proposal_kernel<true>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    hipLaunchKernelGGL(proposal_kernel<true>, dim3(blocks), dim3(kBlock), smem, st, a);
-  } else {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&proposal_kernel<false>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    hipLaunchKernelGGL(proposal_kernel<false>, dim3(blocks), dim3(kBlock), smem, st, a);
-  }
+template <bool TRAIN>
+static hipError_t launch_proposal_t(const PropArgs& a, int blocks, hipStream_t st) {
+  const size_t smem = prop_smem_bytes<TRAIN>();
+  const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&proposal_kernel<TRAIN>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(proposal_kernel<TRAIN>, dim3(blocks), dim3(kBlock), smem, st, a);
   return hipGetLastError();
+}
+
+hipError_t launch_proposal(const PropArgs& a, bool train, int blocks, hipStream_t st) {
+  return train ? launch_proposal_t<true>(a, blocks, st) : launch_proposal_t<false>(a, blocks, st);
 }
 
 hipError_t launch_proposal_targets(const TargetArgs& a, hipStream_t st) {
