@@ -330,10 +330,14 @@ __global__ __launch_bounds__(256) void loss_final_kernel(const float* __restrict
     if (threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
     __syncthreads();
   }
+  // block partials: lane b of wave 0 holds block b's row (nb <= 64), summed
+  // over the wave in a fixed order
+  float col[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) col[c] = wave_sum_dpp((int)threadIdx.x < nb ? part[8 * threadIdx.x + c] : 0.f);
+  }
   if (threadIdx.x == 0) {
-    float col[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int b = 0; b < nb; ++b)
-      for (int c = 0; c < 6; ++c) col[c] += part[8 * b + c];
     const float invM = 1.f / (float)M;
     const float nd = col[5];
     const float L[6] = {col[0] * invM, nd > 0.f ? col[1] / nd : 0.f, col[2] * invM,
@@ -379,12 +383,11 @@ __global__ __launch_bounds__(256) void grad_stage2_kernel(const float* __restric
                                                           int nb, float* __restrict__ grad_mlp) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= kMlpNumel) return;
-  if (e == oV) {
-    float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += dv_part[8 * b];
-    grad_mlp[oV] += s;
-    return;
+  if (blockIdx.x == 0 && threadIdx.x < 64) {   // wave 0 of block 0: the nb <= 64 dL/dv partials
+    const float s = wave_sum_dpp((int)threadIdx.x < nb ? dv_part[8 * threadIdx.x] : 0.f);
+    if (threadIdx.x == 0) grad_mlp[oV] += s;
   }
+  if (e == oV) return;
   grad_mlp[e] += colsum_stage2(tmp, kMlpNumel, e);
 }
 
