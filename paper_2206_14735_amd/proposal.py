@@ -1,4 +1,4 @@
-"""Training driver of the learned proposal sampler over the C ABI.
+"""Training loop of the learned proposal sampler over the C ABI.
 
 Logs per-ray weight distributions from plain forward passes, turns them into
 interval targets with gosurf_proposal_targets, and trains the proposal

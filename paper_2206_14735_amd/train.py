@@ -1,4 +1,4 @@
-"""Device-resident optimisation driver over the C ABI.
+"""Device-resident optimisation loop over the C ABI.
 
 Owns the grid and decoder parameters, their gradients, the Adam moments, a
 ray batch, the forward outputs and the workspace, all allocated once on the

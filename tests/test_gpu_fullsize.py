@@ -155,7 +155,7 @@ def test_gradients_match_central_differences_on_the_device(room_full):
     # The loss is piecewise smooth (ReLU, |.|, max, the alpha clamp): a probe
     # whose +-h moves many samples across a kink (coarse-level features, first-
     # layer weights) gives a difference quotient that is no derivative.  A probe
-    # is judged when the quotients at h and h/2 agree to 1 %; most must be.
+    # is counted when the quotients at h and h/2 agree to 1 %; most must be.
     stable, bad = 0, 0
     for fd, i, an in probes:
         f1, f2 = fd(i, h), fd(i, h / 2)

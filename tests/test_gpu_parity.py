@@ -199,3 +199,24 @@ def test_adam_matches_oracle():
     u = f.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
     rne = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF
     assert torch.equal(bf.cpu().to(torch.int64) & 0xFFFF, rne)
+
+
+def test_autograd_function_matches_direct_calls():
+    """loss.backward() through the autograd wrapper gives the library's own
+    gradients, scaled by the incoming gradient."""
+    G = _G()
+    from paper_2206_14735_amd.autograd import gosurf_loss
+    L, fr, b, grid, mlp = sphere_case(M=256, S=512, grid_std=0.3)
+    model = G.make_model(L)
+    db = G.RayBatch.from_host(b)
+    lc = G.make_loss_cfg(LAMBDAS)
+    ws = G.workspace_for(model, db.M, db.total, db.S)
+    g = grid.cuda().requires_grad_(True)
+    m = mlp.cuda().requires_grad_(True)
+    loss = gosurf_loss(g, m, model, db, lc, ws)
+    (3.0 * loss).backward()
+    torch.cuda.synchronize()
+    ref = run_device(L, b, grid, mlp)
+    assert abs(float(loss) - ref["losses"][6]) <= 1e-6 * abs(ref["losses"][6])
+    check_close("grad_mlp", m.grad.cpu().numpy() / 3.0, ref["grad_mlp"], GRAD_TOL)
+    check_close("grad_grid", g.grad.cpu().numpy() / 3.0, ref["grad_grid"], GRAD_TOL, max_bad_frac=0.002)
