@@ -111,10 +111,11 @@ def test_loss_scale_and_disabled_terms():
 
 
 def test_variable_length_rays_and_no_smoothness():
-    # rays of 1, 3, 63, 64, 65, 127, 200 and 256 samples (chunk boundaries of the
-    # per-ray scan), some leaving the grid box; no smoothness pairs
-    L, fr, b0, grid, mlp = sphere_case(M=8, S=0, grid_std=0.3)
-    lens = np.array([1, 3, 63, 64, 65, 127, 200, 256])
+    # rays of 1, 0, 3, 63, 64, 65, 127, 200 and 256 samples (an empty ray and the
+    # chunk boundaries of the per-ray scan), some leaving the grid box; no
+    # smoothness pairs
+    L, fr, b0, grid, mlp = sphere_case(M=9, S=0, grid_std=0.3)
+    lens = np.array([1, 0, 3, 63, 64, 65, 127, 200, 256])
     seg = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
     rng = np.random.default_rng(9)
     t = np.concatenate([np.sort(rng.uniform(0.1, 3.0, n)) for n in lens]).astype(np.float32)
