@@ -157,7 +157,8 @@ typedef struct {
    GOSURF_MAX_SAMPLES_PER_RAY per ray; ray_of[s] is the ray of sample s. */
 typedef struct {
   int32_t M;            /* rays */
-  int32_t total;        /* samples, = seg[M] */
+  int32_t total;        /* samples, = seg[M]; with a proposal the capacity (seg[M], on the
+                           device, is then the actual count) */
   int32_t S;            /* smoothness pairs */
   float* o;             /* [M][3] ray origin (camera centre) */
   float* r;             /* [M][3] ray direction (camera-z component 1) */
@@ -248,7 +249,10 @@ int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg);
    stratified samples.  A smoothness point tries up to 8 pixels and keeps the
    first with depth, at depth D + (2u - 1) trunc along its ray; eps is delta_s
    times a uniform unit vector; with no valid pixel the point is the box
-   centre with eps = 0.  Errors: NULL, SHAPE (sizes, T*H*W >= 2^32), VALUE. */
+   centre with eps = 0.  With a proposal (see gosurf_sample_cfg) the rays are
+   drawn first, the proposal runs on them, the depth check and the segment
+   offsets follow on the device, and then each ray's samples are written.
+   Errors: NULL, SHAPE (sizes, T*H*W >= 2^32), VALUE. */
 gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames* frames,
                                  const gosurf_sample_cfg* cfg, gosurf_ray_batch* out,
                                  void* stream);
