@@ -191,7 +191,7 @@ def compare(a, G, synth, Reconstruction, torch):
         evaluator.grid, evaluator.mlp = grid, mlp
         evaluator.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr, n_free=n_free,
                                depth_check=depth_check, depth_extend=depth_extend)
-        errs, spr, conf = [], [], []
+        errs, spr, conf, net_conf = [], [], [], []
         for k in range(n_batches):
             evaluator.it = 300_000 + k
             evaluator.sample()
@@ -201,11 +201,13 @@ def compare(a, G, synth, Reconstruction, torch):
             spr.append(evaluator.batch.n_samples() / M)
             if proposal is not None:
                 conf.append((evaluator.batch.prop[:, 2] >= thr).float().mean().item())
+                net_conf.append((evaluator.batch.prop[:, 2].abs() >= thr).float().mean().item())
         e = torch.cat(errs)
         out = {"depth_l1_mm": {"mean": round(1e3 * e.mean().item(), 3), "median": round(1e3 * e.median().item(), 3)},
                "samples_per_ray": round(sum(spr) / len(spr), 2)}
         if conf:
             out["confident_fraction"] = round(sum(conf) / len(conf), 4)
+            out["network_confident_fraction"] = round(sum(net_conf) / len(net_conf), 4)
         return out
 
     def run(rec, steps):
