@@ -136,6 +136,15 @@ __device__ __forceinline__ void atomic_add_lds(float* p, float v) {
   __hip_atomic_fetch_add((lds_float*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Wait until at most N vector-memory operations of this wave are outstanding
+// (s_waitcnt: vmcnt in bits 3:0 and 15:14; expcnt and lgkmcnt at their
+// maxima, so they are not waited on).
+template <int N>
+__device__ __forceinline__ void wait_vmem_at_most() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

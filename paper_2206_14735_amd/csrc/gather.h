@@ -13,22 +13,55 @@ struct LevelSample {
   float inv_v;
 };
 
-__device__ __forceinline__ void locate(const Grid& g, int q, float x, float y, float z, LevelSample& ls) {
+// Sizes of the grid level one lane works on.  The by-value grid description
+// lives in the kernel-argument segment; indexing its per-level arrays with a
+// per-lane level makes the compiler read them from memory at every use, and
+// such a read waits for all earlier memory operations of the wave (the
+// scatter's atomics included, which share the vector-memory counter).  So each
+// entry is read once as a wave-uniform scalar and the lane's value selected in
+// registers.
+struct LevelConst {
+  int n[3];
+  float voxel;
+  long long off;
+};
+
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int pick_level(const int (&a)[4], int q) {
+  const int v0 = uniform_i(a[0]), v1 = uniform_i(a[1]), v2 = uniform_i(a[2]), v3 = uniform_i(a[3]);
+  return q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3;
+}
+
+__device__ __forceinline__ LevelConst level_const(const Grid& g, int q) {
+  LevelConst c;
+  c.n[0] = pick_level(g.nx, q);
+  c.n[1] = pick_level(g.ny, q);
+  c.n[2] = pick_level(g.nz, q);
+  const int vb[4] = {__float_as_int(g.voxel[0]), __float_as_int(g.voxel[1]), __float_as_int(g.voxel[2]),
+                     __float_as_int(g.voxel[3])};
+  c.voxel = __int_as_float(pick_level(vb, q));
+  const int lo[4] = {(int)g.off[0], (int)g.off[1], (int)g.off[2], (int)g.off[3]};
+  const int hi[4] = {(int)(g.off[0] >> 32), (int)(g.off[1] >> 32), (int)(g.off[2] >> 32), (int)(g.off[3] >> 32)};
+  c.off = (long long)(((unsigned long long)(unsigned)pick_level(hi, q) << 32) | (unsigned)pick_level(lo, q));
+  return c;
+}
+
+__device__ __forceinline__ void locate(const Grid& g, const LevelConst& lc, float x, float y, float z,
+                                       LevelSample& ls) {
   const float xyz[3] = {x, y, z};
-  const int n[3] = {g.nx[q], g.ny[q], g.nz[q]};
-  const float v = g.voxel[q];
+  const float v = lc.voxel;
   int i0[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     float u = (xyz[a] - g.p0[a]) / v;
     int c = (int)floorf(u);
-    c = c < 0 ? 0 : (c > n[a] - 2 ? n[a] - 2 : c);
+    c = c < 0 ? 0 : (c > lc.n[a] - 2 ? lc.n[a] - 2 : c);
     i0[a] = c;
     ls.f[a] = u - (float)c;
   }
-  ls.sy = n[0];
-  ls.sz = n[0] * n[1];
-  ls.row = g.off[q] + ((long long)i0[2] * n[1] + i0[1]) * n[0] + i0[0];
+  ls.sy = lc.n[0];
+  ls.sz = lc.n[0] * lc.n[1];
+  ls.row = lc.off + ((long long)i0[2] * lc.n[1] + i0[1]) * lc.n[0] + i0[0];
   ls.inv_v = 1.f / v;
 }
 

@@ -100,6 +100,7 @@ __global__ __launch_bounds__(kBlock) void proposal_kernel(PropArgs A) {
   float loss_acc = 0.f;
   const float invM = 1.f / (float)A.M;
   const int n_tiles = (A.M + 15) / 16;
+  const LevelConst lc = level_const(A.g, kPropLevel);
 
   for (int tile = blockIdx.x * kWavesPerBlock + wave; tile < n_tiles; tile += gridDim.x * kWavesPerBlock) {
     const int m = tile * 16 + j;
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void proposal_kernel(PropArgs A) {
       const float px = mad_norm(tb, r[0], o[0]), py = mad_norm(tb, r[1], o[1]), pz = mad_norm(tb, r[2], o[2]);
       const bool ok = live && inside_box(A.g, px, py, pz);
       LevelSample ls;
-      locate(A.g, kPropLevel, px, py, pz, ls);
+      locate(A.g, lc, px, py, pz, ls);
       float z[4], G[4][3];
       interp<false, false>(A.grid, nullptr, ls, ok, z, G);
       in[h] = v4f{z[0], z[1], z[2], z[3]};
