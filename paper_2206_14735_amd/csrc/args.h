@@ -27,7 +27,8 @@ struct FieldArgs {
   float* smooth_partial;  // [gridDim.x]
   // backward
   const float* seed4;     // [total][4] dL/dphi, dL/dc (scaled)
-  const float* eikw;      // [total] Eikonal weight (scaled), 0 outside S_fs
+  const float* posw;      // [total][4]: sample position (as the forward computed it), Eikonal
+                          // weight (scaled, 0 outside S_fs)
   float smooth_coef;      // 2 * lambda_smooth * loss_scale / S
   float* grad_grid;       // [V][4]
   float* mlp_partial;     // [gridDim.x][kMlpNumel]
@@ -65,7 +66,7 @@ struct RenderArgs {
   const float* n_depth_rays;  // device scalar (losses[7])
   float loss_scale;
   float* seed4;         // [total][4]
-  float* eikw;          // [total]
+  float* posw;          // [total][4]: sample position, Eikonal weight
   float* ray_dv;        // [M]
 };
 

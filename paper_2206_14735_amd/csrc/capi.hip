@@ -118,7 +118,7 @@ struct Workspace {
   float* ray_partial;     // [M][8]
   float* smooth_partial;  // [4096]
   float* seed4;           // [total][4]
-  float* eikw;            // [total]
+  float* posw;            // [total][4]: sample position, Eikonal weight
   float* ray_dv;          // [M]
   float* mlp_partial;     // [2048][kMlpNumel]
   float* priv_partial;    // [2048][priv_max_floats]
@@ -135,7 +135,7 @@ Workspace layout(char* base, int M, int total, int S) {
   w.ray_partial = reinterpret_cast<float*>(take(sizeof(float) * 8 * (size_t)M));
   w.smooth_partial = reinterpret_cast<float*>(take(sizeof(float) * 4096));
   w.seed4 = reinterpret_cast<float*>(take(sizeof(float) * 4 * (size_t)total));
-  w.eikw = reinterpret_cast<float*>(take(sizeof(float) * (size_t)total));
+  w.posw = reinterpret_cast<float*>(take(sizeof(float) * 4 * (size_t)total));
   w.ray_dv = reinterpret_cast<float*>(take(sizeof(float) * (size_t)M));
   w.mlp_partial = reinterpret_cast<float*>(take(sizeof(float) * 2048 * (size_t)gs::kMlpNumel));
   w.priv_partial = reinterpret_cast<float*>(take(sizeof(float) * 2048 * (size_t)gs::priv_max_floats()));
@@ -356,7 +356,7 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs;
   for (int k = 0; k < 6; ++k) ra.lam[k] = loss->lambda[k];
   ra.n_depth_rays = fwd->losses + 7;
-  ra.loss_scale = loss_scale; ra.seed4 = w.seed4; ra.eikw = w.eikw; ra.ray_dv = w.ray_dv;
+  ra.loss_scale = loss_scale; ra.seed4 = w.seed4; ra.posw = w.posw; ra.ray_dv = w.ray_dv;
   if ((st = hip_check(gs::launch_render(ra, true, s), "render bwd")) != GOSURF_OK) return st;
 
   gs::FieldArgs fa{};
@@ -364,7 +364,7 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   fa.grid_bf16 = model->precision == GOSURF_BF16 ? params->grid_bf16 : nullptr;
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
-  fa.seed4 = w.seed4; fa.eikw = w.eikw; fa.need_gx = need_gx;
+  fa.seed4 = w.seed4; fa.posw = w.posw; fa.need_gx = need_gx;
   fa.grad_grid = grads->grid; fa.mlp_partial = w.mlp_partial;
   fa.smooth_coef = b->S > 0 ? 2.f * loss->lambda[5] * loss_scale / (float)b->S : 0.f;
   if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped

@@ -86,17 +86,16 @@ __device__ __forceinline__ void layer(const Smem& sm, int base, const v4f* in, v
 
 // One step of the segmented sum inside a 16-lane level group: lanes of the
 // same run (equal cell) add their right neighbour's partial at distance D.
+// The partial is taken as a multiply by 0 or 1, which folds into one
+// v_fmac_f32 with a DPP source per value (the values are finite).
 template <int CTRL, int D>
 __device__ __forceinline__ void run_step(float (&val)[8][4], int segid, int j) {
   const int so = dpp_i<CTRL>(segid);
-  const bool take = (j + D < 16) && so == segid;
+  const float take = (j + D < 16) && so == segid ? 1.f : 0.f;
 #pragma unroll
   for (int c = 0; c < 8; ++c)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float o = dpp_f<CTRL>(val[c][k]);
-      val[c][k] += take ? o : 0.f;
-    }
+    for (int k = 0; k < 4; ++k) val[c][k] = fmaf(dpp_f<CTRL>(val[c][k]), take, val[c][k]);
 }
 
 // Per-wave LDS staging of the scatter: 64 lanes x 32 floats, the head list
@@ -124,7 +123,15 @@ template <bool HAS_DZ, bool HAS_GV>
 __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const ScatterStage& S, int lane, int q,
                                         int j, const LevelSample& ls, long long go, int po, bool valid,
                                         const float dz[4], const float a[4], const float gv[3]) {
-  const float fx = ls.f[0], fy = ls.f[1], fz = ls.f[2];
+  // an invalid lane's inputs are zeroed (and its weights kept finite), so
+  // its 32 values are exact zeros
+  const float fx = valid ? ls.f[0] : 0.f, fy = valid ? ls.f[1] : 0.f, fz = valid ? ls.f[2] : 0.f;
+  float dzv[4], av[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    dzv[k] = valid ? dz[k] : 0.f;
+    av[k] = valid ? a[k] : 0.f;
+  }
   float val[8][4];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -140,9 +147,9 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const S
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       float v = 0.f;
-      if (HAS_DZ) v += w * dz[k];
-      if (HAS_GV) v += a[k] * jg;
-      val[c][k] = valid ? v : 0.f;
+      if (HAS_DZ) v += w * dzv[k];
+      if (HAS_GV) v += av[k] * jg;
+      val[c][k] = v;
     }
   }
   // runs of equal cells (invalid lanes form runs of their own and never write)
@@ -237,16 +244,25 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
   int item;
   float px, py, pz;
   bool live;
+  float4 seed_in = make_float4(0.f, 0.f, 0.f, 0.f);   // backward: dL/dphi, dL/dc of the sample
+  float ew_in = 0.f;                                   // backward: its Eikonal weight
   if (MODE == 0) {
     item = tile * 16 + j;
     live = item < total;
     px = py = pz = 0.f;
     if (live) {
-      const int ray = A.ray_of[item];
-      const float tt = A.t[item];
-      px = mad_norm(tt, A.r[3 * ray + 0], A.o[3 * ray + 0]);
-      py = mad_norm(tt, A.r[3 * ray + 1], A.o[3 * ray + 1]);
-      pz = mad_norm(tt, A.r[3 * ray + 2], A.o[3 * ray + 2]);
+      if constexpr (BWD) {
+        // position and seeds in one round of independent loads
+        const float4 p4 = *reinterpret_cast<const float4*>(A.posw + 4 * (size_t)item);
+        seed_in = *reinterpret_cast<const float4*>(A.seed4 + 4 * (size_t)item);
+        px = p4.x; py = p4.y; pz = p4.z; ew_in = p4.w;
+      } else {
+        const int ray = A.ray_of[item];
+        const float tt = A.t[item];
+        px = mad_norm(tt, A.r[3 * ray + 0], A.o[3 * ray + 0]);
+        py = mad_norm(tt, A.r[3 * ray + 1], A.o[3 * ray + 1]);
+        pz = mad_norm(tt, A.r[3 * ray + 2], A.o[3 * ray + 2]);
+      }
     }
   } else {
     const int pair = tile * 8 + (j & 7);
@@ -344,12 +360,8 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
   // ================================================================ backward
   float gv[3] = {0.f, 0.f, 0.f};   // dL / d(grad phi)
   if (MODE == 0) {
-    float4 sd = make_float4(0.f, 0.f, 0.f, 0.f);
-    float ew = 0.f;
-    if (live && valid) {
-      sd = *reinterpret_cast<const float4*>(A.seed4 + 4 * (size_t)item);
-      if (A.need_gx) ew = A.eikw[item];
-    }
+    const float4 sd = valid ? seed_in : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float ew = valid && A.need_gx ? ew_in : 0.f;
     if (A.need_gx && ew != 0.f) {
       const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
       const float c = n > 0.f ? ew * 2.f * (n - 1.f) / n : 0.f;

@@ -13,6 +13,7 @@ namespace gs {
 struct RayState {
   int n, s0;
   float s;              // sharpness
+  float o[3], r[3];     // ray origin and direction
   float D, I[3];
   float phi[kChunks], tt[kChunks], col[kChunks][3];
   bool valid[kChunks];
@@ -26,6 +27,8 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
   R.s = __expf(10.f * A.mlp[oV]);
   const float ox = A.o[3 * m], oy = A.o[3 * m + 1], oz = A.o[3 * m + 2];
   const float rx = A.r[3 * m], ry = A.r[3 * m + 1], rz = A.r[3 * m + 2];
+  R.o[0] = ox; R.o[1] = oy; R.o[2] = oz;
+  R.r[0] = rx; R.r[1] = ry; R.r[2] = rz;
   R.D = A.depth[m];
   R.I[0] = A.rgb[3 * m]; R.I[1] = A.rgb[3 * m + 1]; R.I[2] = A.rgb[3 * m + 2];
 #pragma unroll
@@ -274,7 +277,12 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
       float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
       if (R.valid[c]) out = make_float4(dphi * sc, gc[0] * wk * sc, gc[1] * wk * sc, gc[2] * wk * sc);
       *reinterpret_cast<float4*>(A.seed4 + 4 * sidx) = out;
-      A.eikw[sidx] = R.valid[c] ? ew * sc : 0.f;
+      // the position again (same rounding as the forward), so that the field
+      // backward reads it with the seeds instead of through ray_of, t, o, r
+      const float tt = R.tt[c];
+      *reinterpret_cast<float4*>(A.posw + 4 * sidx) =
+          make_float4(mad_norm(tt, R.r[0], R.o[0]), mad_norm(tt, R.r[1], R.o[1]), mad_norm(tt, R.r[2], R.o[2]),
+                      R.valid[c] ? ew * sc : 0.f);
     }
   }
   dv_acc = wave_sum_dpp(dv_acc);
