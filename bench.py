@@ -46,17 +46,28 @@ def parse():
     return ap.parse_args()
 
 
-# Algorithmic bytes per unit of work of the timed kernels (FP32).  The field
-# kernels process ray samples and smoothness pairs in one launch:
-#   backward, per sample: 4 levels x 8 corners x 16 B gathered (512 B) + 128
-#   float atomic adds of 4 B (512 B) + backward seeds (20 B) + depth and ray
-#   index (8 B) = 1052 B; per pair: two points of 512 B gathered + 512 B
-#   atomics + 12 B position / perturbation = 2072 B;
-#   forward, per sample: 512 B gathered + 8 B in + 20 B out = 540 B; per pair:
-#   two points of 512 B gathered + 12 B = 1048 B;
+# Algorithmic bytes per unit of work of the timed kernels.  The field kernels
+# process ray samples and smoothness pairs in one launch; a corner is 16 B in
+# FP32 and 8 B when the gathers read the bfloat16 mirror (BF16 workloads), so
+# one point's 4 levels x 8 corners are g = 512 B (256 B BF16):
+#   backward, per sample: g gathered + 128 float atomic adds of 4 B (512 B) +
+#   seeds (16 B) + position and Eikonal weight (16 B) = 1056 B (800 B BF16);
+#   per pair: 2 g + 2 x 512 B atomics + position and perturbation (24 B)
+#   = 2072 B (1560 B BF16);
+#   forward, per sample: g + t and ray index (8 B) + outputs (20 B) = 540 B
+#   (284 B BF16); per pair: 2 g + 24 B = 1048 B (536 B BF16);
 #   Adam, per parameter: p, g, m, v read and written (32 B).
-BYTES_PER_SAMPLE = {"field_bwd": 1052.0, "field_fwd": 540.0}
-BYTES_PER_PAIR = {"field_bwd": 2072.0, "field_fwd": 1048.0}
+CORNER_BYTES = {"fp32": 16.0, "bf16": 8.0}
+
+
+def field_unit_bytes(kernel, precision):
+    """(bytes per ray sample, bytes per smoothness pair) of one field kernel."""
+    g = 32 * CORNER_BYTES[precision]            # 4 levels x 8 corners
+    if kernel == "field_bwd":
+        return g + 512.0 + 32.0, 2 * g + 1024.0 + 24.0
+    return g + 28.0, 2 * g + 24.0
+
+
 BYTES_PER_PARAM_ADAM = 32.0
 
 
@@ -368,7 +379,8 @@ def main():
     pairs = w.S
 
     def field_bytes(k):
-        return BYTES_PER_SAMPLE[k] * samples_now + BYTES_PER_PAIR[k] * pairs
+        per_sample, per_pair = field_unit_bytes(k, w.precision)
+        return per_sample * samples_now + per_pair * pairs
 
     roofs = {
         "field_bwd": roofline("field_bwd", field_bytes("field_bwd"), kern["field_bwd"],

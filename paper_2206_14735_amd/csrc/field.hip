@@ -119,7 +119,8 @@ struct ScatterStage {
 // 3. Small levels go to the block's LDS copy, the others to HBM.  The
 //    writers compute their segments' destinations, so the atomic loop reads
 //    only LDS (po >= 0: this lane's level has its LDS copy at float offset po).
-template <bool HAS_DZ, bool HAS_GV>
+// BF: the BF16 kernel (decoders in bf16), which keeps fewer atomics in flight.
+template <bool HAS_DZ, bool HAS_GV, bool BF>
 __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const ScatterStage& S, int lane, int q,
                                         int j, const LevelSample& ls, long long go, int po, bool valid,
                                         const float dz[4], const float a[4], const float gv[3]) {
@@ -185,12 +186,14 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const S
   const int f = lane & 7;
   for (int base = 0; base < jobs; base += 8) {
     const int k = base + (lane >> 3);
-    // At most two atomic instructions of this wave in flight: issued back to
-    // back, a tile's atomics queue in the L2 ahead of the other waves' gathers
-    // (measured on MI355X: 0.43 ms unthrottled, 0.44 ms with one and 0.39 ms
-    // with two in flight on the room batch in FP32; 3.58 / 3.17 / 3.17 ms at
-    // 65536 rays in BF16; four in flight: 0.39 / 3.37 ms).
-    wait_vmem_at_most<1>();
+    // At most two (FP32) or one (BF16) atomic instructions of this wave in
+    // flight: issued back to back, a tile's atomics queue in the memory system
+    // ahead of the other waves' gathers.  Measured on MI355X, backward kernel
+    // on the room batch in FP32: 0.43 ms unthrottled, 0.44 ms with one, 0.39
+    // ms with two, 0.39 ms with four in flight; at 65536 rays in BF16, whose
+    // decoders take less time per tile: 3.13 ms with one, 3.30 ms with two.
+    if constexpr (BF) wait_vmem_at_most<0>();
+    else wait_vmem_at_most<1>();
     if (k < jobs) {
       const int h = S.heads[k >> 2], sg = k & 3;
       const float v = S.val[h * 32 + 8 * sg + f];
@@ -457,10 +460,10 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
       rows_to_lanes<1>(scrB, &qv, tY, q, j);
       outer_lanes<BF, 2, 1>(tX, tY, aW1);
       const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
-      scatter<true, true>(A, priv, stage, lane, q, j, ls, lc.off, po, valid, dzl, al, gv);
+      scatter<true, true, BF>(A, priv, stage, lane, q, j, ls, lc.off, po, valid, dzl, al, gv);
     } else {
       const float al[4] = {0, 0, 0, 0};
-      scatter<true, false>(A, priv, stage, lane, q, j, ls, lc.off, po, valid, dzl, al, gv);
+      scatter<true, false, BF>(A, priv, stage, lane, q, j, ls, lc.off, po, valid, dzl, al, gv);
     }
   } else {
     // smoothness pair: d|g(x) - g(x+eps)|^2 / dg at either point is
@@ -493,7 +496,7 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
     outer_lanes<BF, 2, 1>(tX, tY, aW1);
     const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
     const float dzl[4] = {0, 0, 0, 0};
-    scatter<false, true>(A, priv, stage, lane, q, j, ls, lc.off, po, pv, dzl, al, gv);
+    scatter<false, true, BF>(A, priv, stage, lane, q, j, ls, lc.off, po, pv, dzl, al, gv);
   }
   }
 }
