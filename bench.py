@@ -59,6 +59,26 @@ def parse():
 #   Adam, per parameter: p, g, m, v read and written (32 B).
 CORNER_BYTES = {"fp32": 16.0, "bf16": 8.0}
 
+# Algorithmic decoder FLOPs of the field kernels (2 per multiply-add; the
+# 16-32-32-16 geometry and 15-32-3 colour decoders of Sec. 3.1):
+#   forward, per sample: geometry 4096 + colour 1152, plus 3072 for d(phi)/dz
+#   through W3 row 0, W2^T and W1^T when the Eikonal term is on; per pair
+#   point: 4096 + 3072 (no colour);
+#   backward, per sample: the recomputed forward + input gradients of both
+#   decoders (5248) + their weight gradients (5248), plus the double
+#   backward of the Eikonal term (W1, W2 products 3072 and their weight
+#   gradients 3072) when it is on; per pair point: 7168 + 3072 + 3072.
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # dense, MI355X
+
+
+def field_unit_flops(kernel, eikonal):
+    """(FLOPs per ray sample, FLOPs per smoothness pair) of one field kernel."""
+    fwd = 5248.0 + (3072.0 if eikonal else 0.0)
+    pair_point = 7168.0
+    if kernel == "field_bwd":
+        return fwd + 5248.0 + 5248.0 + (6144.0 if eikonal else 0.0), 2 * (pair_point + 6144.0)
+    return fwd, 2 * pair_point
+
 
 def field_unit_bytes(kernel, precision):
     """(bytes per ray sample, bytes per smoothness pair) of one field kernel."""
@@ -78,6 +98,19 @@ def source_digest():
     for f in sorted(os.listdir(csrc)):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:12]
+
+
+def measured_mfma(kernel, workload):
+    """(issued MFMA FLOPs per launch, MFMA busy fraction) from the committed
+    counter summary, if it was taken on the current kernel sources and on
+    this workload (else (None, None))."""
+    path = os.path.join(ROOT, "profiles", "mfma.json")
+    if not os.path.exists(path):
+        return None, None
+    entry = json.load(open(path)).get(f"{kernel}@{workload}")
+    if not entry or entry.get("source_digest") != source_digest():
+        return None, None
+    return entry.get("flops_per_launch"), entry.get("busy_frac")
 
 
 def measured_traffic(kernel, workload):
@@ -389,6 +422,22 @@ def main():
                               "field_kernel<forward> (gosurf_forward: samples and smoothness pairs)"),
         "adam": roofline("adam", BYTES_PER_PARAM_ADAM * n_par, kern["adam"], "adam_kernel (gosurf_adam_step)"),
     }
+    eikonal = w.lambdas[4] > 0
+
+    def mfma_roofline(k, label):
+        per_sample, per_pair = field_unit_flops(k, eikonal)
+        flops = per_sample * samples_now + per_pair * pairs
+        tfs = flops / (kern[k] * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFLOPS[w.precision]
+        issued, busy = measured_mfma(k, w.name)
+        return {"kernel": label, "bound": "mfma", "achieved": round(tfs, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(tfs / peak, 4), "algorithmic_flops_per_launch": flops, "issued_flops_per_launch": issued,
+                "mfma_busy": busy, "ms_per_launch": round(kern[k], 4)}
+
+    mfma_roofs = {
+        "field_bwd_mfma": mfma_roofline("field_bwd", "field_kernel<backward>: decoder FLOPs on MFMA"),
+        "field_fwd_mfma": mfma_roofline("field_fwd", "field_kernel<forward>: decoder FLOPs on MFMA"),
+    }
     dominant = max(("field_fwd", "field_bwd", "adam"), key=lambda k: kern[k])
     roof = roofs[dominant]
 
@@ -428,7 +477,7 @@ def main():
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
         "per_kernel_ms": {k: round(v, 4) for k, v in kern.items()},
         "roofline": roof,
-        "other_rooflines": {k: v for k, v in roofs.items() if k != dominant},
+        "other_rooflines": {**{k: v for k, v in roofs.items() if k != dominant}, **mfma_roofs},
         "source_digest": source_digest(),
         "cpu_baseline": cpu,
         "losses": losses,
