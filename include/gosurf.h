@@ -260,6 +260,52 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
 /* Workspace bytes needed by forward/backward for a batch of these sizes. */
 size_t gosurf_workspace_bytes(const gosurf_model* model, int32_t M, int32_t total, int32_t S);
 
+/* Hierarchical importance sampling (Sec. 3.2, last paragraph: starting from
+   the coarse samples, each step adds n_add samples per ray drawn from the
+   weights of Eq. volume_rendering computed with the samples so far; the
+   implementation details use 96 coarse samples and 3 steps of 12).
+   One step: interval i = [t_i, t_{i+1}] of a ray gets probability
+   proportional to w_i + weight_eps, with w_i = T_i alpha_i (Eq.
+   volume_rendering_alpha at the model's sharpness s = exp(10 v); an interval
+   touching a sample outside the grid box has alpha = 0), uniform within the
+   interval; the draws are u_j = (j + xi_j) / n_add, xi_j from Philox4x32-10
+   keyed by seed with counter (ray, step, 8 + step index, j / 4), word j % 4;
+   the new samples are merged into the ray's sorted list, existing samples
+   first on ties. */
+typedef struct {
+  int32_t steps;       /* importance steps, 1..8 (3 in the paper) */
+  int32_t n_add;       /* samples added per ray and step, 1..64 (12 in the paper) */
+  float weight_eps;    /* added to every interval weight, > 0 (1e-5) */
+  uint64_t seed;       /* Philox key */
+  int64_t step;        /* iteration number (Philox counter word, low 32 bits) */
+} gosurf_importance_cfg;
+
+/* Workspace bytes for gosurf_importance_sample on M rays with n_coarse
+   samples each. */
+size_t gosurf_importance_workspace_bytes(int32_t M, int32_t n_coarse, const gosurf_importance_cfg* cfg);
+
+/* The full sampler: the SDF of the coarse samples (the forward field kernel,
+   at the model's precision), then `steps` times one importance step, the SDF
+   at the new samples and the merge.  `coarse` must hold the same number n0 of
+   sorted samples on every ray (a batch of gosurf_sample_rays without a
+   proposal: total = M * n0).  Writes out->t [M * nf], out->seg [M + 1] and
+   out->ray_of [M * nf] with nf = n0 + steps * n_add <=
+   GOSURF_MAX_SAMPLES_PER_RAY; out->M must be M and out->total M * nf; the
+   other arrays of `out` are not touched (point them at the coarse batch's).
+   Errors: NULL, SHAPE, VALUE, WORKSPACE, HIP. */
+gosurf_status gosurf_importance_sample(const gosurf_model* model, const gosurf_params* params,
+                                       const gosurf_ray_batch* coarse, const gosurf_importance_cfg* cfg,
+                                       gosurf_ray_batch* out, void* workspace, size_t workspace_bytes,
+                                       void* stream);
+
+/* One importance step on given SDF values: rays->t holds n = total / M sorted
+   samples per ray (n >= 2, total = M * n), phi [total] their SDF values, and
+   step_index selects the Philox stream; writes t_new [M * n_add], each ray's
+   new samples in draw order (u_j increasing).  Errors: NULL, SHAPE, VALUE, HIP. */
+gosurf_status gosurf_importance_step(const gosurf_model* model, const float* mlp, const gosurf_ray_batch* rays,
+                                     const float* phi, const gosurf_importance_cfg* cfg, int32_t step_index,
+                                     float* t_new, void* stream);
+
 /* Forward pass and loss (Sec. 3.1-3.5).  Per-ray opacities
    alpha_i = max(1 - Phi_s(phi_{i+1}) / Phi_s(phi_i), 0), alpha_last = 0,
    w_i = T_i alpha_i; colour/depth = sum w_i c_i / sum w_i t_i.  Loss terms:

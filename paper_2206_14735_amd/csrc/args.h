@@ -134,4 +134,37 @@ struct SampleArgs {
   int n_free;
 };
 
+
+// Hierarchical importance sampling: one step (new depths from the current
+// samples of every ray, all rays with n samples) and the merge of the new
+// depths into the sorted lists.
+constexpr int kImpMaxAdd = 64;   // samples added per ray and step
+struct ImpArgs {
+  Grid g;
+  const float* o;
+  const float* r;
+  const float* t;        // [M][n] sorted
+  const float* phi;      // SDF of sample i at phi[i * phi_stride]
+  int phi_stride;
+  const float* mlp;      // sharpness s = exp(10 v)
+  int M, n, n_add;
+  float eps;             // added to every interval weight
+  uint32_t k0, k1, iteration, stream;   // Philox key and counter words
+  float* t_new;          // [M][n_add]
+  int* ray_of_new;       // [M][n_add] or null
+};
+struct ImpMergeArgs {
+  const float* ta;       // [M][na] sorted
+  const float* pa;       // value carried with ta: pa[i * pa_stride]
+  int pa_stride, na;
+  const float* tb;       // [M][nb]
+  const float* pb;
+  int pb_stride, nb;
+  int M;
+  float* t_out;          // [M][na + nb]
+  float* p_out;          // or null
+  int* ray_of_out;       // or null
+  int* seg_out;          // [M + 1] or null
+};
+
 }  // namespace gs

@@ -36,6 +36,8 @@ int proposal_blocks(int M);
 int proposal_numel();
 hipError_t launch_colsum(const float* part, int rows, int cols, float* tmp, float* add_dst, int n_add,
                          float* set_dst, int set_col, hipStream_t st);
+hipError_t launch_importance_step(const ImpArgs& a, hipStream_t st);
+hipError_t launch_importance_merge(const ImpMergeArgs& a, hipStream_t st);
 
 }  // namespace gs
 
@@ -501,6 +503,158 @@ gosurf_status gosurf_adam_step(const gosurf_adam_cfg* c, gosurf_adam_state* s, v
   mark(GOSURF_KERNEL_ADAM, true, (hipStream_t)stream);
   if ((st = hip_check(gs::launch_adam(*c, copy, (hipStream_t)stream), "adam")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_ADAM, false, (hipStream_t)stream);
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- hierarchical importance sampling
+namespace {
+
+constexpr uint32_t kImpStream = 8;   // Philox stream of importance step k: 8 + k
+
+gosurf_status check_importance_cfg(const gosurf_importance_cfg* c) {
+  if (!c) return fail(GOSURF_ERR_NULL, "importance config is NULL");
+  if (c->steps < 1 || c->steps > 8) return fail(GOSURF_ERR_VALUE, "importance steps = %d (1..8)", c->steps);
+  if (c->n_add < 1 || c->n_add > gs::kImpMaxAdd)
+    return fail(GOSURF_ERR_VALUE, "n_add = %d (1..%d)", c->n_add, gs::kImpMaxAdd);
+  if (!(c->weight_eps > 0.f) || !std::isfinite(c->weight_eps))
+    return fail(GOSURF_ERR_VALUE, "weight_eps must be finite and > 0");
+  return GOSURF_OK;
+}
+
+struct ImpWorkspace {
+  float* ta;        // [M][nf] current depths (two buffers, alternating)
+  float* pa;        // [M][nf] their SDF values
+  float* tb;
+  float* pb;
+  float* t_new;     // [M][n_add]
+  int* ray_new;     // [M][n_add]
+  float* out_c;     // [M][n0][4] forward outputs at the coarse samples
+  float* out_n;     // [M][n_add][4] forward outputs at the new samples
+  size_t bytes;
+};
+
+ImpWorkspace imp_layout(char* base, int M, int n0, int n_add, int steps) {
+  ImpWorkspace w{};
+  const size_t nf = (size_t)n0 + (size_t)steps * n_add;
+  size_t off = 0;
+  auto take = [&](size_t n) { char* p = base ? base + off : nullptr; off += up(n); return p; };
+  w.ta = reinterpret_cast<float*>(take(sizeof(float) * M * nf));
+  w.pa = reinterpret_cast<float*>(take(sizeof(float) * M * nf));
+  w.tb = reinterpret_cast<float*>(take(sizeof(float) * M * nf));
+  w.pb = reinterpret_cast<float*>(take(sizeof(float) * M * nf));
+  w.t_new = reinterpret_cast<float*>(take(sizeof(float) * M * (size_t)n_add));
+  w.ray_new = reinterpret_cast<int*>(take(sizeof(int) * M * (size_t)n_add));
+  w.out_c = reinterpret_cast<float*>(take(sizeof(float) * 4 * M * (size_t)n0));
+  w.out_n = reinterpret_cast<float*>(take(sizeof(float) * 4 * M * (size_t)n_add));
+  w.bytes = off;
+  return w;
+}
+
+// SDF (with colour) of `total` samples given by (t, ray_of) through the forward field kernel
+gosurf_status field_phi(const gosurf_model* model, const gosurf_params* params, const gosurf_ray_batch* rays,
+                        const float* t, const int* ray_of, int total, float* out4, hipStream_t s) {
+  gs::FieldArgs fa{};
+  fa.g = to_grid(model); fa.grid = params->grid; fa.mlp = params->mlp;
+  fa.grid_bf16 = model->precision == GOSURF_BF16 ? params->grid_bf16 : nullptr;
+  fa.o = rays->o; fa.r = rays->r; fa.t = t; fa.ray_of = ray_of; fa.total = total;
+  fa.S = 0; fa.out4 = out4; fa.need_gx = 0;
+  const int nb = gs::field_grid(fa, false);
+  if (nb <= 0) return fail(GOSURF_ERR_HIP, "field grid: the occupancy query failed");
+  return hip_check(gs::launch_field(fa, false, nb, s), "field fwd (importance)");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gosurf_importance_workspace_bytes(int32_t M, int32_t n_coarse, const gosurf_importance_cfg* cfg) {
+  if (!cfg || M < 1 || n_coarse < 1) return 0;
+  return imp_layout(nullptr, M, n_coarse, cfg->n_add, cfg->steps).bytes;
+}
+
+gosurf_status gosurf_importance_step(const gosurf_model* model, const float* mlp, const gosurf_ray_batch* rays,
+                                     const float* phi, const gosurf_importance_cfg* cfg, int32_t step_index,
+                                     float* t_new, void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if ((st = check_importance_cfg(cfg)) != GOSURF_OK) return st;
+  if (!mlp || !rays || !phi || !t_new || !rays->o || !rays->r || !rays->t)
+    return fail(GOSURF_ERR_NULL, "an importance-step array is NULL");
+  if (rays->M < 1 || rays->total % rays->M != 0)
+    return fail(GOSURF_ERR_SHAPE, "total = %d is not a multiple of M = %d", rays->total, rays->M);
+  const int n = rays->total / rays->M;
+  if (n < 2 || n > GOSURF_MAX_SAMPLES_PER_RAY)
+    return fail(GOSURF_ERR_SHAPE, "%d samples per ray (2..%d)", n, GOSURF_MAX_SAMPLES_PER_RAY);
+  if (step_index < 0) return fail(GOSURF_ERR_VALUE, "step_index = %d < 0", step_index);
+  gs::ImpArgs a{};
+  a.g = to_grid(model); a.o = rays->o; a.r = rays->r; a.t = rays->t; a.phi = phi; a.phi_stride = 1;
+  a.mlp = mlp; a.M = rays->M; a.n = n; a.n_add = cfg->n_add; a.eps = cfg->weight_eps;
+  a.k0 = (uint32_t)(cfg->seed & 0xffffffffu); a.k1 = (uint32_t)(cfg->seed >> 32);
+  a.iteration = (uint32_t)cfg->step; a.stream = kImpStream + (uint32_t)step_index;
+  a.t_new = t_new; a.ray_of_new = nullptr;
+  if ((st = hip_check(gs::launch_importance_step(a, (hipStream_t)stream), "importance step")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
+gosurf_status gosurf_importance_sample(const gosurf_model* model, const gosurf_params* params,
+                                       const gosurf_ray_batch* coarse, const gosurf_importance_cfg* cfg,
+                                       gosurf_ray_batch* out, void* ws, size_t ws_bytes, void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if ((st = check_params(model, params)) != GOSURF_OK) return st;
+  if ((st = check_batch(coarse, false)) != GOSURF_OK) return st;
+  if ((st = check_importance_cfg(cfg)) != GOSURF_OK) return st;
+  const int M = coarse->M;
+  if (coarse->total % M != 0)
+    return fail(GOSURF_ERR_SHAPE, "coarse total = %d is not a multiple of M = %d", coarse->total, M);
+  const int n0 = coarse->total / M;
+  const long long nf = (long long)n0 + (long long)cfg->steps * cfg->n_add;
+  if (n0 < 2 || nf > GOSURF_MAX_SAMPLES_PER_RAY)
+    return fail(GOSURF_ERR_SHAPE, "%d coarse + %d x %d samples per ray (at most %d)", n0, cfg->steps, cfg->n_add,
+                GOSURF_MAX_SAMPLES_PER_RAY);
+  if (!out || !out->t || !out->seg || !out->ray_of) return fail(GOSURF_ERR_NULL, "an output array is NULL");
+  if (out->M != M || (long long)out->total != (long long)M * nf)
+    return fail(GOSURF_ERR_SHAPE, "out has M = %d, total = %d; expected %d, %lld", out->M, out->total, M,
+                (long long)M * nf);
+  if ((long long)M * nf * 4 >= (1LL << 31)) return fail(GOSURF_ERR_SHAPE, "too many samples");
+  const ImpWorkspace w = imp_layout(static_cast<char*>(ws), M, n0, cfg->n_add, cfg->steps);
+  if (!ws || ws_bytes < w.bytes)
+    return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, w.bytes);
+  hipStream_t s = (hipStream_t)stream;
+
+  if ((st = field_phi(model, params, coarse, coarse->t, coarse->ray_of, M * n0, w.out_c, s)) != GOSURF_OK)
+    return st;
+  const float* t_cur = coarse->t;
+  const float* p_cur = w.out_c;
+  int p_stride = 4, n = n0;
+  float* t_dst = w.tb;
+  float* p_dst = w.pb;
+  for (int k = 0; k < cfg->steps; ++k) {
+    gs::ImpArgs a{};
+    a.g = to_grid(model); a.o = coarse->o; a.r = coarse->r; a.t = t_cur; a.phi = p_cur; a.phi_stride = p_stride;
+    a.mlp = params->mlp; a.M = M; a.n = n; a.n_add = cfg->n_add; a.eps = cfg->weight_eps;
+    a.k0 = (uint32_t)(cfg->seed & 0xffffffffu); a.k1 = (uint32_t)(cfg->seed >> 32);
+    a.iteration = (uint32_t)cfg->step; a.stream = kImpStream + (uint32_t)k;
+    a.t_new = w.t_new; a.ray_of_new = w.ray_new;
+    if ((st = hip_check(gs::launch_importance_step(a, s), "importance step")) != GOSURF_OK) return st;
+    if ((st = field_phi(model, params, coarse, w.t_new, w.ray_new, M * cfg->n_add, w.out_n, s)) != GOSURF_OK)
+      return st;
+    const bool last = k + 1 == cfg->steps;
+    gs::ImpMergeArgs mg{};
+    mg.ta = t_cur; mg.pa = p_cur; mg.pa_stride = p_stride; mg.na = n;
+    mg.tb = w.t_new; mg.pb = w.out_n; mg.pb_stride = 4; mg.nb = cfg->n_add; mg.M = M;
+    mg.t_out = last ? out->t : t_dst;
+    mg.p_out = last ? nullptr : p_dst;
+    mg.ray_of_out = last ? out->ray_of : nullptr;
+    mg.seg_out = last ? out->seg : nullptr;
+    if ((st = hip_check(gs::launch_importance_merge(mg, s), "importance merge")) != GOSURF_OK) return st;
+    t_cur = t_dst; p_cur = p_dst; p_stride = 1; n += cfg->n_add;
+    t_dst = (t_dst == w.tb) ? w.ta : w.tb;
+    p_dst = (p_dst == w.pb) ? w.pa : w.pb;
+  }
   return ok();
 }
 

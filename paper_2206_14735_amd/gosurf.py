@@ -95,7 +95,8 @@ class AdamState(C.Structure):
 EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "gosurf_workspace_bytes",
            "gosurf_forward", "gosurf_backward", "gosurf_adam_step", "gosurf_refresh_bf16",
            "gosurf_proposal_forward", "gosurf_proposal_targets", "gosurf_proposal_workspace_bytes",
-           "gosurf_proposal_backward", "gosurf_time_kernel")
+           "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_workspace_bytes",
+           "gosurf_importance_step", "gosurf_importance_sample")
 
 _lib = None
 
@@ -131,9 +132,17 @@ def lib():
                                                C.POINTER(SampleCfg), C.c_void_p, C.c_float, C.c_float,
                                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.gosurf_time_kernel.argtypes = [C.c_int32, C.c_void_p, C.c_void_p]
+        L.gosurf_importance_workspace_bytes.restype = C.c_size_t
+        L.gosurf_importance_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.POINTER(ImportanceCfg)]
+        L.gosurf_importance_step.argtypes = [C.POINTER(Model), C.c_void_p, C.POINTER(RayBatchC), C.c_void_p,
+                                             C.POINTER(ImportanceCfg), C.c_int32, C.c_void_p, C.c_void_p]
+        L.gosurf_importance_sample.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
+                                               C.POINTER(ImportanceCfg), C.POINTER(RayBatchC), C.c_void_p,
+                                               C.c_size_t, C.c_void_p]
         for f in ("gosurf_sample_rays", "gosurf_forward", "gosurf_backward", "gosurf_adam_step",
                   "gosurf_refresh_bf16", "gosurf_proposal_forward", "gosurf_proposal_targets",
-                  "gosurf_proposal_backward", "gosurf_time_kernel"):
+                  "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_step",
+                  "gosurf_importance_sample"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -414,3 +423,51 @@ def gosurf_time_kernel(kernel, start=None, stop=None):
 def workspace_for(model, M, total, S, device="cuda"):
     n = gosurf_workspace_bytes(model, M, total, S)
     return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+class ImportanceCfg(C.Structure):
+    """gosurf_importance_cfg: hierarchical importance sampling (3 steps of 12 in the paper)."""
+    _fields_ = [("steps", C.c_int32), ("n_add", C.c_int32), ("weight_eps", C.c_float), ("seed", C.c_uint64),
+                ("step", C.c_int64)]
+
+
+def make_importance_cfg(steps=3, n_add=12, weight_eps=1e-5, seed=0, step=0):
+    return ImportanceCfg(steps, n_add, weight_eps, seed, step)
+
+
+def gosurf_importance_workspace_bytes(M, n_coarse, cfg):
+    return int(lib().gosurf_importance_workspace_bytes(M, n_coarse, C.byref(cfg)))
+
+
+def gosurf_importance_step(model, mlp, rays, phi, cfg, step_index, t_new=None, stream=None):
+    """One importance step on given SDF values phi [total]; returns t_new [M * n_add]."""
+    if t_new is None:
+        t_new = torch.empty(rays.M * cfg.n_add, device=rays.t.device, dtype=torch.float32)
+    bc = rays.c()
+    _check("gosurf_importance_step", lib().gosurf_importance_step(
+        C.byref(model), _ptr(mlp, F32), C.byref(bc), _ptr(phi, F32), C.byref(cfg), step_index, _ptr(t_new, F32),
+        _stream(stream)))
+    return t_new
+
+
+def gosurf_importance_sample(model, grid, mlp, coarse, cfg, out=None, workspace=None, grid_bf16=None,
+                             stream=None):
+    """The full sampler: returns a RayBatch with n0 + steps * n_add samples per ray that shares the coarse
+    batch's rays, targets and smoothness pairs."""
+    M = coarse.M
+    n0 = coarse.total // M
+    nf = n0 + cfg.steps * cfg.n_add
+    dev = coarse.t.device
+    if out is None:
+        out = RayBatch(coarse.o, coarse.r, coarse.rgb, coarse.depth,
+                       torch.empty(M * nf, device=dev, dtype=torch.float32),
+                       torch.empty(M + 1, device=dev, dtype=torch.int32),
+                       torch.empty(M * nf, device=dev, dtype=torch.int32), coarse.xs, coarse.eps, coarse.pixel)
+    if workspace is None:
+        workspace = torch.empty(gosurf_importance_workspace_bytes(M, n0, cfg), dtype=torch.uint8, device=dev)
+    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
+    cc, oc = coarse.c(), out.c()
+    _check("gosurf_importance_sample", lib().gosurf_importance_sample(
+        C.byref(model), C.byref(p), C.byref(cc), C.byref(cfg), C.byref(oc), _ptr(workspace), workspace.numel(),
+        _stream(stream)))
+    return out
