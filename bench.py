@@ -449,7 +449,10 @@ def main():
         print("# calibration copy: 1 GiB read + 1 GiB written", file=sys.stderr, flush=True)
 
     cpu = None
-    if not a.no_cpu_baseline:
+    if "importance_steps" in w.extra and not a.no_cpu_baseline:
+        # the oracle baseline covers the stratified step; this workload's step also samples by importance
+        print("# oracle baseline: not run for the importance-sampling workload", file=sys.stderr, flush=True)
+    elif not a.no_cpu_baseline:
         fr_cpu = synth.Frames(frames.rgb.cpu(), frames.depth.cpu(), frames.c2w.cpu(), frames.fx, frames.fy,
                               frames.cx, frames.cy)
         print(f"# oracle baseline on {a.cpu_rays} rays ...", file=sys.stderr, flush=True)
@@ -462,17 +465,23 @@ def main():
         torch.cuda.empty_cache()
         comparison = compare(a, G, synth, Reconstruction, torch)
 
-    samples = w.M * w.n_samples
+    spr = rec.total // w.M                 # samples per ray of the batch the step trains on
+    samples = w.M * spr
+    if "importance_steps" in w.extra:
+        sampling = (f"({w.n_strat} stratified + {w.extra['importance_steps']} importance steps of "
+                    f"{w.extra['importance_add']}) samples")
+    else:
+        sampling = f"({w.n_strat}+{w.n_near}) samples"
     out = {
         "metric": "ray-samples/s per fwd+bwd step, plain FP32 vs BF16+proposal at equal depth L1",
         "value": samples / (ms * 1e-3), "unit": "ray-samples/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms, "iterations_per_s": 1e3 / ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if w.precision == "fp32" else "bf16",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.M} rays x ({w.n_strat}+{w.n_near}) samples, {w.S} smoothness "
+        "config": {"workload": f"{w.name}: {w.M} rays x {sampling}, {w.S} smoothness "
                                f"pairs, grid {'/'.join(str(v) for v in sorted(w.voxels))} m "
                                f"({n_par / 1e6:.2f} M params), {n_frames} frames {w.W}x{w.H}, {w.precision}",
-                   "rays": w.M, "samples_per_ray": w.n_samples, "smoothness_pairs": w.S,
+                   "rays": w.M, "samples_per_ray": spr, "smoothness_pairs": w.S,
                    "grid_params": grid_numel, "frames": n_frames},
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},
         "per_kernel_ms": {k: round(v, 4) for k, v in kern.items()},

@@ -44,18 +44,28 @@ class Reconstruction:
         self.ws = G.workspace_for(self.model, M, self.total, S, self.device)
         self.lr_grid, self.lr_mlp = lr_grid, lr_mlp
         self.loss_scale = loss_scale
+        self.importance = None
         self.it = 0
 
     @classmethod
     def from_workload(cls, w, frames, seed=0, **kw):
         span = G.SPAN_FIXED if w.span == "fixed" else G.SPAN_BOX
         prec = G.BF16 if w.precision == "bf16" else G.FP32
-        return cls(w.layout(), frames, w.n_strat, w.n_near, w.M, w.S, span, w.near, w.far, w.trunc,
-                   w.delta_s, w.lambdas, w.alpha_fs, w.lr_grid, w.lr_mlp, seed, prec, w.loss_scale, **kw)
+        rec = cls(w.layout(), frames, w.n_strat, w.n_near, w.M, w.S, span, w.near, w.far, w.trunc,
+                  w.delta_s, w.lambdas, w.alpha_fs, w.lr_grid, w.lr_mlp, seed, prec, w.loss_scale, **kw)
+        if "importance_steps" in w.extra:
+            rec.use_importance(w.extra["importance_steps"], w.extra["importance_add"])
+        return rec
 
     def sample(self):
         self.cfg.step = self.it
-        G.gosurf_sample_rays(self.model, self.frames, self.cfg, out=self.batch)
+        if self.importance is None:
+            G.gosurf_sample_rays(self.model, self.frames, self.cfg, out=self.batch)
+            return
+        G.gosurf_sample_rays(self.model, self.frames, self.cfg, out=self.coarse)
+        self.importance.step = self.it
+        G.gosurf_importance_sample(self.model, self.grid, self.mlp, self.coarse, self.importance, out=self.batch,
+                                   workspace=self.imp_ws, grid_bf16=self.grid_bf16)
 
     def forward(self):
         return G.gosurf_forward(self.model, self.grid, self.mlp, self.batch, self.loss_cfg, self.ws,
@@ -76,6 +86,25 @@ class Reconstruction:
         self.backward()
         self.adam()
         self.it += 1
+
+    def use_importance(self, steps=3, n_add=12, weight_eps=1e-5):
+        """Hierarchical importance sampling from now on: the sampled batch becomes
+        the coarse set, and each step adds `steps` x `n_add` samples per ray."""
+        M, S = self.cfg.M, self.cfg.S
+        self.importance = G.make_importance_cfg(steps, n_add, weight_eps, seed=self.cfg.seed, step=self.it)
+        self.coarse = self.batch
+        n0 = self.coarse.total // M
+        nf = n0 + steps * n_add
+        dev = self.device
+        self.batch = G.RayBatch(self.coarse.o, self.coarse.r, self.coarse.rgb, self.coarse.depth,
+                                torch.empty(M * nf, device=dev), torch.empty(M + 1, device=dev, dtype=torch.int32),
+                                torch.empty(M * nf, device=dev, dtype=torch.int32), self.coarse.xs, self.coarse.eps,
+                                self.coarse.pixel)
+        self.total = M * nf
+        self.imp_ws = torch.empty(G.gosurf_importance_workspace_bytes(M, n0, self.importance), dtype=torch.uint8,
+                                  device=dev)
+        self.fwd = G.FwdOut.empty(M, self.total, dev)
+        self.ws = G.workspace_for(self.model, M, self.total, S, dev)
 
     def use_proposal(self, proposal, n_proposal=24, conf_threshold=0.5, n_free=0, depth_check=False,
                      depth_extend=0.0):

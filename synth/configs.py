@@ -10,6 +10,8 @@
   (96 + 32) samples, 2^20 smoothness points.
 * ``room_bf16`` - the room at 65536 x (64 + 32), BF16 decoders and grid reads.
 * ``room_proposal`` - the room with 2000 frames, proposal-driven sampling.
+* ``room_importance`` - the room with the paper's own sampling: 6144 rays x
+  (96 stratified coarse + 3 importance steps of 12) = 132 samples.
 """
 from __future__ import annotations
 
@@ -74,4 +76,8 @@ ROOM_PROPOSAL = Workload("room_proposal", "room", (0.03, 0.06, 0.24, 0.96), 2000
                          extra={"proposal_samples": 24, "free_samples": 0, "conf_threshold": 0.5,
                                 "cover_tol": 0.05, "depth_check": True, "depth_extend": 0.1})
 
-ALL = {w.name: w for w in (SPHERE, ROOM, ROOM_STRESS, ROOM_BF16, ROOM_PROPOSAL)}
+ROOM_IMPORTANCE = Workload("room_importance", "room", (0.03, 0.06, 0.24, 0.96), 1000, 480, 640, 525.0,
+                           M=6144, n_strat=96, n_near=0, span="aabb", near=0.1, far=1e9,
+                           trunc=0.1, S=16384, extra={"importance_steps": 3, "importance_add": 12})
+
+ALL = {w.name: w for w in (SPHERE, ROOM, ROOM_STRESS, ROOM_BF16, ROOM_PROPOSAL, ROOM_IMPORTANCE)}
