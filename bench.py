@@ -459,13 +459,13 @@ def main():
         cpu = cpu_baseline(w, fr_cpu, grid, mlp, a.cpu_rays)
         print(f"# oracle baseline: {cpu['sample']}", file=sys.stderr, flush=True)
 
+    spr = rec.total // w.M                 # samples per ray of the batch the step trains on
     comparison = None
     if not a.no_compare:
         del rec
         torch.cuda.empty_cache()
         comparison = compare(a, G, synth, Reconstruction, torch)
 
-    spr = rec.total // w.M                 # samples per ray of the batch the step trains on
     samples = w.M * spr
     if "importance_steps" in w.extra:
         sampling = (f"({w.n_strat} stratified + {w.extra['importance_steps']} importance steps of "
