@@ -372,6 +372,37 @@ gosurf_status gosurf_proposal_backward(const gosurf_model* model, const float* g
                                        const float* targets, float beta, float cover_tol, float* grad,
                                        float* loss, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Surface extraction (evaluation, not part of an optimisation step).  The
+   reconstructed surface is the zero level set of phi (Sec. 3.1); the paper
+   meshes it on a 1 cm lattice.
+
+   The SDF on the lattice p0 + h (i, j, k), i < nx, j < ny, k < nz, stored in
+   phi [nz][ny][nx] (x fastest), evaluated by the forward field kernel at the
+   model's precision (lattice point x = p0 + i h rounded as float32 i*h + p0).
+   Points outside the grid box get the decoder's value at zero features.  The
+   lattice is processed in z-slabs as large as the workspace allows
+   (gosurf_lattice_workspace_bytes(nx, ny, layers) bytes hold `layers`
+   z-layers; at least one layer is needed).
+   Errors: NULL, SHAPE, VALUE, WORKSPACE, HIP. */
+size_t gosurf_lattice_workspace_bytes(int32_t nx, int32_t ny, int32_t layers);
+gosurf_status gosurf_sdf_lattice(const gosurf_model* model, const gosurf_params* params, const float p0[3],
+                                 float h, int32_t nx, int32_t ny, int32_t nz, float* phi, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
+/* Marching tetrahedra on phi [nz][ny][nx] (lattice as above): each cube is
+   split into the six tetrahedra around its main diagonal (corner c = bx +
+   2 by + 4 bz: (0,1,3,7) (0,3,2,7) (0,2,6,7) (0,6,4,7) (0,4,5,7)
+   (0,5,1,7)); a corner is inside when phi < 0; a tetrahedron with one corner
+   on one side gives one triangle, one with two on each side two; an edge
+   (p, q) crosses at p + phi_p / (phi_p - phi_q) (q - p).  Writes up to
+   max_triangles triangles to triangles [max_triangles][3][3] (vertex
+   positions, unordered, orientation not fixed) and the number found (which
+   may exceed max_triangles; the rest are then not written) to the device int
+   *count.  Errors: NULL, SHAPE, VALUE, HIP. */
+gosurf_status gosurf_marching_tetrahedra(const float* phi, const float p0[3], float h, int32_t nx, int32_t ny,
+                                         int32_t nz, float* triangles, int64_t max_triangles, int32_t* count,
+                                         void* stream);
+
 /* Round the float32 grid to its bfloat16 mirror (round to nearest even), as
    gosurf_adam_step does after every update; call once before the first
    GOSURF_BF16 forward.  numel = 4 * n_vertices.  Errors: NULL, SHAPE, ALIGN,

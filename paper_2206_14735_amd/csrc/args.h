@@ -167,4 +167,25 @@ struct ImpMergeArgs {
   int* seg_out;          // [M + 1] or null
 };
 
+// Surface extraction: lattice rows as rays for the forward field kernel, and
+// marching tetrahedra over the SDF lattice.
+struct LatticeArgs {
+  float p0[3];
+  float h;
+  int nx, ny, k0, layers;   // a slab of `layers` z-layers starting at k0
+  float* t;                 // [nx * ny * layers]
+  int* ray_of;              // [nx * ny * layers]
+  float* o;                 // [ny * layers][3]
+  float* r;                 // [ny * layers][3]
+};
+struct MtArgs {
+  const float* phi;         // [nz][ny][nx]
+  float p0[3];
+  float h;
+  int nx, ny, nz;
+  float* tris;              // [max_tris][3][3]
+  long long max_tris;
+  int* count;               // triangles found (may exceed max_tris)
+};
+
 }  // namespace gs

@@ -38,6 +38,9 @@ hipError_t launch_colsum(const float* part, int rows, int cols, float* tmp, floa
                          float* set_dst, int set_col, hipStream_t st);
 hipError_t launch_importance_step(const ImpArgs& a, hipStream_t st);
 hipError_t launch_importance_merge(const ImpMergeArgs& a, hipStream_t st);
+hipError_t launch_lattice_rays(const LatticeArgs& a, hipStream_t st);
+hipError_t launch_phi_copy(const float* out4, long long n, float* phi, hipStream_t st);
+hipError_t launch_marching_tets(const MtArgs& a, hipStream_t st);
 
 }  // namespace gs
 
@@ -659,3 +662,114 @@ gosurf_status gosurf_importance_sample(const gosurf_model* model, const gosurf_p
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- surface extraction
+namespace {
+
+struct LatWorkspace {
+  float* t;
+  int* ray_of;
+  float* out4;
+  float* o;
+  float* r;
+  size_t bytes;
+};
+
+LatWorkspace lat_layout(char* base, long long nx, long long ny, long long layers) {
+  LatWorkspace w{};
+  size_t off = 0;
+  const size_t n = (size_t)(nx * ny * layers), rows = (size_t)(ny * layers);
+  auto take = [&](size_t b) { char* p = base ? base + off : nullptr; off += up(b); return p; };
+  w.t = reinterpret_cast<float*>(take(sizeof(float) * n));
+  w.ray_of = reinterpret_cast<int*>(take(sizeof(int) * n));
+  w.out4 = reinterpret_cast<float*>(take(sizeof(float) * 4 * n));
+  w.o = reinterpret_cast<float*>(take(sizeof(float) * 3 * rows));
+  w.r = reinterpret_cast<float*>(take(sizeof(float) * 3 * rows));
+  w.bytes = off;
+  return w;
+}
+
+gosurf_status check_lattice(const float* p0, float h, int nx, int ny, int nz) {
+  if (!p0) return fail(GOSURF_ERR_NULL, "p0 is NULL");
+  if (nx < 2 || ny < 2 || nz < 2) return fail(GOSURF_ERR_SHAPE, "lattice %d x %d x %d (at least 2 each)", nx, ny, nz);
+  if (!(h > 0.f) || !std::isfinite(h)) return fail(GOSURF_ERR_VALUE, "lattice spacing must be finite and > 0");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p0[a])) return fail(GOSURF_ERR_VALUE, "p0 must be finite");
+  return GOSURF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gosurf_lattice_workspace_bytes(int32_t nx, int32_t ny, int32_t layers) {
+  if (nx < 1 || ny < 1 || layers < 1) return 0;
+  return lat_layout(nullptr, nx, ny, layers).bytes;
+}
+
+gosurf_status gosurf_sdf_lattice(const gosurf_model* model, const gosurf_params* params, const float p0[3],
+                                 float h, int32_t nx, int32_t ny, int32_t nz, float* phi, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  gosurf_status st;
+  if ((st = check_model(model)) != GOSURF_OK) return st;
+  if ((st = check_params(model, params)) != GOSURF_OK) return st;
+  if ((st = check_lattice(p0, h, nx, ny, nz)) != GOSURF_OK) return st;
+  if (!phi || !ws) return fail(GOSURF_ERR_NULL, "phi or the workspace is NULL");
+  // the largest slab that fits the workspace and the field kernel's sample indexing
+  long long layers = 0;
+  for (long long lo = 1, hi = nz; lo <= hi;) {
+    const long long mid = (lo + hi) / 2;
+    if (lat_layout(nullptr, nx, ny, mid).bytes <= ws_bytes && (long long)nx * ny * mid * 4 < (1LL << 31)) {
+      layers = mid;
+      lo = mid + 1;
+    } else {
+      hi = mid - 1;
+    }
+  }
+  if (layers < 1)
+    return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes holds no z-layer (%zu needed)", ws_bytes,
+                lat_layout(nullptr, nx, ny, 1).bytes);
+  const LatWorkspace w = lat_layout(static_cast<char*>(ws), nx, ny, layers);
+  hipStream_t s = (hipStream_t)stream;
+  for (int k0 = 0; k0 < nz; k0 += (int)layers) {
+    const int L = (int)((nz - k0) < layers ? (nz - k0) : layers);
+    gs::LatticeArgs la{};
+    for (int a = 0; a < 3; ++a) la.p0[a] = p0[a];
+    la.h = h; la.nx = nx; la.ny = ny; la.k0 = k0; la.layers = L;
+    la.t = w.t; la.ray_of = w.ray_of; la.o = w.o; la.r = w.r;
+    if ((st = hip_check(gs::launch_lattice_rays(la, s), "lattice rays")) != GOSURF_OK) return st;
+    gs::FieldArgs fa{};
+    fa.g = to_grid(model); fa.grid = params->grid; fa.mlp = params->mlp;
+    fa.grid_bf16 = model->precision == GOSURF_BF16 ? params->grid_bf16 : nullptr;
+    fa.o = w.o; fa.r = w.r; fa.t = w.t; fa.ray_of = w.ray_of; fa.total = nx * ny * L;
+    fa.S = 0; fa.out4 = w.out4; fa.need_gx = 0;
+    const int nb = gs::field_grid(fa, false);
+    if (nb <= 0) return fail(GOSURF_ERR_HIP, "field grid: the occupancy query failed");
+    if ((st = hip_check(gs::launch_field(fa, false, nb, s), "field fwd (lattice)")) != GOSURF_OK) return st;
+    if ((st = hip_check(gs::launch_phi_copy(w.out4, (long long)nx * ny * L, phi + (size_t)k0 * nx * ny, s),
+                        "lattice copy")) != GOSURF_OK)
+      return st;
+  }
+  return ok();
+}
+
+gosurf_status gosurf_marching_tetrahedra(const float* phi, const float p0[3], float h, int32_t nx, int32_t ny,
+                                         int32_t nz, float* triangles, int64_t max_triangles, int32_t* count,
+                                         void* stream) {
+  gosurf_status st;
+  if ((st = check_lattice(p0, h, nx, ny, nz)) != GOSURF_OK) return st;
+  if (!phi || !count || (max_triangles > 0 && !triangles)) return fail(GOSURF_ERR_NULL, "an array is NULL");
+  if (max_triangles < 0) return fail(GOSURF_ERR_VALUE, "max_triangles < 0");
+  if ((long long)(nx - 1) * (ny - 1) * (nz - 1) * 12 >= (1LL << 31))
+    return fail(GOSURF_ERR_SHAPE, "lattice too large for a 32-bit triangle count");
+  gs::MtArgs a{};
+  a.phi = phi;
+  for (int q = 0; q < 3; ++q) a.p0[q] = p0[q];
+  a.h = h; a.nx = nx; a.ny = ny; a.nz = nz; a.tris = triangles; a.max_tris = max_triangles; a.count = count;
+  if ((st = hip_check(gs::launch_marching_tets(a, (hipStream_t)stream), "marching tetrahedra")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
+}  // extern "C"
+

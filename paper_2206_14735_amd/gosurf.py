@@ -96,7 +96,8 @@ EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "g
            "gosurf_forward", "gosurf_backward", "gosurf_adam_step", "gosurf_refresh_bf16",
            "gosurf_proposal_forward", "gosurf_proposal_targets", "gosurf_proposal_workspace_bytes",
            "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_workspace_bytes",
-           "gosurf_importance_step", "gosurf_importance_sample")
+           "gosurf_importance_step", "gosurf_importance_sample", "gosurf_lattice_workspace_bytes",
+           "gosurf_sdf_lattice", "gosurf_marching_tetrahedra")
 
 _lib = None
 
@@ -139,10 +140,17 @@ def lib():
         L.gosurf_importance_sample.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
                                                C.POINTER(ImportanceCfg), C.POINTER(RayBatchC), C.c_void_p,
                                                C.c_size_t, C.c_void_p]
+        L.gosurf_lattice_workspace_bytes.restype = C.c_size_t
+        L.gosurf_lattice_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        L.gosurf_sdf_lattice.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(C.c_float), C.c_float,
+                                         C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                         C.c_void_p]
+        L.gosurf_marching_tetrahedra.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_float, C.c_int32, C.c_int32,
+                                                 C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         for f in ("gosurf_sample_rays", "gosurf_forward", "gosurf_backward", "gosurf_adam_step",
                   "gosurf_refresh_bf16", "gosurf_proposal_forward", "gosurf_proposal_targets",
                   "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_step",
-                  "gosurf_importance_sample"):
+                  "gosurf_importance_sample", "gosurf_sdf_lattice", "gosurf_marching_tetrahedra"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -471,3 +479,38 @@ def gosurf_importance_sample(model, grid, mlp, coarse, cfg, out=None, workspace=
         C.byref(model), C.byref(p), C.byref(cc), C.byref(cfg), C.byref(oc), _ptr(workspace), workspace.numel(),
         _stream(stream)))
     return out
+
+
+def gosurf_lattice_workspace_bytes(nx, ny, layers):
+    return int(lib().gosurf_lattice_workspace_bytes(nx, ny, layers))
+
+
+def _vec3(p):
+    return (C.c_float * 3)(*[float(v) for v in p])
+
+
+def gosurf_sdf_lattice(model, grid, mlp, p0, h, dims, phi=None, workspace=None, grid_bf16=None, stream=None):
+    """SDF on the lattice p0 + h (i, j, k), dims = (nx, ny, nz); returns phi [nz, ny, nx]."""
+    nx, ny, nz = dims
+    if phi is None:
+        phi = torch.empty(nz, ny, nx, device=grid.device, dtype=torch.float32)
+    if workspace is None:
+        workspace = torch.empty(gosurf_lattice_workspace_bytes(nx, ny, nz), dtype=torch.uint8, device=grid.device)
+    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
+    _check("gosurf_sdf_lattice", lib().gosurf_sdf_lattice(
+        C.byref(model), C.byref(p), _vec3(p0), float(h), nx, ny, nz, _ptr(phi, F32), _ptr(workspace),
+        workspace.numel(), _stream(stream)))
+    return phi
+
+
+def gosurf_marching_tetrahedra(phi, p0, h, max_triangles, triangles=None, count=None, stream=None):
+    """Triangles [max_triangles, 3, 3] and the device count (int32 [1]) of the zero level set of phi [nz, ny, nx]."""
+    nz, ny, nx = phi.shape
+    if triangles is None:
+        triangles = torch.empty(max_triangles, 3, 3, device=phi.device, dtype=torch.float32)
+    if count is None:
+        count = torch.empty(1, device=phi.device, dtype=torch.int32)
+    _check("gosurf_marching_tetrahedra", lib().gosurf_marching_tetrahedra(
+        _ptr(phi, F32), _vec3(p0), float(h), nx, ny, nz, _ptr(triangles, F32), max_triangles,
+        _ptr(count, torch.int32), _stream(stream)))
+    return triangles, count

@@ -1,0 +1,127 @@
+"""Surface extraction on the device against the FP64 oracle (oracle/mesh.py).
+
+Marching tetrahedra decides inside/outside by phi < 0; on identical float32
+lattices both sides take the same decisions, so the triangle count is exact
+and the triangles agree to float32 rounding of the crossing points.  The SDF
+lattice is compared at the same float32 lattice positions to the forward
+tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy.spatial import cKDTree
+
+import synth
+from oracle import mesh as MS
+from tests.helpers import FWD_TOL, check_close, sphere_case
+
+pytestmark = pytest.mark.gpu
+
+OB3 = 2112            # packed offset of the geometry decoder's output bias (b3[0] is phi's)
+
+
+def _G():
+    from paper_2206_14735_amd import gosurf as G
+    G.lib()
+    return G
+
+
+def _area(t):
+    t = np.asarray(t, dtype=np.float64)
+    return 0.5 * np.linalg.norm(np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0]), axis=1).sum()
+
+
+def _f32_lattice(p0, h, dims):
+    """Lattice positions rounded as the device forms them (float32 i*h, then + p0)."""
+    nx, ny, nz = dims
+    h32 = np.float32(h)
+    ax = [np.float32(np.float32(np.arange(n, dtype=np.float32) * h32) + np.float32(p0[a]))
+          for a, n in enumerate((nx, ny, nz))]
+    z, y, x = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.stack([x, y, z], -1).reshape(-1, 3).astype(np.float64)
+
+
+def _compare_meshes(got, count, ref, tol):
+    assert count == len(ref), (count, len(ref))
+    cg = np.asarray(got, np.float64).mean(1)
+    cr = ref.mean(1)
+    d1, _ = cKDTree(cr).query(cg)
+    d2, _ = cKDTree(cg).query(cr)
+    print(f"{count} triangles; centroid distance max {max(d1.max(), d2.max()):.2e}", flush=True)
+    assert d1.max() <= tol and d2.max() <= tol
+    assert _area(got) == pytest.approx(_area(ref), rel=1e-5)
+
+
+def test_marching_tetrahedra_matches_oracle_on_an_identical_lattice():
+    G = _G()
+    rng = np.random.default_rng(8)
+    dims = (37, 29, 23)                     # ragged against 256-thread blocks
+    h, p0 = 0.05, (-0.9, -0.7, -0.55)
+    x = MS.lattice_points(p0, h, dims)
+    phi = (np.linalg.norm(x - [0.05, -0.02, 0.0], axis=1) - 0.45) + 0.03 * np.sin(7 * x[:, 0]) * np.cos(5 * x[:, 1])
+    phi = np.float32(phi + 0.002 * rng.standard_normal(phi.shape)).reshape(dims[2], dims[1], dims[0])
+    ref = MS.marching_tetrahedra(np.float64(phi), p0, h)
+    tris, cnt = G.gosurf_marching_tetrahedra(torch.as_tensor(phi).cuda(), p0, h, max_triangles=len(ref) + 100)
+    torch.cuda.synchronize()
+    n = int(cnt.item())
+    _compare_meshes(tris[:n].cpu().numpy(), n, ref, 1e-5)
+
+
+def test_marching_tetrahedra_reports_overflow_and_writes_within_capacity():
+    G = _G()
+    dims = (20, 20, 20)
+    h, p0 = 0.1, (-1.0, -1.0, -1.0)
+    x = MS.lattice_points(p0, h, dims)
+    phi = np.float32(np.linalg.norm(x, axis=1) - 0.6).reshape(20, 20, 20)
+    ref = MS.marching_tetrahedra(np.float64(phi), p0, h)
+    cap = len(ref) // 3
+    guard = torch.full((cap + 50, 3, 3), 7.0, device="cuda")
+    tris, cnt = G.gosurf_marching_tetrahedra(torch.as_tensor(phi).cuda(), p0, h, max_triangles=cap,
+                                             triangles=guard)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == len(ref)
+    assert torch.all(guard[cap:] == 7.0)     # nothing written past the capacity
+    assert torch.all(guard[:cap].abs() <= 1.0)
+
+
+def test_sdf_lattice_matches_oracle_over_several_slabs():
+    G = _G()
+    # the unshifted field: phi stays away from 0 (0.04-0.15), where the forward
+    # tolerance applies entry by entry; near 0, phi is a difference of terms of
+    # ~0.1 and carries their float32 rounding (~1e-7) as absolute error
+    L, fr, b, grid, mlp = sphere_case(M=8, S=0, grid_std=0.3)
+    dims = (23, 19, 17)
+    h = 0.09
+    p0 = (L.p0[0] + 0.013, L.p0[1] + 0.021, L.p0[2] + 0.007)
+    model = G.make_model(L)
+    ws = torch.empty(G.gosurf_lattice_workspace_bytes(dims[0], dims[1], 5), dtype=torch.uint8, device="cuda")
+    phi = G.gosurf_sdf_lattice(model, grid.cuda().contiguous(), mlp.cuda().contiguous(), p0, h, dims, workspace=ws)
+    torch.cuda.synchronize()
+    x = _f32_lattice(p0, h, dims)
+    assert np.all(x <= np.asarray(L.p1)) and np.all(x >= np.asarray(L.p0))
+    ref = MS.field_sdf(grid.numpy(), mlp.numpy(), L)(x)
+    check_close("lattice phi", phi.cpu().numpy().reshape(-1), ref, FWD_TOL)
+
+
+def test_mesh_of_the_field_matches_oracle():
+    G = _G()
+    L, fr, b, grid, mlp = sphere_case(M=8, S=0, grid_std=0.3)
+    mlp[OB3] -= 0.095     # shift phi so that its zero level set runs through the lattice
+    dims = (41, 41, 41)
+    h = 0.045
+    p0 = (L.p0[0] + 0.01, L.p0[1] + 0.01, L.p0[2] + 0.01)
+    model = G.make_model(L)
+    phi = G.gosurf_sdf_lattice(model, grid.cuda().contiguous(), mlp.cuda().contiguous(), p0, h, dims)
+    ref_phi = MS.field_sdf(grid.numpy(), mlp.numpy(), L)(_f32_lattice(p0, h, dims)).reshape(dims[2], dims[1], dims[0])
+    ref = MS.marching_tetrahedra(ref_phi, p0, h)
+    assert len(ref) > 100
+    tris, cnt = G.gosurf_marching_tetrahedra(phi, p0, h, max_triangles=2 * len(ref) + 1000)
+    torch.cuda.synchronize()
+    n = int(cnt.item())
+    got = tris[:n].cpu().numpy()
+    # the SDF differs by float32 rounding, so a few lattice values near 0 may change sign
+    near_zero = float(np.mean(np.abs(ref_phi) < 1e-5))
+    print(f"device {n} triangles, oracle {len(ref)}; lattice values within 1e-5 of 0: {near_zero:.2e}", flush=True)
+    assert abs(n - len(ref)) <= max(2, 0.001 * len(ref))
+    d, _ = cKDTree(ref.mean(1)).query(np.float64(got).mean(1))
+    assert np.mean(d <= 1e-4) >= 0.999
