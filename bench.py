@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--compare-phase1", type=int, default=300,
                     help="shared plain FP32 steps (65536 rays) before the two continuations")
     ap.add_argument("--compare-phase2", type=int, default=300, help="steps of each continuation (timed)")
+    ap.add_argument("--mesh", type=float, default=0.0,
+                    help="also extract the surface on a lattice of this spacing (m) after --mesh-train more steps")
+    ap.add_argument("--mesh-train", type=int, default=1000)
     return ap.parse_args()
 
 
@@ -155,6 +158,55 @@ def cpu_baseline(w, frames_cpu, grid, mlp, n_rays):
             "sample": f"{n_rays} rays x {w.n_samples} samples + {S} smoothness pairs fwd+bwd over the full "
                       f"grid ({t_fb:.1f} s), scaled by {w.M}/{n_rays}, plus one dense Adam step over all "
                       f"{grid.numel() + mlp.numel()} parameters ({t_adam:.1f} s)"}
+
+
+def mesh_measure(a, G, rec, w, scene, torch):
+    """SDF lattice over the grid box and marching tetrahedra on it, timed with
+    HIP events; accuracy = |analytic scene SDF| at triangle centroids."""
+    for _ in range(a.mesh_train):
+        rec.step()
+    torch.cuda.synchronize()
+    lay = rec.layout
+    h = a.mesh
+    dims = tuple(int((lay.p1[q] - lay.p0[q]) / h) + 1 for q in range(3))
+    nx, ny, nz = dims
+    n_pts = nx * ny * nz
+    layers = min(nz, 64)
+    ws = torch.empty(G.gosurf_lattice_workspace_bytes(nx, ny, layers), dtype=torch.uint8, device="cuda")
+    phi = torch.empty(nz, ny, nx, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    G.gosurf_sdf_lattice(rec.model, rec.grid, rec.mlp, lay.p0, h, dims, phi=phi, workspace=ws,
+                         grid_bf16=rec.grid_bf16)              # warm-up
+    ev[0].record()
+    G.gosurf_sdf_lattice(rec.model, rec.grid, rec.mlp, lay.p0, h, dims, phi=phi, workspace=ws,
+                         grid_bf16=rec.grid_bf16)
+    ev[1].record()
+    cap = 80_000_000
+    tris = torch.empty(cap, 3, 3, device="cuda")
+    count = torch.empty(1, device="cuda", dtype=torch.int32)
+    G.gosurf_marching_tetrahedra(phi, lay.p0, h, cap, triangles=tris, count=count)   # warm-up
+    ev[2].record()
+    G.gosurf_marching_tetrahedra(phi, lay.p0, h, cap, triangles=tris, count=count)
+    ev[3].record()
+    torch.cuda.synchronize()
+    sdf_ms, mt_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])
+    n_tri = G.triangle_count(count)
+    kept = min(n_tri, cap)
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    pick = torch.randint(0, max(kept, 1), (min(kept, 1_000_000),), device="cuda", generator=gen)
+    cen = tris[pick].double().mean(1)
+    err = scene.sdf(cen).abs() if kept else torch.zeros(1, device="cuda", dtype=torch.float64)
+    # per lattice point: 4 levels x 8 corners x 16 B gathered, t and ray index in, 4 outputs out, phi copied
+    per_pt = 32 * CORNER_BYTES[w.precision] + 8.0 + 16.0 + 8.0
+    gbs = per_pt * n_pts / (sdf_ms * 1e-3) / 1e9
+    return {"spacing_m": h, "lattice": list(dims), "points": n_pts, "train_steps_before": a.mesh_train,
+            "sdf_lattice_ms": round(sdf_ms, 3), "lattice_points_per_s": round(n_pts / (sdf_ms * 1e-3)),
+            "sdf_lattice_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": per_pt},
+            "marching_ms": round(mt_ms, 3), "cubes_per_s": round((nx - 1) * (ny - 1) * (nz - 1) / (mt_ms * 1e-3)),
+            "triangles": n_tri, "triangle_capacity": cap,
+            "accuracy_mm": {"mean": round(1e3 * float(err.mean()), 3), "median": round(1e3 * float(err.median()), 3),
+                            "centroids": int(pick.numel())}}
 
 
 def compare(a, G, synth, Reconstruction, torch):
@@ -460,6 +512,12 @@ def main():
         print(f"# oracle baseline: {cpu['sample']}", file=sys.stderr, flush=True)
 
     spr = rec.total // w.M                 # samples per ray of the batch the step trains on
+    mesh = None
+    if a.mesh > 0:
+        if scene is None:
+            raise SystemExit("--mesh needs a room workload (its analytic scene judges the accuracy)")
+        mesh = mesh_measure(a, G, rec, w, scene, torch)
+        print(f"# mesh: {mesh}", file=sys.stderr, flush=True)
     comparison = None
     if not a.no_compare:
         del rec
@@ -492,6 +550,8 @@ def main():
         "losses": losses,
         "comparison": comparison,
     }
+    if mesh is not None:
+        out["mesh"] = mesh
     print(json.dumps(out), flush=True)
 
 

@@ -397,10 +397,11 @@ gosurf_status gosurf_sdf_lattice(const gosurf_model* model, const gosurf_params*
    (p, q) crosses at p + phi_p / (phi_p - phi_q) (q - p).  Writes up to
    max_triangles triangles to triangles [max_triangles][3][3] (vertex
    positions, unordered, orientation not fixed) and the number found (which
-   may exceed max_triangles; the rest are then not written) to the device int
-   *count.  Errors: NULL, SHAPE, VALUE, HIP. */
+   may exceed max_triangles; the rest are then not written) to the device
+   *count (at most 12 per cube; (nx-1)(ny-1)(nz-1) * 12 < 2^32 is required).
+   Errors: NULL, SHAPE, VALUE, HIP. */
 gosurf_status gosurf_marching_tetrahedra(const float* phi, const float p0[3], float h, int32_t nx, int32_t ny,
-                                         int32_t nz, float* triangles, int64_t max_triangles, int32_t* count,
+                                         int32_t nz, float* triangles, int64_t max_triangles, uint32_t* count,
                                          void* stream);
 
 /* Round the float32 grid to its bfloat16 mirror (round to nearest even), as

@@ -185,7 +185,7 @@ struct MtArgs {
   int nx, ny, nz;
   float* tris;              // [max_tris][3][3]
   long long max_tris;
-  int* count;               // triangles found (may exceed max_tris)
+  unsigned* count;          // triangles found (may exceed max_tris)
 };
 
 }  // namespace gs

@@ -754,18 +754,19 @@ gosurf_status gosurf_sdf_lattice(const gosurf_model* model, const gosurf_params*
 }
 
 gosurf_status gosurf_marching_tetrahedra(const float* phi, const float p0[3], float h, int32_t nx, int32_t ny,
-                                         int32_t nz, float* triangles, int64_t max_triangles, int32_t* count,
+                                         int32_t nz, float* triangles, int64_t max_triangles, uint32_t* count,
                                          void* stream) {
   gosurf_status st;
   if ((st = check_lattice(p0, h, nx, ny, nz)) != GOSURF_OK) return st;
   if (!phi || !count || (max_triangles > 0 && !triangles)) return fail(GOSURF_ERR_NULL, "an array is NULL");
   if (max_triangles < 0) return fail(GOSURF_ERR_VALUE, "max_triangles < 0");
-  if ((long long)(nx - 1) * (ny - 1) * (nz - 1) * 12 >= (1LL << 31))
+  if ((long long)(nx - 1) * (ny - 1) * (nz - 1) * 12 >= (1LL << 32))
     return fail(GOSURF_ERR_SHAPE, "lattice too large for a 32-bit triangle count");
   gs::MtArgs a{};
   a.phi = phi;
   for (int q = 0; q < 3; ++q) a.p0[q] = p0[q];
-  a.h = h; a.nx = nx; a.ny = ny; a.nz = nz; a.tris = triangles; a.max_tris = max_triangles; a.count = count;
+  a.h = h; a.nx = nx; a.ny = ny; a.nz = nz; a.tris = triangles; a.max_tris = max_triangles;
+  a.count = reinterpret_cast<unsigned*>(count);
   if ((st = hip_check(gs::launch_marching_tets(a, (hipStream_t)stream), "marching tetrahedra")) != GOSURF_OK)
     return st;
   return ok();

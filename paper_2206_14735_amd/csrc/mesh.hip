@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void phi_copy_kernel(const float* __restrict__
     phi[e] = out4[4 * e];
 }
 
-__global__ void zero_count_kernel(int* count) { *count = 0; }
+__global__ void zero_count_kernel(unsigned* count) { *count = 0u; }
 
 // tetrahedra of a cube around its main diagonal 0-7
 __device__ __forceinline__ int tet_corner(int t, int q) {
@@ -94,9 +94,9 @@ __global__ __launch_bounds__(256) void marching_tets_kernel(MtArgs A) {
       if (lane >= d) incl += u;
     }
     const int total = __shfl(incl, 63, 64);
-    int off = 0;
-    if (lane == 63 && total > 0) off = atomicAdd(A.count, total);
-    off = __shfl(off, 63, 64);
+    unsigned off = 0u;
+    if (lane == 63 && total > 0) off = atomicAdd(A.count, (unsigned)total);
+    off = (unsigned)__shfl((int)off, 63, 64);
     if (!live || ntri == 0) continue;
     long long slot = (long long)off + incl - ntri;
 #pragma unroll

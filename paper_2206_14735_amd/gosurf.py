@@ -504,7 +504,8 @@ def gosurf_sdf_lattice(model, grid, mlp, p0, h, dims, phi=None, workspace=None, 
 
 
 def gosurf_marching_tetrahedra(phi, p0, h, max_triangles, triangles=None, count=None, stream=None):
-    """Triangles [max_triangles, 3, 3] and the device count (int32 [1]) of the zero level set of phi [nz, ny, nx]."""
+    """Triangles [max_triangles, 3, 3] and the device count of the zero level set of phi [nz, ny, nx]; the count
+    is an unsigned 32-bit value held in an int32 [1] tensor (read it with triangle_count())."""
     nz, ny, nx = phi.shape
     if triangles is None:
         triangles = torch.empty(max_triangles, 3, 3, device=phi.device, dtype=torch.float32)
@@ -514,3 +515,8 @@ def gosurf_marching_tetrahedra(phi, p0, h, max_triangles, triangles=None, count=
         _ptr(phi, F32), _vec3(p0), float(h), nx, ny, nz, _ptr(triangles, F32), max_triangles,
         _ptr(count, torch.int32), _stream(stream)))
     return triangles, count
+
+
+def triangle_count(count):
+    """The unsigned 32-bit triangle count written by gosurf_marching_tetrahedra."""
+    return int(count.item()) & 0xFFFFFFFF

@@ -63,7 +63,7 @@ def test_marching_tetrahedra_matches_oracle_on_an_identical_lattice():
     ref = MS.marching_tetrahedra(np.float64(phi), p0, h)
     tris, cnt = G.gosurf_marching_tetrahedra(torch.as_tensor(phi).cuda(), p0, h, max_triangles=len(ref) + 100)
     torch.cuda.synchronize()
-    n = int(cnt.item())
+    n = G.triangle_count(cnt)
     _compare_meshes(tris[:n].cpu().numpy(), n, ref, 1e-5)
 
 
@@ -79,7 +79,7 @@ def test_marching_tetrahedra_reports_overflow_and_writes_within_capacity():
     tris, cnt = G.gosurf_marching_tetrahedra(torch.as_tensor(phi).cuda(), p0, h, max_triangles=cap,
                                              triangles=guard)
     torch.cuda.synchronize()
-    assert int(cnt.item()) == len(ref)
+    assert G.triangle_count(cnt) == len(ref)
     assert torch.all(guard[cap:] == 7.0)     # nothing written past the capacity
     assert torch.all(guard[:cap].abs() <= 1.0)
 
@@ -117,7 +117,7 @@ def test_mesh_of_the_field_matches_oracle():
     assert len(ref) > 100
     tris, cnt = G.gosurf_marching_tetrahedra(phi, p0, h, max_triangles=2 * len(ref) + 1000)
     torch.cuda.synchronize()
-    n = int(cnt.item())
+    n = G.triangle_count(cnt)
     got = tris[:n].cpu().numpy()
     # the SDF differs by float32 rounding, so a few lattice values near 0 may change sign
     near_zero = float(np.mean(np.abs(ref_phi) < 1e-5))
