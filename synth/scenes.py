@@ -106,6 +106,46 @@ class RoomScene:
         self.noise = 0.15 + 0.7 * torch.rand(37, 29, 17, 3, generator=g, dtype=torch.float64)
         self.tint = 0.6 + 0.4 * torch.rand(1 + n_objects, 3, generator=g, dtype=torch.float64)
 
+    def surface_samples(self, density, seed=0):
+        """Points on the scene's surfaces, `density` per square metre on average
+        (walls and floor up to the box height, box faces, spheres), without the
+        parts inside another solid: [N, 3] float64."""
+        g = torch.Generator().manual_seed(seed)
+        pts = []
+
+        def rect(origin, e1, e2):
+            origin, e1, e2 = (torch.as_tensor(v, dtype=torch.float64) for v in (origin, e1, e2))
+            area = float(torch.linalg.norm(torch.linalg.cross(e1, e2)))
+            n = int(torch.poisson(torch.tensor(area * density, dtype=torch.float64), generator=g).item())
+            a = torch.rand(n, 1, generator=g, dtype=torch.float64)
+            b = torch.rand(n, 1, generator=g, dtype=torch.float64)
+            pts.append(origin + a * e1 + b * e2)
+
+        X, Y, Z = self.bounds_max
+        rect((0, 0, 0), (0, Y, 0), (0, 0, Z))
+        rect((X, 0, 0), (0, Y, 0), (0, 0, Z))
+        rect((0, 0, 0), (X, 0, 0), (0, 0, Z))
+        rect((0, Y, 0), (X, 0, 0), (0, 0, Z))
+        rect((0, 0, 0), (X, 0, 0), (0, Y, 0))
+        for lo, hi in self.boxes:
+            d = (hi - lo).tolist()
+            for axis in range(3):
+                u, v = [a for a in range(3) if a != axis]
+                e1 = [0.0, 0.0, 0.0]
+                e2 = [0.0, 0.0, 0.0]
+                e1[u], e2[v] = d[u], d[v]
+                for side in (lo, hi):
+                    o = lo.tolist()
+                    o[axis] = float(side[axis])
+                    rect(o, e1, e2)
+        for c, r in self.spheres:
+            n = int(torch.poisson(torch.tensor(4 * math.pi * r * r * density, dtype=torch.float64),
+                                  generator=g).item())
+            d = torch.randn(n, 3, generator=g, dtype=torch.float64)
+            pts.append(c + r * d / d.norm(dim=1, keepdim=True))
+        p = torch.cat(pts, 0)
+        return p[self.sdf(p).abs() < 1e-6]
+
     def sdf(self, p):
         lo = torch.tensor(self.bounds_min, dtype=p.dtype, device=p.device)
         hi = torch.tensor(self.bounds_max, dtype=p.dtype, device=p.device)
