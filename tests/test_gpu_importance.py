@@ -136,3 +136,26 @@ def test_importance_rejects_bad_shapes():
         G.gosurf_importance_sample(model, g, m, db, G.make_importance_cfg(steps=3, n_add=70))
     with pytest.raises(G.GosurfError):
         G.gosurf_importance_sample(model, g, m, db, G.make_importance_cfg(steps=30, n_add=12))
+
+
+def test_importance_one_step_of_one_sample_matches_oracle():
+    G = _G()
+    L, fr, b, grid, mlp = sphere_case(M=65, S=0, grid_std=0.3)
+    n0 = b.t.size // 65
+    t0 = np.float32(np.asarray(b.t)).reshape(65, n0)
+    cfg = G.make_importance_cfg(steps=1, n_add=1, seed=9, step=11)
+    out = G.gosurf_importance_sample(G.make_model(L), grid.cuda().contiguous(), mlp.cuda().contiguous(),
+                                     G.RayBatch.from_host(b), cfg)
+    torch.cuda.synchronize()
+    got = out.t.cpu().numpy().reshape(65, n0 + 1)
+    np.testing.assert_array_equal(out.seg.cpu().numpy(), np.arange(66) * (n0 + 1))
+    P = OD.unpack(torch.as_tensor(mlp, dtype=torch.float64))
+    g64 = torch.as_tensor(grid, dtype=torch.float64)
+
+    def sdf(x):
+        return OD.geometry(OG.interp_all(g64, L, torch.as_tensor(x)), P)[:, 0].numpy()
+
+    ref = I.hierarchical(np.asarray(b.o), np.asarray(b.r), np.float64(t0), sdf, float(OD.sharpness(P)), L.p0, L.p1,
+                         1, 1, seed=9, iteration=11)
+    frac, _ = _report("one step of one", got, ref)
+    assert frac >= MIN_FRAC

@@ -125,3 +125,29 @@ def test_mesh_of_the_field_matches_oracle():
     assert abs(n - len(ref)) <= max(2, 0.001 * len(ref))
     d, _ = cKDTree(ref.mean(1)).query(np.float64(got).mean(1))
     assert np.mean(d <= 1e-4) >= 0.999
+
+
+@pytest.mark.parametrize("corner,count", [(0, 6), (7, 6), (1, 2), (6, 2)])
+def test_single_cube(corner, count):
+    G = _G()
+    phi = np.ones((2, 2, 2), dtype=np.float32)
+    bx, by, bz = corner & 1, (corner >> 1) & 1, (corner >> 2) & 1
+    phi[bz, by, bx] = -1.0
+    ref = MS.marching_tetrahedra(np.float64(phi), (0.0, 0.0, 0.0), 1.0)
+    assert len(ref) == count
+    tris, cnt = G.gosurf_marching_tetrahedra(torch.as_tensor(phi).cuda(), (0.0, 0.0, 0.0), 1.0, max_triangles=16)
+    torch.cuda.synchronize()
+    _compare_meshes(tris[:G.triangle_count(cnt)].cpu().numpy(), G.triangle_count(cnt), ref, 1e-6)
+
+
+def test_count_only_call():
+    G = _G()
+    dims = (16, 16, 16)
+    h, p0 = 0.1, (-0.8, -0.8, -0.8)
+    x = MS.lattice_points(p0, h, dims)
+    phi = np.float32(np.linalg.norm(x, axis=1) - 0.5).reshape(16, 16, 16)
+    ref = MS.marching_tetrahedra(np.float64(phi), p0, h)
+    empty = torch.empty(0, 3, 3, device="cuda")
+    _, cnt = G.gosurf_marching_tetrahedra(torch.as_tensor(phi).cuda(), p0, h, max_triangles=0, triangles=empty)
+    torch.cuda.synchronize()
+    assert G.triangle_count(cnt) == len(ref)
