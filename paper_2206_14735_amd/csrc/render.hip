@@ -77,24 +77,25 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
     R.alpha[c] = a;
   }
   // transmittance: exclusive product of (1 - alpha)
+  // (one store per chunk of T and w, so that they stay in registers)
   float carry = 1.f;
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
-    if (c >= nch) {
-      R.T[c] = R.w[c] = 0.f;
-      continue;
-    }
-    float v = 1.f - R.alpha[c];
+    float Tc = 0.f;
+    if (c < nch) {
+      float v = 1.f - R.alpha[c];
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const float u = __shfl_up(v, d, 64);
-      if (lane >= d) v *= u;
+      for (int d = 1; d < 64; d <<= 1) {
+        const float u = __shfl_up(v, d, 64);
+        if (lane >= d) v *= u;
+      }
+      float ex = __shfl_up(v, 1, 64);
+      if (lane == 0) ex = 1.f;
+      Tc = carry * ex;
+      carry *= __shfl(v, 63, 64);
     }
-    float ex = __shfl_up(v, 1, 64);
-    if (lane == 0) ex = 1.f;
-    R.T[c] = carry * ex;
-    carry *= __shfl(v, 63, 64);
-    R.w[c] = R.T[c] * R.alpha[c];
+    R.T[c] = Tc;
+    R.w[c] = Tc * R.alpha[c];
   }
   float cr = 0.f, cg = 0.f, cbl = 0.f, dd = 0.f, ws = 0.f;
 #pragma unroll
