@@ -151,3 +151,36 @@ def test_count_only_call():
     _, cnt = G.gosurf_marching_tetrahedra(torch.as_tensor(phi).cuda(), p0, h, max_triangles=0, triangles=empty)
     torch.cuda.synchronize()
     assert G.triangle_count(cnt) == len(ref)
+
+
+def test_bf16_lattice_and_importance_follow_fp32():
+    """The BF16 paths (gathers from the bfloat16 mirror, bf16 decoders) of the SDF lattice and of the
+    importance sampler stay within bfloat16 error of the FP32 paths."""
+    G = _G()
+    L, fr, b, grid, mlp = sphere_case(M=128, S=0, grid_std=0.3)
+    g, m = grid.cuda().contiguous(), mlp.cuda().contiguous()
+    gb = torch.empty(g.shape, dtype=torch.bfloat16, device="cuda")
+    G.gosurf_refresh_bf16(g, gb)
+    m32, m16 = G.make_model(L, G.FP32), G.make_model(L, G.BF16)
+    dims, h = (21, 19, 17), 0.1
+    p0 = (L.p0[0] + 0.02, L.p0[1] + 0.02, L.p0[2] + 0.02)
+    phi32 = G.gosurf_sdf_lattice(m32, g, m, p0, h, dims)
+    phi16 = G.gosurf_sdf_lattice(m16, g, m, p0, h, dims, grid_bf16=gb)
+    db = G.RayBatch.from_host(b)
+    cfg = G.make_importance_cfg(seed=3, step=2)
+    out32 = G.gosurf_importance_sample(m32, g, m, db, cfg)
+    t32 = out32.t.clone()
+    out16 = G.gosurf_importance_sample(m16, g, m, db, cfg, grid_bf16=gb)
+    torch.cuda.synchronize()
+    scale = float(phi32.abs().max())
+    err = float((phi16 - phi32).abs().max()) / scale
+    print(f"BF16 lattice phi: max error {err:.2e} of the largest |phi|", flush=True)
+    assert 0 < err < 0.05
+    n0 = b.t.size // 128
+    t16 = out16.t.view(128, -1)
+    assert torch.all(t16[:, 1:] >= t16[:, :-1])
+    assert torch.equal(out16.seg, out32.seg)
+    d = (t16 - t32.view(128, -1)).abs()
+    print(f"BF16 importance depths: median difference {float(d.median()):.2e} m", flush=True)
+    assert float(d.median()) < 1e-2
+    assert t16.shape[1] == n0 + 36
