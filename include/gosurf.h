@@ -156,9 +156,10 @@ typedef struct {
    t[seg[m] .. seg[m+1]-1], sorted ascending, at most
    GOSURF_MAX_SAMPLES_PER_RAY per ray; ray_of[s] is the ray of sample s. */
 typedef struct {
-  int32_t M;            /* rays */
-  int32_t total;        /* samples, = seg[M]; with a proposal the capacity (seg[M], on the
-                           device, is then the actual count) */
+  int32_t M;            /* rays, >= 1 (an empty batch is rejected with GOSURF_ERR_SHAPE) */
+  int32_t total;        /* samples, = seg[M], M <= total < 2^29 (else GOSURF_ERR_SHAPE); with
+                           a proposal the capacity (seg[M], on the device, is then the
+                           actual count) */
   int32_t S;            /* smoothness pairs */
   float* o;             /* [M][3] ray origin (camera centre) */
   float* r;             /* [M][3] ray direction (camera-z component 1) */

@@ -144,3 +144,121 @@ def test_adam_rejects_bad_step_and_sizes(lib):
     c.step = 1
     s.grid_numel = 6                       # grid group must be a multiple of 4
     assert lib.gosurf_adam_step(C.byref(c), C.byref(s), None) == 2
+
+
+def _batch(M, total, S=0):
+    b = G.RayBatchC()
+    b.M, b.total, b.S = M, total, S
+    for f in ("o", "r", "rgb", "depth", "t", "seg", "ray_of"):
+        setattr(b, f, 64)
+    return b
+
+
+def _forward(lib, b):
+    m = _model()
+    p = G.Params(16, None, 16)
+    lc = G.make_loss_cfg()
+    out = G.FwdOutC(16, 16, 16, 16, 16, None)
+    return lib.gosurf_forward(C.byref(m), C.byref(p), C.byref(b), C.byref(lc), C.byref(out), 256, 1 << 30, None)
+
+
+def test_forward_rejects_empty_and_oversized_batches(lib):
+    assert _forward(lib, _batch(0, 0)) == 2 and b"M = 0" in lib.gosurf_last_error()
+    assert _forward(lib, _batch(8, 4)) == 2 and b"total" in lib.gosurf_last_error()
+    assert _forward(lib, _batch(8, 1 << 29)) == 2 and b"too many samples" in lib.gosurf_last_error()
+    assert _forward(lib, _batch(8, 64, -1)) == 2
+    b = _batch(8, 64, 16)                  # pairs without their arrays
+    assert _forward(lib, b) == 1 and b"smoothness" in lib.gosurf_last_error()
+
+
+def test_backward_rejects_bf16_model_without_mirror(lib):
+    m = G.make_model(_model_layout(), G.BF16)
+    p = G.Params(16, None, 16)
+    g = G.GradsC(16, 16)
+    out = G.FwdOutC(16, 16, 16, 16, 16, None)
+    lc = G.make_loss_cfg()
+    st = lib.gosurf_backward(C.byref(m), C.byref(p), C.byref(_batch(8, 64)), C.byref(lc), C.byref(out), 1.0,
+                             C.byref(g), 256, 1 << 30, None)
+    assert st == 1 and b"grid_bf16" in lib.gosurf_last_error()
+
+
+def _model_layout():
+    import synth
+    return synth.configs.SPHERE.layout()
+
+
+def test_size_queries_reject_negative_or_empty_sizes(lib):
+    m = _model()
+    assert G.gosurf_workspace_bytes(m, -1, 64, 0) == 0
+    assert lib.gosurf_batch_samples(None) == -1
+    cfg = G.make_importance_cfg()
+    assert lib.gosurf_importance_workspace_bytes(0, 96, C.byref(cfg)) == 0
+    assert lib.gosurf_importance_workspace_bytes(64, 96, None) == 0
+    assert lib.gosurf_lattice_workspace_bytes(0, 4, 4) == 0
+    assert lib.gosurf_proposal_workspace_bytes(0) == 0
+
+
+def test_importance_rejects_bad_configs_and_shapes(lib):
+    m = _model()
+    rays = _batch(8, 8 * 96)
+
+    def step(cfg, rays=rays, index=0):
+        return lib.gosurf_importance_step(C.byref(m), 16, C.byref(rays), 16, C.byref(cfg), index, 16, None)
+
+    assert step(G.make_importance_cfg(steps=0)) == 4
+    assert step(G.make_importance_cfg(steps=9)) == 4
+    assert step(G.make_importance_cfg(n_add=0)) == 4
+    assert step(G.make_importance_cfg(n_add=65)) == 4
+    assert step(G.make_importance_cfg(weight_eps=0.0)) == 4
+    assert step(G.make_importance_cfg(weight_eps=float("nan"))) == 4
+    assert step(G.make_importance_cfg(), index=-1) == 4
+    assert step(G.make_importance_cfg(), rays=_batch(8, 8 * 96 + 3)) == 2     # not n samples on every ray
+    assert step(G.make_importance_cfg(), rays=_batch(8, 8)) == 2              # one sample per ray
+    assert step(G.make_importance_cfg(), rays=_batch(0, 0)) == 2
+    assert lib.gosurf_importance_step(C.byref(m), None, C.byref(rays), 16, C.byref(G.make_importance_cfg()), 0,
+                                      16, None) == 1
+    # the full sampler: more samples per ray than a ray may hold, and a mis-sized output
+    p = G.Params(16, None, 16)
+    out = _batch(8, 8 * 96)
+    cfg = G.make_importance_cfg(steps=3, n_add=60)
+    st = lib.gosurf_importance_sample(C.byref(m), C.byref(p), C.byref(rays), C.byref(cfg), C.byref(out), 256,
+                                      1 << 30, None)
+    assert st == 2 and b"at most" in lib.gosurf_last_error()
+    st = lib.gosurf_importance_sample(C.byref(m), C.byref(p), C.byref(rays), C.byref(G.make_importance_cfg()),
+                                      C.byref(out), 256, 1 << 30, None)
+    assert st == 2 and b"expected" in lib.gosurf_last_error()
+    out = _batch(8, 8 * 132)
+    st = lib.gosurf_importance_sample(C.byref(m), C.byref(p), C.byref(rays), C.byref(G.make_importance_cfg()),
+                                      C.byref(out), 256, 16, None)
+    assert st == 5
+
+
+def test_lattice_and_marching_reject_bad_arguments(lib):
+    m = _model()
+    p = G.Params(16, None, 16)
+    p0 = (C.c_float * 3)(0.0, 0.0, 0.0)
+
+    def lattice(h, nx, ny, nz, p0=p0, ws_bytes=1 << 30):
+        return lib.gosurf_sdf_lattice(C.byref(m), C.byref(p), p0, h, nx, ny, nz, 16, 256, ws_bytes, None)
+
+    assert lattice(0.01, 1, 4, 4) == 2
+    assert lattice(0.0, 4, 4, 4) == 4
+    assert lattice(float("inf"), 4, 4, 4) == 4
+    assert lattice(0.01, 4, 4, 4, p0=(C.c_float * 3)(0.0, float("nan"), 0.0)) == 4
+    assert lattice(0.01, 4, 4, 4, ws_bytes=64) == 5
+    assert lib.gosurf_sdf_lattice(C.byref(m), C.byref(p), p0, 0.01, 4, 4, 4, None, 256, 1 << 30, None) == 1
+
+    def marching(nx, ny, nz, max_tris=16, tris=16, count=16, h=0.01):
+        return lib.gosurf_marching_tetrahedra(16, p0, h, nx, ny, nz, tris, max_tris, count, None)
+
+    assert marching(4, 1, 4) == 2
+    assert marching(4, 4, 4, h=-0.01) == 4
+    assert marching(4, 4, 4, max_tris=-1) == 4
+    assert marching(4, 4, 4, count=None) == 1
+    assert marching(4, 4, 4, tris=None) == 1            # triangles needed when max_triangles > 0
+    assert marching(1000, 1000, 1000) == 2 and b"32-bit" in lib.gosurf_last_error()
+
+
+def test_time_kernel_rejects_unknown_kernel(lib):
+    assert lib.gosurf_time_kernel(7, None, None) == 4
+    assert lib.gosurf_time_kernel(0, None, None) == 0
