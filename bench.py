@@ -35,7 +35,9 @@ def parse():
     ap.add_argument("--workload", default="room")
     ap.add_argument("--frames", type=int, default=None, help="override the number of frames")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=512)
+    ap.add_argument("--cpu-rays", type=int, default=0,
+                    help="rays of the oracle baseline's sample (0: the workload's whole batch)")
+    ap.add_argument("--cpu-reps", type=int, default=7, help="oracle baseline steps timed")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for memory counters)")
     ap.add_argument("--no-compare", action="store_true",
@@ -130,11 +132,11 @@ def measured_traffic(kernel, workload):
     return entry.get("bytes_per_launch")
 
 
-def cpu_baseline(w, frames_cpu, grid, mlp, n_rays):
-    """FP64 oracle on a bounded sample of the same workload: one step's
-    forward+backward on `n_rays` rays (with the proportional share of
-    smoothness pairs) over the full grid, plus one dense Adam update of all
-    parameters; scaled to the full batch."""
+def cpu_baseline(w, frames_cpu, grid, mlp, n_rays, reps=1):
+    """FP64 oracle on a bounded sample of the same workload: `reps` steps,
+    each a forward+backward on `n_rays` rays (with the proportional share of
+    smoothness pairs) over the full grid and one dense Adam update of all
+    parameters; the forward+backward time is scaled to the full batch."""
     import numpy as np
     import torch
 
@@ -146,19 +148,23 @@ def cpu_baseline(w, frames_cpu, grid, mlp, n_rays):
                                    S, w.delta_s, seed=0, step=0)
     g64 = grid.double().numpy()
     m64 = mlp.double().numpy()
-    t0 = time.perf_counter()
-    res = ostep.evaluate(g64, m64, L, b, ostep.LossCfg(w.lambdas, w.trunc, w.alpha_fs))
-    t_fb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ostep.adam(g64, res["grad_grid"].numpy(), np.zeros_like(g64), np.zeros_like(g64), 1, w.lr_grid)
-    ostep.adam(m64, res["grad_mlp"].numpy(), np.zeros_like(m64), np.zeros_like(m64), 1, w.lr_mlp)
-    t_adam = time.perf_counter() - t0
-    t_step = t_fb * (w.M / n_rays) + t_adam
+    t_fb = t_adam = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = ostep.evaluate(g64, m64, L, b, ostep.LossCfg(w.lambdas, w.trunc, w.alpha_fs))
+        t_fb += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ostep.adam(g64, res["grad_grid"].numpy(), np.zeros_like(g64), np.zeros_like(g64), 1, w.lr_grid)
+        ostep.adam(m64, res["grad_mlp"].numpy(), np.zeros_like(m64), np.zeros_like(m64), 1, w.lr_mlp)
+        t_adam += time.perf_counter() - t0
+        del res
+    t_step = (t_fb * (w.M / n_rays) + t_adam) / reps
+    scaled = f", scaled by {w.M}/{n_rays}" if n_rays != w.M else ""
     return {"value": w.M * w.n_samples / t_step, "unit": "ray-samples/s", "cores": torch.get_num_threads(),
             "kind": "oracle",
-            "sample": f"{n_rays} rays x {w.n_samples} samples + {S} smoothness pairs fwd+bwd over the full "
-                      f"grid ({t_fb:.1f} s), scaled by {w.M}/{n_rays}, plus one dense Adam step over all "
-                      f"{grid.numel() + mlp.numel()} parameters ({t_adam:.1f} s)"}
+            "sample": f"{reps} step(s) of {n_rays} rays x {w.n_samples} samples + {S} smoothness pairs fwd+bwd "
+                      f"over the full grid ({t_fb:.1f} s){scaled}, each with one dense Adam step over all "
+                      f"{grid.numel() + mlp.numel()} parameters ({t_adam:.1f} s in all)"}
 
 
 def mesh_measure(a, G, rec, w, scene, frames, torch):
@@ -525,8 +531,9 @@ def main():
     elif not a.no_cpu_baseline:
         fr_cpu = synth.Frames(frames.rgb.cpu(), frames.depth.cpu(), frames.c2w.cpu(), frames.fx, frames.fy,
                               frames.cx, frames.cy)
-        print(f"# oracle baseline on {a.cpu_rays} rays ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, fr_cpu, grid, mlp, a.cpu_rays)
+        n_cpu = a.cpu_rays if 0 < a.cpu_rays < w.M else w.M
+        print(f"# oracle baseline: {a.cpu_reps} step(s) on {n_cpu} rays ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, fr_cpu, grid, mlp, n_cpu, a.cpu_reps)
         print(f"# oracle baseline: {cpu['sample']}", file=sys.stderr, flush=True)
 
     spr = rec.total // w.M                 # samples per ray of the batch the step trains on
