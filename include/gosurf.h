@@ -16,7 +16,9 @@
  *                       second-order grid-sampler blocks that the Eikonal and
  *                       smoothness terms need (supplementary "Second-order Grid
  *                       Sampler", Eqs. second_sdf_grad_theta, second_sdf_grad_omega)
- *   gosurf_adam_step    Adam over all parameters (implementation details)
+ *   gosurf_adam_step    Adam over all parameters (implementation details);
+ *                       gosurf_adam_step_checked skips a step whose
+ *                       gradients hold an inf or NaN
  *
  * A precision variant runs the decoders in bfloat16 on the matrix cores with
  * float32 accumulation and reads grid features from a bfloat16 mirror of the
@@ -31,9 +33,11 @@
  *   gosurf_workspace_bytes().
  * - Every call only validates its arguments on the host and enqueues kernels
  *   on `stream` (a hipStream_t; NULL = the default stream).  It returns
- *   GOSURF_OK or an error status and never blocks.  Device faults surface at
+ *   GOSURF_OK or an error status and never blocks (gosurf_adam_step_checked
+ *   alone waits for its stream).  Device faults surface at
  *   the caller's next synchronisation.  On error nothing has been enqueued
- *   and gosurf_last_error() (thread-local) describes the problem.
+ *   (GOSURF_ERR_NONFINITE aside) and gosurf_last_error() (thread-local)
+ *   describes the problem.
  * - No C++ exception crosses this interface.  Calls are re-entrant; calls that
  *   share output or workspace buffers must be ordered by the caller.
  *
@@ -82,7 +86,8 @@ typedef enum {
   GOSURF_ERR_ALIGN = 3,      /* a pointer is not suitably aligned */
   GOSURF_ERR_VALUE = 4,      /* a scalar argument is invalid (NaN, <= 0, ...) */
   GOSURF_ERR_WORKSPACE = 5,  /* workspace missing or smaller than required */
-  GOSURF_ERR_HIP = 6         /* a kernel launch failed */
+  GOSURF_ERR_HIP = 6,        /* a kernel launch failed */
+  GOSURF_ERR_NONFINITE = 7   /* gosurf_adam_step_checked: a gradient was inf or NaN, the update skipped */
 } gosurf_status;
 
 typedef enum { GOSURF_FP32 = 0, GOSURF_BF16 = 1 } gosurf_precision;
@@ -418,6 +423,21 @@ gosurf_status gosurf_refresh_bf16(const float* grid, uint16_t* grid_bf16, int64_
    Gradients are zeroed and the bfloat16 mirror (if any) refreshed in the same
    pass.  Errors: NULL, SHAPE, ALIGN, VALUE, HIP. */
 gosurf_status gosurf_adam_step(const gosurf_adam_cfg* cfg, gosurf_adam_state* state, void* stream);
+
+/* gosurf_adam_step behind a guard against non-finite gradients, for callers
+   that scale the loss (the BF16 precision variant) or otherwise want a step
+   with an inf or NaN gradient discarded rather than written into the
+   parameters and moments.  Clears *flag (a caller-owned device int32), sets
+   it to 1 if any entry of grid_grad or mlp_grad is inf or NaN, and then
+   WAITS for the stream (the one call here that blocks) to read it.  Finite:
+   runs gosurf_adam_step and returns its status.  Non-finite: leaves the
+   parameters, moments and bfloat16 mirror unchanged, zeroes both gradient
+   arrays on the stream and returns GOSURF_ERR_NONFINITE (the check and the
+   zeroing have then been enqueued).  Extra traffic: one read of the
+   gradients (4 B per parameter).  Errors: NULL, SHAPE, ALIGN, VALUE, HIP,
+   NONFINITE. */
+gosurf_status gosurf_adam_step_checked(const gosurf_adam_cfg* cfg, gosurf_adam_state* state, int32_t* flag,
+                                       void* stream);
 
 #ifdef __cplusplus
 }

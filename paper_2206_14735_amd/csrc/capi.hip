@@ -24,6 +24,9 @@ hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smoo
 hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
                               float* tmp, float* ray_part, hipStream_t st);
 hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st);
+hipError_t launch_nonfinite_check(const float* grid_grad, long long n_grid, const float* mlp_grad, long long n_mlp,
+                                  int* flag, hipStream_t st);
+hipError_t launch_zero(float* a, long long n, hipStream_t st);
 hipError_t launch_sample(const SampleArgs& a, hipStream_t st);
 hipError_t launch_to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t st);
 hipError_t launch_sample_rays_only(const SampleArgs& a, hipStream_t st);
@@ -483,7 +486,11 @@ gosurf_status gosurf_refresh_bf16(const float* grid, uint16_t* grid_bf16, int64_
   return ok();
 }
 
-gosurf_status gosurf_adam_step(const gosurf_adam_cfg* c, gosurf_adam_state* s, void* stream) {
+}  // extern "C"
+
+namespace {
+
+gosurf_status check_adam(const gosurf_adam_cfg* c, const gosurf_adam_state* s) {
   if (!c || !s) return fail(GOSURF_ERR_NULL, "cfg and state must not be NULL");
   if (s->grid_numel > 0 && (!s->grid || !s->grid_grad || !s->grid_m || !s->grid_v))
     return fail(GOSURF_ERR_NULL, "a grid-group Adam array is NULL");
@@ -501,12 +508,43 @@ gosurf_status gosurf_adam_step(const gosurf_adam_cfg* c, gosurf_adam_state* s, v
   if (!(c->eps > 0.f) || !std::isfinite(c->lr_grid) || !std::isfinite(c->lr_mlp) ||
       !std::isfinite(c->inv_loss_scale))
     return fail(GOSURF_ERR_VALUE, "eps must be > 0 and rates finite");
+  return GOSURF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gosurf_status gosurf_adam_step(const gosurf_adam_cfg* c, gosurf_adam_state* s, void* stream) {
   gosurf_status st;
+  if ((st = check_adam(c, s)) != GOSURF_OK) return st;
   gosurf_adam_state copy = *s;
   mark(GOSURF_KERNEL_ADAM, true, (hipStream_t)stream);
   if ((st = hip_check(gs::launch_adam(*c, copy, (hipStream_t)stream), "adam")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_ADAM, false, (hipStream_t)stream);
   return ok();
+}
+
+gosurf_status gosurf_adam_step_checked(const gosurf_adam_cfg* c, gosurf_adam_state* s, int32_t* flag,
+                                       void* stream) {
+  gosurf_status st;
+  if ((st = check_adam(c, s)) != GOSURF_OK) return st;
+  if (!flag) return fail(GOSURF_ERR_NULL, "flag is NULL");
+  if (!aligned(flag, 4)) return fail(GOSURF_ERR_ALIGN, "flag must be 4-byte aligned");
+  hipStream_t h = (hipStream_t)stream;
+  if ((st = hip_check(gs::launch_nonfinite_check(s->grid_grad, s->grid_numel, s->mlp_grad, s->mlp_numel, flag, h),
+                      "non-finite check")) != GOSURF_OK)
+    return st;
+  int32_t bad = 0;
+  if ((st = hip_check(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, h), "flag copy")) != GOSURF_OK)
+    return st;
+  if ((st = hip_check(hipStreamSynchronize(h), "flag wait")) != GOSURF_OK) return st;
+  if (bad) {
+    if ((st = hip_check(gs::launch_zero(s->grid_grad, s->grid_numel, h), "gradient reset")) != GOSURF_OK) return st;
+    if ((st = hip_check(gs::launch_zero(s->mlp_grad, s->mlp_numel, h), "gradient reset")) != GOSURF_OK) return st;
+    return fail(GOSURF_ERR_NONFINITE, "a gradient is inf or NaN: the update was skipped and the gradients zeroed");
+  }
+  return gosurf_adam_step(c, s, stream);
 }
 
 }  // extern "C"

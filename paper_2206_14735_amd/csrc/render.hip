@@ -586,4 +586,50 @@ hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- non-finite gradient check
+// A float is non-finite when its exponent bits are all ones (inf or NaN);
+// tested on the bits so that no compiler flag can fold the test away.
+__device__ __forceinline__ bool nonfinite(float x) { return (__float_as_uint(x) & 0x7f800000u) == 0x7f800000u; }
+
+__global__ void set_flag_kernel(int* flag, int value) { *flag = value; }
+
+// *flag = 1 if any of a[0 .. n) is inf or NaN (a is 16-byte aligned); the
+// flag is cleared on the stream beforehand, and every writer stores the same value
+__global__ __launch_bounds__(256) void nonfinite_kernel(const float* __restrict__ a, long long n,
+                                                        int* __restrict__ flag) {
+  const long long n4 = n / 4;
+  const float4* a4 = reinterpret_cast<const float4*>(a);
+  bool bad = false;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
+    const float4 v = a4[i];
+    bad |= nonfinite(v.x) | nonfinite(v.y) | nonfinite(v.z) | nonfinite(v.w);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) bad |= nonfinite(a[4 * n4 + threadIdx.x]);
+  if (bad) flag[0] = 1;
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(float* __restrict__ a, long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) a[i] = 0.f;
+}
+
+static unsigned stream_blocks(long long n) {
+  long long b = (n + 255) / 256;
+  return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+hipError_t launch_nonfinite_check(const float* grid_grad, long long n_grid, const float* mlp_grad, long long n_mlp,
+                                  int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(set_flag_kernel, dim3(1), dim3(1), 0, st, flag, 0);
+  if (n_grid > 0)
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(stream_blocks(n_grid / 4)), dim3(256), 0, st, grid_grad, n_grid, flag);
+  if (n_mlp > 0)
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(stream_blocks(n_mlp / 4)), dim3(256), 0, st, mlp_grad, n_mlp, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(float* a, long long n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3(stream_blocks(n)), dim3(256), 0, st, a, n);
+  return hipGetLastError();
+}
+
 }  // namespace gs

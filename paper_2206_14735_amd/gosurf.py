@@ -25,7 +25,8 @@ MAX_SAMPLES_PER_RAY = 256
 FP32, BF16 = 0, 1
 SPAN_FIXED, SPAN_BOX = 0, 1
 STATUS = {0: "OK", 1: "ERR_NULL", 2: "ERR_SHAPE", 3: "ERR_ALIGN", 4: "ERR_VALUE",
-          5: "ERR_WORKSPACE", 6: "ERR_HIP"}
+          5: "ERR_WORKSPACE", 6: "ERR_HIP", 7: "ERR_NONFINITE"}
+ERR_NONFINITE = 7
 LOSS_NAMES = ("rgb", "depth", "sdf", "fs", "eik", "smooth", "total", "n_depth_rays")
 
 
@@ -93,7 +94,7 @@ class AdamState(C.Structure):
 
 
 EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "gosurf_workspace_bytes",
-           "gosurf_forward", "gosurf_backward", "gosurf_adam_step", "gosurf_refresh_bf16",
+           "gosurf_forward", "gosurf_backward", "gosurf_adam_step", "gosurf_adam_step_checked", "gosurf_refresh_bf16",
            "gosurf_proposal_forward", "gosurf_proposal_targets", "gosurf_proposal_workspace_bytes",
            "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_workspace_bytes",
            "gosurf_importance_step", "gosurf_importance_sample", "gosurf_lattice_workspace_bytes",
@@ -122,6 +123,7 @@ def lib():
                                       C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_float, C.POINTER(GradsC),
                                       C.c_void_p, C.c_size_t, C.c_void_p]
         L.gosurf_adam_step.argtypes = [C.POINTER(AdamCfg), C.POINTER(AdamState), C.c_void_p]
+        L.gosurf_adam_step_checked.argtypes = [C.POINTER(AdamCfg), C.POINTER(AdamState), C.c_void_p, C.c_void_p]
         L.gosurf_refresh_bf16.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
         L.gosurf_proposal_forward.argtypes = [C.POINTER(Model), C.c_void_p, C.c_void_p, C.POINTER(RayBatchC),
                                               C.POINTER(SampleCfg), C.c_void_p, C.c_void_p]
@@ -148,6 +150,7 @@ def lib():
         L.gosurf_marching_tetrahedra.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_float, C.c_int32, C.c_int32,
                                                  C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         for f in ("gosurf_sample_rays", "gosurf_forward", "gosurf_backward", "gosurf_adam_step",
+                  "gosurf_adam_step_checked",
                   "gosurf_refresh_bf16", "gosurf_proposal_forward", "gosurf_proposal_targets",
                   "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_step",
                   "gosurf_importance_sample", "gosurf_sdf_lattice", "gosurf_marching_tetrahedra"):
@@ -359,6 +362,22 @@ def gosurf_adam_step(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_grad, mlp_m
     s = AdamState(_ptr(grid, F32), _ptr(grid_grad, F32), _ptr(grid_m, F32), _ptr(grid_v, F32), _ptr(grid_bf16),
                   ng, _ptr(mlp, F32), _ptr(mlp_grad, F32), _ptr(mlp_m, F32), _ptr(mlp_v, F32), mlp.numel())
     _check("gosurf_adam_step", lib().gosurf_adam_step(C.byref(c), C.byref(s), _stream(stream)))
+
+
+def gosurf_adam_step_checked(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_grad, mlp_m, mlp_v, flag, lr_grid=1e-2,
+                             lr_mlp=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, inv_loss_scale=1.0, grid_bf16=None,
+                             stream=None):
+    """gosurf_adam_step guarded against inf / NaN gradients; waits for the stream.  Returns True if the update
+    was applied, False if it was skipped (the gradients are then zeroed).  flag: device int32 [1]."""
+    c = AdamCfg(lr_grid, lr_mlp, beta1, beta2, eps, int(step), inv_loss_scale)
+    ng = 0 if grid is None else grid.numel()
+    s = AdamState(_ptr(grid, F32), _ptr(grid_grad, F32), _ptr(grid_m, F32), _ptr(grid_v, F32), _ptr(grid_bf16),
+                  ng, _ptr(mlp, F32), _ptr(mlp_grad, F32), _ptr(mlp_m, F32), _ptr(mlp_v, F32), mlp.numel())
+    st = lib().gosurf_adam_step_checked(C.byref(c), C.byref(s), _ptr(flag, torch.int32), _stream(stream))
+    if st == ERR_NONFINITE:
+        return False
+    _check("gosurf_adam_step_checked", st)
+    return True
 
 
 def set_proposal(cfg, proposal, grid, n_proposal=24, conf_threshold=0.5, n_free=0, depth_check=False,

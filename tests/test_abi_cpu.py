@@ -262,3 +262,13 @@ def test_lattice_and_marching_reject_bad_arguments(lib):
 def test_time_kernel_rejects_unknown_kernel(lib):
     assert lib.gosurf_time_kernel(7, None, None) == 4
     assert lib.gosurf_time_kernel(0, None, None) == 0
+
+
+def test_checked_adam_rejects_missing_or_misaligned_flag(lib):
+    c = G.AdamCfg(1e-2, 1e-3, 0.9, 0.999, 1e-8, 1, 1.0)
+    s = G.AdamState(16, 16, 16, 16, None, 8, 16, 16, 16, 16, 4)
+    assert lib.gosurf_adam_step_checked(C.byref(c), C.byref(s), None, None) == 1
+    assert b"flag" in lib.gosurf_last_error()
+    assert lib.gosurf_adam_step_checked(C.byref(c), C.byref(s), 18, None) == 3
+    c.step = 0                                          # the Adam checks come first
+    assert lib.gosurf_adam_step_checked(C.byref(c), C.byref(s), 16, None) == 4
