@@ -5,7 +5,6 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <string>
 
 #include "device.h"
 
@@ -49,7 +48,9 @@ hipError_t launch_marching_tets(const MtArgs& a, hipStream_t st);
 
 namespace {
 
-thread_local std::string g_err;
+// last error text of this thread: a fixed buffer, so that recording an error
+// never allocates and nothing can throw across the C interface
+thread_local char g_err[512];
 
 // optional event pair recorded around one kernel (measurement hook)
 thread_local int g_timed_kernel = GOSURF_KERNEL_NONE;
@@ -62,17 +63,15 @@ void mark(int kernel, bool start, hipStream_t s) {
 
 gosurf_status fail(gosurf_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 gosurf_status fail(gosurf_status s, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return s;
 }
 
 gosurf_status ok() {
-  g_err.clear();
+  g_err[0] = '\0';
   return GOSURF_OK;
 }
 
@@ -192,7 +191,7 @@ gosurf_status check_params(const gosurf_model* m, const gosurf_params* p) {
 
 extern "C" {
 
-const char* gosurf_last_error(void) { return g_err.c_str(); }
+const char* gosurf_last_error(void) { return g_err; }
 
 gosurf_status gosurf_time_kernel(int32_t kernel, void* start_event, void* stop_event) {
   if (kernel != GOSURF_KERNEL_NONE && kernel != GOSURF_KERNEL_FIELD_FWD && kernel != GOSURF_KERNEL_FIELD_BWD &&
