@@ -438,3 +438,90 @@ def test_adam_loss_scale_invariance():
     a = S.adam(np.ones(3), g, np.zeros(3), np.zeros(3), 1, 0.01)[0]
     b = S.adam(np.ones(3), g * 1024, np.zeros(3), np.zeros(3), 1, 0.01, inv_scale=1 / 1024)[0]
     assert torch.allclose(a, b, atol=0)
+
+
+# ---------------------------------------------------------------- loss terms by hand
+def test_rgb_term_is_channel_mean_of_absolute_differences():
+    # Sec. 3.2 colour term, reading: mean over the 3 channels of |I - c_hat|,
+    # then the mean over rays.  Hand values: ray 0 -> (0.1 + 0 + 0.3) / 3,
+    # ray 1 -> (0.5 + 0.5 + 0) / 3; their mean is 7/30.  A channel sum would
+    # give 0.7, a Euclidean norm (sqrt(0.1) + sqrt(0.5)) / 2.
+    gt = torch.tensor([[0.1, 0.2, 0.3], [1.0, 0.0, 0.5]])
+    ch = torch.tensor([[0.2, 0.2, 0.0], [0.5, 0.5, 0.5]])
+    assert abs(float(O.rgb_term(gt, ch)) - 7.0 / 30.0) < 1e-15
+
+
+def test_depth_term_divides_by_rays_with_depth():
+    # Sec. 3.5: the depth term averages |D - d_hat| over R_d, the rays with an
+    # observed depth; rays with D <= 0 contribute nothing and do not count.
+    # Rays 0 and 2 have depth: (0.1 + 0.5) / 2 = 0.3 (dividing by M = 4 would
+    # give 0.15; including the missing rays would add 5 and 8).
+    D = torch.tensor([2.0, 0.0, 1.5, -1.0])
+    dh = torch.tensor([1.9, 5.0, 1.0, 7.0])
+    assert abs(float(O.depth_term(D, dh)) - 0.3) < 1e-15
+    # no ray with depth: the term is 0 (and still differentiable)
+    z = O.depth_term(torch.zeros(3), torch.tensor([1.0, 2.0, 3.0], requires_grad=True))
+    assert float(z.detach()) == 0.0
+
+
+def test_total_applies_the_implementation_lambdas_to_the_named_terms():
+    # Implementation details: lambda_rgb = 10, lambda_depth = 1, lambda_sdf = 10,
+    # lambda_fs = 1, lambda_eik = 1, lambda_smooth = 1 (Sec. 3.5 objective).
+    # Terms set to distinct powers of two make every term's weight readable.
+    assert S.LossCfg().lambdas == (10.0, 1.0, 10.0, 1.0, 1.0, 1.0)
+    terms = {"rgb": 1.0, "depth": 2.0, "sdf": 4.0, "fs": 8.0, "eik": 16.0, "smooth": 32.0}
+    assert O.total(terms, S.LossCfg().lambdas) == 10 * 1 + 2 + 10 * 4 + 8 + 16 + 32
+    for k, name in enumerate(O.TERMS):
+        one_hot = tuple(1.0 if j == k else 0.0 for j in range(6))
+        assert O.total(terms, one_hot) == terms[name]
+
+
+def test_evaluate_routes_each_term_by_its_lambda():
+    # One-hot weights through the whole oracle step: the total equals the one
+    # term named at that position, and the colour and depth terms equal the
+    # hand sums over the rendered values (channel mean; depth over R_d only).
+    L, batch, grid, mlp = _tiny_problem(0)
+    base = S.evaluate(grid, mlp, L, batch, want_grads=False)
+    M = batch.o.shape[0]
+    rgb_hand = sum(sum(abs(float(batch.rgb[m, c]) - float(base["c_hat"][m, c])) for c in range(3)) / 3.0
+                   for m in range(M)) / M
+    with_d = [m for m in range(M) if batch.depth[m] > 0]
+    assert 0 < len(with_d) < M          # the sphere batch has misses
+    dep_hand = sum(abs(float(batch.depth[m]) - float(base["d_hat"][m])) for m in with_d) / len(with_d)
+    assert abs(base["losses"]["rgb"] - rgb_hand) < 1e-12
+    assert abs(base["losses"]["depth"] - dep_hand) < 1e-12
+    for k, name in enumerate(O.TERMS):
+        cfg = S.LossCfg(lambdas=tuple(1.0 if j == k else 0.0 for j in range(6)))
+        res = S.evaluate(grid, mlp, L, batch, cfg, want_grads=False)
+        assert abs(res["total"] - base["losses"][name]) <= 1e-12 * max(1.0, abs(base["losses"][name]))
+
+
+# ---------------------------------------------------------------- Adam beyond the first step
+@pytest.mark.parametrize("k", [2, 3, 10, 1000])
+def test_adam_constant_gradient_moves_lr_every_step(k):
+    # Bias correction makes m_hat = g and v_hat = g^2 exactly for a constant
+    # gradient from zero moments, so every step moves by -lr g / (|g| + eps).
+    # A slip such as (1 - beta1)^k for 1 - beta1^k agrees at k = 1 only.
+    g = np.array([0.3, -2.0, 1e-3])
+    p, m, v = np.ones(3), np.zeros(3), np.zeros(3)
+    for step in range(1, k + 1):
+        p_prev = np.asarray(p, dtype=np.float64).copy()
+        p, m, v = S.adam(p, g, m, v, step=step, lr=0.01)
+        d = p.numpy() - p_prev
+        assert np.allclose(d, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0)
+    b1, b2 = 0.9, 0.999
+    assert np.allclose(m.numpy(), (1 - b1 ** k) * g, rtol=1e-12)
+    assert np.allclose(v.numpy(), (1 - b2 ** k) * g * g, rtol=1e-12)
+
+
+def test_adam_second_step_after_a_zero_gradient():
+    # g then 0: m_2 = b1 (1 - b1) g, v_2 = b2 (1 - b2) g^2, so the second move is
+    # -lr (b1 / (1 + b1)) g / (sqrt(b2 / (1 + b2)) |g| + eps): it pins which
+    # beta goes with which moment and the square root on v.
+    b1, b2, lr, eps = 0.9, 0.999, 0.01, 1e-8
+    g = np.array([0.5, -3.0])
+    p1, m1, v1 = S.adam(np.zeros(2), g, np.zeros(2), np.zeros(2), 1, lr)
+    p2, _, _ = S.adam(p1, np.zeros(2), m1, v1, 2, lr)
+    d = (p2 - p1).numpy()
+    ref = -lr * (b1 / (1 + b1)) * g / (np.sqrt(b2 / (1 + b2)) * np.abs(g) + eps)
+    assert np.allclose(d, ref, rtol=1e-12, atol=0)
