@@ -71,12 +71,26 @@ def coefficient_hessian(f, theta):
                         torch.stack([h13, h23, zero], -1)], -2)
 
 
-def cell_and_local(x, p0, voxel, dims):
-    """Cell origin (long [..., 3], no gradient) and local coordinates f [..., 3]."""
-    p0 = torch.as_tensor(p0, dtype=x.dtype)
-    u = (x - p0) / voxel
+def cell_and_local(x, p0, voxel, dims, x32=None):
+    """Cell origin (long [..., 3], no gradient) and local coordinates f [..., 3].
+
+    The cell is an integer decision: at a face between two cells the
+    interpolated value is continuous but its derivative in x jumps, so both
+    implementations must pick the same cell.  With x32 (the float32 positions
+    the device works on) the decision is taken as float32 arithmetic takes it,
+    u = (x32 - p0) / voxel rounded to float32; the local coordinates are then
+    u - i0 in the arithmetic of x."""
+    p0t = torch.as_tensor(p0, dtype=x.dtype)
+    u = (x - p0t) / voxel
     n = torch.as_tensor(dims, dtype=torch.long)
-    i0 = torch.minimum(torch.floor(u.detach()).long().clamp(min=0), n - 2)
+    if x32 is None:
+        fl = torch.floor(u.detach()).long()
+    else:
+        import numpy as np
+        u32 = (np.asarray(x32, dtype=np.float32).reshape(tuple(u.shape)) - np.asarray(p0, dtype=np.float32)) \
+            / np.float32(voxel)
+        fl = torch.from_numpy(np.floor(u32.astype(np.float32)).astype(np.int64))
+    i0 = torch.minimum(fl.clamp(min=0), n - 2)
     f = u - i0.to(x.dtype)
     return i0, f
 
@@ -90,22 +104,23 @@ def corner_rows(i0, dims):
     return torch.stack(rows, -1)
 
 
-def interp_level(table, x, p0, voxel, dims):
-    """Trilinear interpolation of one level: table [V, F], x [P, 3] -> [P, F]."""
-    i0, f = cell_and_local(x, p0, voxel, dims)
+def interp_level(table, x, p0, voxel, dims, x32=None):
+    """Trilinear interpolation of one level: table [V, F], x [P, 3] -> [P, F]
+    (x32: float32 positions that decide the cell, see cell_and_local)."""
+    i0, f = cell_and_local(x, p0, voxel, dims, x32)
     w = coefficient_vector(f)                       # [P, 8]
     rows = corner_rows(i0, dims)                    # [P, 8]
     theta = table[rows]                             # [P, 8, F]
     return (w[..., None] * theta).sum(-2)
 
 
-def interp_all(grid, layout, x):
+def interp_all(grid, layout, x, x32=None):
     """Concatenated features z = [V^0(x), ..., V^{L-1}(x)], coarsest level first."""
     out = []
     for l in range(layout.n_levels):
         nx, ny, nz = layout.dims[l]
         tab = grid[layout.offsets[l]:layout.offsets[l] + nx * ny * nz]
-        out.append(interp_level(tab, x, layout.p0, layout.voxels[l], layout.dims[l]))
+        out.append(interp_level(tab, x, layout.p0, layout.voxels[l], layout.dims[l], x32))
     return torch.cat(out, -1)
 
 
@@ -120,6 +135,16 @@ def interp_level_bruteforce(table, x, p0, voxel, dims):
     hz = (1 - (u[:, 2, None] - torch.arange(nz, dtype=x.dtype)).abs()).clamp(min=0)
     w = hz[:, :, None, None] * hy[:, None, :, None] * hx[:, None, None, :]   # [P, nz, ny, nx]
     return w.reshape(x.shape[0], -1) @ table
+
+
+def position_fp32(o32, t32, r32):
+    """The point o + t r as the device forms it in float32 (product rounded,
+    then sum rounded)."""
+    import numpy as np
+    o32 = np.asarray(o32, dtype=np.float32)
+    r32 = np.asarray(r32, dtype=np.float32)
+    t32 = np.asarray(t32, dtype=np.float32)
+    return (o32 + (t32[..., None] * r32).astype(np.float32)).astype(np.float32)
 
 
 def inside_box_fp32(o32, t32, r32, p0, p1):

@@ -55,32 +55,43 @@ def _pad(batch):
     return ray_of, slot, M, max(N, 1)
 
 
-def _gradient_at(gridv, mlpP, layout, x):
-    """phi(x), decoder output and d phi/d x with a differentiable graph."""
+def _gradient_at(gridv, mlpP, layout, x, x32=None):
+    """phi(x), decoder output and d phi/d x with a differentiable graph (x32:
+    the float32 positions that decide each point's cell)."""
     x = x.detach().requires_grad_(True)
-    z = G.interp_all(gridv, layout, x)
+    z = G.interp_all(gridv, layout, x, x32)
     out = decoder.geometry(z, mlpP)
     gphi, = torch.autograd.grad(out[:, 0].sum(), x, create_graph=True)
     return out, gphi
 
 
-def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True):
-    """grid [V, 4], mlp [P] (any float array) -> dict of float64 results."""
-    gridv = torch.as_tensor(np.asarray(grid), dtype=torch.float64).clone().requires_grad_(want_grads)
-    mlpv = torch.as_tensor(np.asarray(mlp), dtype=torch.float64).clone().requires_grad_(want_grads)
+def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=torch.float64):
+    """grid [V, 4], mlp [P] (any float array) -> dict of results (float64).
+
+    dtype selects the arithmetic: float64 is the reference; float32 runs the
+    same definition in single precision, which measures how much float32
+    rounding alone moves each result (the conditioning of the problem)."""
+    gridv = torch.as_tensor(np.asarray(grid), dtype=dtype).clone().requires_grad_(want_grads)
+    mlpv = torch.as_tensor(np.asarray(mlp), dtype=dtype).clone().requires_grad_(want_grads)
     P = decoder.unpack(mlpv)
     s = decoder.sharpness(P)
     ray_of, slot, M, N = _pad(batch)
-    o = torch.as_tensor(batch.o, dtype=torch.float64)
-    r = torch.as_tensor(batch.r, dtype=torch.float64)
-    t = torch.as_tensor(batch.t, dtype=torch.float64)
-    depth = torch.as_tensor(batch.depth, dtype=torch.float64)
-    rgb = torch.as_tensor(batch.rgb, dtype=torch.float64)
+    o = torch.as_tensor(batch.o, dtype=dtype)
+    r = torch.as_tensor(batch.r, dtype=dtype)
+    t = torch.as_tensor(batch.t, dtype=dtype)
+    depth = torch.as_tensor(batch.depth, dtype=dtype)
+    rgb = torch.as_tensor(batch.rgb, dtype=dtype)
 
     valid_s = G.inside_box_fp32(batch.o[ray_of], batch.t, batch.r[ray_of], layout.p0, layout.p1)
-    x = o[ray_of] + t[:, None] * r[ray_of]
+    # The sample point x_i = o + d_i r (Sec. 3.2) is the float32 point the
+    # device forms (product rounded, then sum rounded).  The field is evaluated
+    # exactly there: between that point and the exact one may lie a kink of
+    # the method (|phi - b|, a ReLU unit, the opacity clamp), and the two
+    # sides must differentiate on the same side of it.
+    x32 = G.position_fp32(batch.o[ray_of], batch.t, batch.r[ray_of])
+    x = torch.as_tensor(x32, dtype=dtype)
     with torch.enable_grad():
-        out, gphi = _gradient_at(gridv, P, layout, x)
+        out, gphi = _gradient_at(gridv, P, layout, x, x32)
         phi = out[:, 0]
         col = decoder.colour(out[:, 1:], P)
 
@@ -107,11 +118,13 @@ def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True):
         hi = np.asarray(layout.p1, dtype=np.float32)
         pair_ok = torch.from_numpy(np.all((xs32 >= lo) & (xs32 <= hi) & (x2_32 >= lo) & (x2_32 <= hi), -1))
         if xs32.shape[0]:
-            _, g1 = _gradient_at(gridv, P, layout, torch.as_tensor(xs32, dtype=torch.float64))
-            _, g2 = _gradient_at(gridv, P, layout, torch.as_tensor(x2_32, dtype=torch.float64))
+            _, g1 = _gradient_at(gridv, P, layout, torch.as_tensor(xs32, dtype=dtype), xs32)
+            _, g2 = _gradient_at(gridv, P, layout, torch.as_tensor(x2_32, dtype=dtype), x2_32)
             smooth = O.smoothness_term(g1, g2, pair_ok)
+            pair_grads = torch.stack([g1, g2], 1).detach()
         else:
             smooth = phi.sum() * 0
+            pair_grads = torch.zeros((0, 2, 3), dtype=dtype)
 
         terms = {
             "rgb": O.rgb_term(rgb, c_hat),
@@ -124,6 +137,7 @@ def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True):
         loss = O.total(terms, cfg.lambdas)
         res = {
             "phi": phi.detach(), "col": col.detach(), "grad_phi": gphi.detach(),
+            "grad_phi_pairs": pair_grads, "pair_ok": pair_ok,
             "valid": torch.from_numpy(valid_s),
             "w": w.detach()[torch.as_tensor(ray_of), torch.as_tensor(slot)],
             "c_hat": c_hat.detach(), "d_hat": d_hat.detach(), "wsum": wsum.detach(),

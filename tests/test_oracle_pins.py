@@ -525,3 +525,32 @@ def test_adam_second_step_after_a_zero_gradient():
     d = (p2 - p1).numpy()
     ref = -lr * (b1 / (1 + b1)) * g / (np.sqrt(b2 / (1 + b2)) * np.abs(g) + eps)
     assert np.allclose(d, ref, rtol=1e-12, atol=0)
+
+
+def test_cell_decision_in_float32_at_a_face():
+    """A point within one float32 rounding of a cell face: the cell is decided
+    from the float32 position as the device decides it, the value is the same
+    from either side (interpolation is continuous across the face) while the
+    derivative along the face normal jumps (so the decision matters)."""
+    import numpy as np
+    from oracle import grid as G
+    p0, v, dims = (0.0, 0.0, 0.0), 0.02, (40, 40, 40)
+    g = torch.Generator().manual_seed(3)
+    tab = torch.randn(40 * 40 * 40, 4, generator=g, dtype=torch.float64)
+    # the float32 number just below the face x = 17 v: float32 puts it in cell 16
+    x32 = np.array([[np.nextafter(np.float32(17 * v), np.float32(0)), 0.31, 0.27]], dtype=np.float32)
+    u32 = (x32[0, 0] - np.float32(0)) / np.float32(v)
+    x = torch.tensor(x32, dtype=torch.float64, requires_grad=True)
+    i_f32, _ = G.cell_and_local(x, p0, v, dims, x32)
+    assert int(i_f32[0, 0]) == int(np.floor(u32))
+    # both cells around the face give the same value, different x-derivatives
+    xa = torch.tensor([[17 * v, 0.31, 0.27]], dtype=torch.float64, requires_grad=True)
+    below = np.array([[np.float32(17 * v) - np.float32(1e-4), 0.31, 0.27]], dtype=np.float32)
+    above = np.array([[np.float32(17 * v) + np.float32(1e-4), 0.31, 0.27]], dtype=np.float32)
+    za = G.interp_level(tab, xa, p0, v, dims, below)     # cell 16, f = 1
+    zb = G.interp_level(tab, xa, p0, v, dims, above)     # cell 17, f = 0
+    assert torch.allclose(za, zb, rtol=0, atol=1e-12)
+    ga, = torch.autograd.grad(za[0, 0], xa)
+    gb, = torch.autograd.grad(zb[0, 0], xa)
+    assert abs(float(ga[0, 0] - gb[0, 0])) > 1e-3
+    assert torch.allclose(ga[0, 1:], gb[0, 1:], atol=1e-12)
