@@ -33,11 +33,9 @@
  *   gosurf_workspace_bytes().
  * - Every call only validates its arguments on the host and enqueues kernels
  *   on `stream` (a hipStream_t; NULL = the default stream).  It returns
- *   GOSURF_OK or an error status and never blocks (gosurf_adam_step_checked
- *   alone waits for its stream).  Device faults surface at
+ *   GOSURF_OK or an error status and never blocks.  Device faults surface at
  *   the caller's next synchronisation.  On error nothing has been enqueued
- *   (GOSURF_ERR_NONFINITE aside) and gosurf_last_error() (thread-local)
- *   describes the problem.
+ *   and gosurf_last_error() (thread-local) describes the problem.
  * - No C++ exception crosses this interface.  Calls are re-entrant; calls that
  *   share output or workspace buffers must be ordered by the caller.
  *
@@ -87,7 +85,7 @@ typedef enum {
   GOSURF_ERR_VALUE = 4,      /* a scalar argument is invalid (NaN, <= 0, ...) */
   GOSURF_ERR_WORKSPACE = 5,  /* workspace missing or smaller than required */
   GOSURF_ERR_HIP = 6,        /* a kernel launch failed */
-  GOSURF_ERR_NONFINITE = 7   /* gosurf_adam_step_checked: a gradient was inf or NaN, the update skipped */
+  GOSURF_ERR_NONFINITE = 7   /* reserved (no call returns it: gosurf_adam_step_checked reports through its flag) */
 } gosurf_status;
 
 typedef enum { GOSURF_FP32 = 0, GOSURF_BF16 = 1 } gosurf_precision;
@@ -159,7 +157,8 @@ typedef struct {
 /* A ray batch.  Written by gosurf_sample_rays, read by forward/backward.
    Samples are stored ray-major: the samples of ray m are
    t[seg[m] .. seg[m+1]-1], sorted ascending, at most
-   GOSURF_MAX_SAMPLES_PER_RAY per ray; ray_of[s] is the ray of sample s. */
+   GOSURF_MAX_SAMPLES_PER_RAY per ray (a longer ray is cut to that many by
+   forward and backward); ray_of[s] is the ray of sample s. */
 typedef struct {
   int32_t M;            /* rays, >= 1 (an empty batch is rejected with GOSURF_ERR_SHAPE) */
   int32_t total;        /* samples, = seg[M], M <= total < 2^29 (else GOSURF_ERR_SHAPE); with
@@ -197,6 +196,17 @@ typedef struct {
   float* losses;        /* [GOSURF_N_LOSSES] */
   float* saved;         /* [total][4]: phi, colour per sample; then [total] eik residual */
   float* weights;       /* [total] per-sample weights w_i, or NULL */
+  float* grad_phi;      /* [total + 2 S][3] d(phi)/dx, or NULL (inspection output): row s < total
+                           for sample s (written when the Eikonal weight is nonzero), rows
+                           total + 2p and total + 2p + 1 for the points x and x + eps of
+                           smoothness pair p (written when the smoothness weight is nonzero) */
+  float* ray_terms;     /* [M][8] per-ray terms, or NULL (inspection output): the channel-mean
+                           |I - c_hat|, |D - d_hat| (0 without depth), the means of |phi - b| over
+                           S_tr, of the free-space term and of the Eikonal residual over S_fs,
+                           1 if the ray has depth, then two zeros */
+  float* pair_terms;    /* [S] |grad phi(x) - grad phi(x + eps)|^2 per smoothness pair (0 for a
+                           pair leaving the box), or NULL; written when the smoothness weight
+                           is nonzero */
 } gosurf_fwd_out;
 
 /* Gradient accumulators (caller zeroes them once; Adam re-zeroes them). */
@@ -329,11 +339,16 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
                              gosurf_fwd_out* out, void* workspace, size_t workspace_bytes,
                              void* stream);
 
-/* Backward pass: ADDS loss_scale * d(total)/d(params) into grads.  Must follow
-   the gosurf_forward call that produced `fwd` with the same params, batch,
-   loss config and workspace.  Grid gradients are accumulated with float32
-   atomics (summation order varies between runs); decoder gradients are
-   reduced in a fixed order.  Errors: NULL, SHAPE, VALUE, WORKSPACE, HIP. */
+/* Backward pass: ADDS loss_scale * d(total)/d(params) into grads (loss_scale
+   any finite value: a negative one gives the gradient of -scale * total, 0
+   adds zeros).  Must follow the gosurf_forward call that produced `fwd` with
+   the same params, batch, loss config and workspace.  Grid gradients are
+   accumulated with float32 atomics (summation order varies between runs);
+   decoder gradients are reduced in a fixed order.  A ray holding more than
+   GOSURF_MAX_SAMPLES_PER_RAY samples ends at that many: forward and backward
+   treat it as the ray of its first GOSURF_MAX_SAMPLES_PER_RAY samples (the
+   rest get weight 0, no loss and no gradient).  Device offsets seg[] beyond
+   `total` are clamped to it.  Errors: NULL, SHAPE, VALUE, WORKSPACE, HIP. */
 gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* params,
                               const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
                               const gosurf_fwd_out* fwd, float loss_scale, gosurf_grads* grads,
@@ -427,15 +442,15 @@ gosurf_status gosurf_adam_step(const gosurf_adam_cfg* cfg, gosurf_adam_state* st
 /* gosurf_adam_step behind a guard against non-finite gradients, for callers
    that scale the loss (the BF16 precision variant) or otherwise want a step
    with an inf or NaN gradient discarded rather than written into the
-   parameters and moments.  Clears *flag (a caller-owned device int32), sets
-   it to 1 if any entry of grid_grad or mlp_grad is inf or NaN, and then
-   WAITS for the stream (the one call here that blocks) to read it.  Finite:
-   runs gosurf_adam_step and returns its status.  Non-finite: leaves the
-   parameters, moments and bfloat16 mirror unchanged, zeroes both gradient
-   arrays on the stream and returns GOSURF_ERR_NONFINITE (the check and the
-   zeroing have then been enqueued).  Extra traffic: one read of the
-   gradients (4 B per parameter).  Errors: NULL, SHAPE, ALIGN, VALUE, HIP,
-   NONFINITE. */
+   parameters and moments.  Enqueues, on the stream: clearing *flag (a
+   caller-owned device int32), setting it to 1 if any entry of grid_grad or
+   mlp_grad is inf or NaN, and the update, which reads the flag on the device:
+   flag 0 gives exactly gosurf_adam_step; flag 1 leaves the parameters,
+   moments and bfloat16 mirror unchanged and only zeroes both gradient arrays.
+   Nothing waits on the host: the caller reads *flag after the stream has
+   reached it to learn whether the step was taken (the step number passed in
+   `cfg` is the caller's to keep or repeat).  Extra traffic: one read of the
+   gradients (4 B per parameter).  Errors: NULL, SHAPE, ALIGN, VALUE, HIP. */
 gosurf_status gosurf_adam_step_checked(const gosurf_adam_cfg* cfg, gosurf_adam_state* state, int32_t* flag,
                                        void* stream);
 

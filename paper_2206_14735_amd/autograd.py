@@ -6,7 +6,7 @@ Calling ``backward()`` on it (or on anything computed from it) makes
 gosurf_backward write the exact gradients of that total into ``grid.grad``
 and ``mlp.grad``: the grid scatter, the decoder weight gradients and the
 double backward of the Eikonal and smoothness terms, all in the library's
-kernels.  The incoming gradient is passed to the library as its loss scale.
+kernels.  The incoming gradient (any sign) is passed to the library as its loss scale.
 The per-ray and per-sample forward results stay available in
 ``last_forward`` of the returned tensor's grad_fn context.
 

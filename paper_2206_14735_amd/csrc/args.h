@@ -25,6 +25,8 @@ struct FieldArgs {
   float* out4;            // [total][4] phi, c
   float* eik;             // [total] (1 - |grad phi|)^2
   float* smooth_partial;  // [gridDim.x]
+  float* grad_phi;        // [total + 2 S][3] d(phi)/dx (forward, optional; total = the capacity)
+  float* pair_terms;      // [S] per-pair smoothness value (forward, optional)
   // backward
   const float* seed4;     // [total][4] dL/dphi, dL/dc (scaled)
   const float* posw;      // [total][4]: sample position (as the forward computed it), Eikonal
@@ -51,6 +53,7 @@ struct RenderArgs {
   const float* t;
   const int* seg;
   int M;
+  int total;            // sample capacity of the batch
   const float* mlp;
   const float* out4;    // [total][4]
   const float* eik;     // [total] or null

@@ -22,7 +22,7 @@ hipError_t launch_loss_reduce(const float* ray_partial, int M, const float* smoo
                               const float lam[6], float* losses, float* ray_part, hipStream_t st);
 hipError_t launch_grad_reduce(const float* partial, int n_part, const float* ray_dv, int M, float* grad_mlp,
                               float* tmp, float* ray_part, hipStream_t st);
-hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st);
+hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, const int* skip, hipStream_t st);
 hipError_t launch_nonfinite_check(const float* grid_grad, long long n_grid, const float* mlp_grad, long long n_mlp,
                                   int* flag, hipStream_t st);
 hipError_t launch_zero(float* a, long long n, hipStream_t st);
@@ -315,6 +315,7 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
+  fa.grad_phi = out->grad_phi; fa.pair_terms = out->pair_terms;
   if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped
   const int nb = gs::field_grid(fa, false);
   if (nb <= 0) return fail(GOSURF_ERR_HIP, "field grid: the occupancy query failed");
@@ -324,13 +325,13 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   const int n_sp = fa.S > 0 ? nb : 0;
   gs::RenderArgs ra{};
   ra.g = g; ra.o = b->o; ra.r = b->r; ra.rgb = b->rgb; ra.depth = b->depth; ra.t = b->t; ra.seg = b->seg;
-  ra.M = b->M; ra.mlp = params->mlp; ra.out4 = out->saved; ra.eik = need_gx ? eik : nullptr;
+  ra.M = b->M; ra.total = b->total; ra.mlp = params->mlp; ra.out4 = out->saved; ra.eik = need_gx ? eik : nullptr;
   ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs;
   for (int k = 0; k < 6; ++k) ra.lam[k] = loss->lambda[k];
   ra.rgb_hat = out->rgb_hat; ra.depth_hat = out->depth_hat; ra.wsum = out->wsum; ra.weights = out->weights;
-  ra.ray_partial = w.ray_partial;
+  ra.ray_partial = out->ray_terms ? out->ray_terms : w.ray_partial;
   if ((st = hip_check(gs::launch_render(ra, false, s), "render fwd")) != GOSURF_OK) return st;
-  if ((st = hip_check(gs::launch_loss_reduce(w.ray_partial, b->M, w.smooth_partial, n_sp, b->S, loss->lambda,
+  if ((st = hip_check(gs::launch_loss_reduce(ra.ray_partial, b->M, w.smooth_partial, n_sp, b->S, loss->lambda,
                                              out->losses, w.ray_part, s),
                       "loss reduce")) != GOSURF_OK)
     return st;
@@ -348,7 +349,7 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   if (!fwd || !fwd->saved || !fwd->losses) return fail(GOSURF_ERR_NULL, "forward outputs are NULL");
   if (!grads || !grads->grid || !grads->mlp) return fail(GOSURF_ERR_NULL, "gradient buffers are NULL");
   if (!aligned(grads->grid, 16)) return fail(GOSURF_ERR_ALIGN, "grads.grid must be 16-byte aligned");
-  if (!(loss_scale > 0.f) || !std::isfinite(loss_scale)) return fail(GOSURF_ERR_VALUE, "loss_scale must be > 0");
+  if (!std::isfinite(loss_scale)) return fail(GOSURF_ERR_VALUE, "loss_scale must be finite");
   const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
   if (!ws || ws_bytes < w.bytes)
     return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
@@ -359,7 +360,7 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
 
   gs::RenderArgs ra{};
   ra.g = g; ra.o = b->o; ra.r = b->r; ra.rgb = b->rgb; ra.depth = b->depth; ra.t = b->t; ra.seg = b->seg;
-  ra.M = b->M; ra.mlp = params->mlp; ra.out4 = fwd->saved; ra.eik = nullptr;
+  ra.M = b->M; ra.total = b->total; ra.mlp = params->mlp; ra.out4 = fwd->saved; ra.eik = nullptr;
   ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs;
   for (int k = 0; k < 6; ++k) ra.lam[k] = loss->lambda[k];
   ra.n_depth_rays = fwd->losses + 7;
@@ -519,7 +520,7 @@ gosurf_status gosurf_adam_step(const gosurf_adam_cfg* c, gosurf_adam_state* s, v
   if ((st = check_adam(c, s)) != GOSURF_OK) return st;
   gosurf_adam_state copy = *s;
   mark(GOSURF_KERNEL_ADAM, true, (hipStream_t)stream);
-  if ((st = hip_check(gs::launch_adam(*c, copy, (hipStream_t)stream), "adam")) != GOSURF_OK) return st;
+  if ((st = hip_check(gs::launch_adam(*c, copy, nullptr, (hipStream_t)stream), "adam")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_ADAM, false, (hipStream_t)stream);
   return ok();
 }
@@ -531,19 +532,16 @@ gosurf_status gosurf_adam_step_checked(const gosurf_adam_cfg* c, gosurf_adam_sta
   if (!flag) return fail(GOSURF_ERR_NULL, "flag is NULL");
   if (!aligned(flag, 4)) return fail(GOSURF_ERR_ALIGN, "flag must be 4-byte aligned");
   hipStream_t h = (hipStream_t)stream;
+  // the check writes the flag on the stream; the update kernels read it there
+  // and skip the step on the device, so nothing waits on the host
   if ((st = hip_check(gs::launch_nonfinite_check(s->grid_grad, s->grid_numel, s->mlp_grad, s->mlp_numel, flag, h),
                       "non-finite check")) != GOSURF_OK)
     return st;
-  int32_t bad = 0;
-  if ((st = hip_check(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, h), "flag copy")) != GOSURF_OK)
-    return st;
-  if ((st = hip_check(hipStreamSynchronize(h), "flag wait")) != GOSURF_OK) return st;
-  if (bad) {
-    if ((st = hip_check(gs::launch_zero(s->grid_grad, s->grid_numel, h), "gradient reset")) != GOSURF_OK) return st;
-    if ((st = hip_check(gs::launch_zero(s->mlp_grad, s->mlp_numel, h), "gradient reset")) != GOSURF_OK) return st;
-    return fail(GOSURF_ERR_NONFINITE, "a gradient is inf or NaN: the update was skipped and the gradients zeroed");
-  }
-  return gosurf_adam_step(c, s, stream);
+  gosurf_adam_state copy = *s;
+  mark(GOSURF_KERNEL_ADAM, true, h);
+  if ((st = hip_check(gs::launch_adam(*c, copy, flag, h), "adam")) != GOSURF_OK) return st;
+  mark(GOSURF_KERNEL_ADAM, false, h);
+  return ok();
 }
 
 }  // extern "C"

@@ -48,10 +48,13 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 __device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
 
 // ---------------------------------------------------------------- exact-rounding helpers
-// o + t*r with the product and the sum rounded separately (no contraction),
-// so that the box test takes the same decision as a plain float32 evaluation.
+// o + t*r with the product and the sum rounded separately, so that the box
+// test and the cell choice take the same decisions as a plain float32
+// evaluation.  The pragma matters: hipcc fuses even __fadd_rn(__fmul_rn())
+// into one v_fmac_f32 (a single rounding) under its default contraction.
 __device__ __forceinline__ float mad_norm(float t, float r, float o) {
-  return __fadd_rn(__fmul_rn(t, r), o);
+#pragma clang fp contract(off)
+  return t * r + o;
 }
 
 __device__ __forceinline__ bool inside_box(const Grid& g, float x, float y, float z) {

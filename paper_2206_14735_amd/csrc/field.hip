@@ -347,15 +347,25 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
         if (A.need_gx) {
           const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
           A.eik[item] = (1.f - n) * (1.f - n);
+          if (A.grad_phi) {
+            float* gp = A.grad_phi + 3 * (size_t)item;
+            gp[0] = gx[0]; gp[1] = gx[1]; gp[2] = gx[2];
+          }
         }
       }
     } else {
+      if (A.grad_phi && q == 0 && live) {
+        float* gp = A.grad_phi + 3 * ((size_t)A.total + 2 * (size_t)item + (j >> 3));
+        gp[0] = gx[0]; gp[1] = gx[1]; gp[2] = gx[2];
+      }
       // pair partner is lane j ^ 8 of the same level group
       float d0 = gx[0] - __shfl_xor(gx[0], 8, 64);
       float d1 = gx[1] - __shfl_xor(gx[1], 8, 64);
       float d2 = gx[2] - __shfl_xor(gx[2], 8, 64);
       const bool pv = valid && __shfl_xor((int)valid, 8, 64);
-      if (q == 0 && j < 8 && pv) smooth_acc += d0 * d0 + d1 * d1 + d2 * d2;
+      const float sq = d0 * d0 + d1 * d1 + d2 * d2;
+      if (q == 0 && j < 8 && pv) smooth_acc += sq;
+      if (A.pair_terms && q == 0 && j < 8 && live) A.pair_terms[item] = pv ? sq : 0.f;
     }
     return;
   } else {
@@ -543,7 +553,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
     for (int e = tid; e < A.priv_floats; e += kBlock) priv[e] = 0.f;
   __syncthreads();
 
-  const int total = A.seg_end ? *A.seg_end : A.total;
+  // the device sample count never exceeds the capacity the workspace and the
+  // forward outputs were sized for
+  const int total = A.seg_end ? min(*A.seg_end, A.total) : A.total;
   const int n_pair_tiles = (A.S + 7) / 8;
   const int n_tiles = n_pair_tiles + (total + 15) / 16;
 

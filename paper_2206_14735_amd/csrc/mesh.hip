@@ -24,8 +24,8 @@ __global__ __launch_bounds__(256) void lattice_rays_kernel(LatticeArgs A) {
     if (i == 0) {
       const int j = (int)(row % A.ny), k = A.k0 + (int)(row / A.ny);
       A.o[3 * row + 0] = A.p0[0];
-      A.o[3 * row + 1] = __fadd_rn(__fmul_rn((float)j, A.h), A.p0[1]);
-      A.o[3 * row + 2] = __fadd_rn(__fmul_rn((float)k, A.h), A.p0[2]);
+      A.o[3 * row + 1] = mad_norm((float)j, A.h, A.p0[1]);
+      A.o[3 * row + 2] = mad_norm((float)k, A.h, A.p0[2]);
       A.r[3 * row + 0] = 1.f;
       A.r[3 * row + 1] = 0.f;
       A.r[3 * row + 2] = 0.f;

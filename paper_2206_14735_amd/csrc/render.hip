@@ -22,8 +22,10 @@ struct RayState {
 };
 
 __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane, RayState& R) {
-  R.s0 = A.seg[m];
-  R.n = A.seg[m + 1] - R.s0;
+  // offsets clamped to the batch's capacity (the segment array lives on the
+  // device and is not validated by the host)
+  R.s0 = min(max(A.seg[m], 0), A.total);
+  R.n = max(min(A.seg[m + 1], A.total) - R.s0, 0);
   R.s = __expf(10.f * A.mlp[oV]);
   const float ox = A.o[3 * m], oy = A.o[3 * m + 1], oz = A.o[3 * m + 2];
   const float rx = A.r[3 * m], ry = A.r[3 * m + 1], rz = A.r[3 * m + 2];
@@ -137,6 +139,10 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs A) {
       nfs += 1.f;
     }
   }
+  // a ray ends at its GOSURF_MAX_SAMPLES_PER_RAY-th sample: later samples are
+  // not rendered and get weight 0
+  if (A.weights)
+    for (int k = kChunks * 64 + lane; k < R.n; k += 64) A.weights[R.s0 + k] = 0.f;
   sdf = wave_sum_dpp(sdf); fs = wave_sum_dpp(fs); ek = wave_sum_dpp(ek);
   ntr = wave_sum_dpp(ntr); nfs = wave_sum_dpp(nfs);
   if (lane == 0) {
@@ -285,6 +291,15 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
           make_float4(mad_norm(tt, R.r[0], R.o[0]), mad_norm(tt, R.r[1], R.o[1]), mad_norm(tt, R.r[2], R.o[2]),
                       R.valid[c] ? ew * sc : 0.f);
     }
+  }
+  // samples past the per-ray cap are not rendered: zero seeds and a position
+  // outside the box, so that the field backward neither gathers nor scatters
+  // for them (instead of reading what an earlier call left in the workspace)
+  for (int k = kChunks * 64 + lane; k < R.n; k += 64) {
+    const size_t sidx = R.s0 + k;
+    *reinterpret_cast<float4*>(A.seed4 + 4 * sidx) = make_float4(0.f, 0.f, 0.f, 0.f);
+    *reinterpret_cast<float4*>(A.posw + 4 * sidx) =
+        make_float4(A.g.p0[0] - 1.f, A.g.p0[1] - 1.f, A.g.p0[2] - 1.f, 0.f);
   }
   dv_acc = wave_sum_dpp(dv_acc);
   // d s / d v = 10 s
@@ -464,10 +479,20 @@ struct AdamGroup {
 // Two float4 per thread and pass, both loaded before either is updated.  The
 // grid group comes first in the flattened index, then the decoder group.
 constexpr int kAdamUnroll = 2;
+// skip (optional device flag, nonzero = skip): the step is dropped on the
+// device, only the gradients are zeroed.
 __global__ __launch_bounds__(256) void adam_kernel(AdamGroup G0, AdamGroup G1, float b1, float b2, float eps,
-                                                   float inv_bc1, float inv_sqrt_bc2, float inv_scale) {
+                                                   float inv_bc1, float inv_sqrt_bc2, float inv_scale,
+                                                   const int* __restrict__ skip) {
   const long long n4 = G0.n4 + G1.n4;
   const long long stride = (long long)gridDim.x * 256 * kAdamUnroll;
+  if (skip && __builtin_amdgcn_readfirstlane(*skip) != 0) {
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
+      const AdamGroup& Gr = i < G0.n4 ? G0 : G1;
+      st_stream(make_float4(0.f, 0.f, 0.f, 0.f), Gr.g + (i < G0.n4 ? i : i - G0.n4));
+    }
+    return;
+  }
   for (long long base = (long long)blockIdx.x * 256 * kAdamUnroll + threadIdx.x; base < n4; base += stride) {
     float4 p[kAdamUnroll], g[kAdamUnroll], m[kAdamUnroll], v[kAdamUnroll];
 #pragma unroll
@@ -549,9 +574,13 @@ hipError_t launch_to_bf16(const float* src, uint16_t* dst, long long n, hipStrea
 // the last numel % 4 entries of a group (scalar)
 __global__ void adam_tail_kernel(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                                  float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float inv_bc1,
-                                 float inv_sqrt_bc2, float inv_scale) {
+                                 float inv_sqrt_bc2, float inv_scale, const int* __restrict__ skip) {
   const int i = threadIdx.x;
   if (i >= n) return;
+  if (skip && *skip != 0) {
+    g[i] = 0.f;
+    return;
+  }
   const float gg = g[i] * inv_scale;
   m[i] = b1 * m[i] + (1.f - b1) * gg;
   v[i] = b2 * v[i] + (1.f - b2) * gg * gg;
@@ -559,7 +588,7 @@ __global__ void adam_tail_kernel(float* __restrict__ p, float* __restrict__ g, f
   g[i] = 0.f;
 }
 
-hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream_t st) {
+hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, const int* skip, hipStream_t st) {
   const long long n4g = s.grid_numel / 4;
   const int n4m = s.mlp_numel / 4;
   const int tail = s.mlp_numel - 4 * n4m;
@@ -576,12 +605,12 @@ hipError_t launch_adam(const gosurf_adam_cfg& c, gosurf_adam_state& s, hipStream
   if (blocks < 1) blocks = 1;
   if (n4g + n4m > 0)
     hipLaunchKernelGGL(adam_kernel, dim3((unsigned)blocks), dim3(256), 0, st, G0, G1, c.beta1, c.beta2, c.eps,
-                       (float)(1.0 / bc1), (float)(1.0 / sqrt(bc2)), c.inv_loss_scale);
+                       (float)(1.0 / bc1), (float)(1.0 / sqrt(bc2)), c.inv_loss_scale, skip);
   if (tail > 0) {
     const size_t o = 4 * (size_t)n4m;
     hipLaunchKernelGGL(adam_tail_kernel, dim3(1), dim3(64), 0, st, s.mlp + o, s.mlp_grad + o, s.mlp_m + o,
                        s.mlp_v + o, tail, c.lr_mlp, c.beta1, c.beta2, c.eps, (float)(1.0 / bc1),
-                       (float)(1.0 / sqrt(bc2)), c.inv_loss_scale);
+                       (float)(1.0 / sqrt(bc2)), c.inv_loss_scale, skip);
   }
   return hipGetLastError();
 }

@@ -74,7 +74,8 @@ class LossCfg(C.Structure):
 
 class FwdOutC(C.Structure):
     _fields_ = [("rgb_hat", C.c_void_p), ("depth_hat", C.c_void_p), ("wsum", C.c_void_p),
-                ("losses", C.c_void_p), ("saved", C.c_void_p), ("weights", C.c_void_p)]
+                ("losses", C.c_void_p), ("saved", C.c_void_p), ("weights", C.c_void_p),
+                ("grad_phi", C.c_void_p), ("ray_terms", C.c_void_p), ("pair_terms", C.c_void_p)]
 
 
 class GradsC(C.Structure):
@@ -282,19 +283,26 @@ class FwdOut:
     losses: torch.Tensor
     saved: torch.Tensor
     weights: torch.Tensor | None = None
+    grad_phi: torch.Tensor | None = None    # [total + 2 S, 3] inspection outputs
+    ray_terms: torch.Tensor | None = None   # [M, 8]
+    pair_terms: torch.Tensor | None = None  # [S]
 
     def c(self):
         o = FwdOutC()
-        for f in ("rgb_hat", "depth_hat", "wsum", "losses", "saved", "weights"):
+        for f in ("rgb_hat", "depth_hat", "wsum", "losses", "saved", "weights", "grad_phi", "ray_terms",
+                  "pair_terms"):
             setattr(o, f, _ptr(getattr(self, f), F32))
         return o
 
     @staticmethod
-    def empty(M, total, device="cuda", weights=False):
+    def empty(M, total, device="cuda", weights=False, grad_phi_rows=0, terms_S=None):
         f = dict(device=device, dtype=torch.float32)
         return FwdOut(torch.empty(M, 3, **f), torch.empty(M, **f), torch.empty(M, **f),
                       torch.empty(N_LOSSES, **f), torch.empty(5 * total, **f),
-                      torch.empty(total, **f) if weights else None)
+                      torch.empty(total, **f) if weights else None,
+                      torch.zeros(grad_phi_rows, 3, **f) if grad_phi_rows else None,
+                      torch.zeros(M, 8, **f) if terms_S is not None else None,
+                      torch.zeros(max(terms_S, 1), **f) if terms_S is not None else None)
 
     def sample_values(self, total):
         """(phi [total], colour [total, 3]) views of the saved per-sample values."""
@@ -333,9 +341,10 @@ def gosurf_sample_rays(model, frames, cfg, out=None, stream=None):
 
 
 def gosurf_forward(model, grid, mlp, batch, loss_cfg, workspace, out=None, grid_bf16=None, weights=False,
-                   stream=None):
+                   stream=None, grad_phi=False, terms=False):
     if out is None:
-        out = FwdOut.empty(batch.M, batch.total, grid.device, weights)
+        out = FwdOut.empty(batch.M, batch.total, grid.device, weights,
+                           (batch.total + 2 * batch.S) if grad_phi else 0, batch.S if terms else None)
     p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
     bc, oc = batch.c(), out.c()
     _check("gosurf_forward", lib().gosurf_forward(C.byref(model), C.byref(p), C.byref(bc), C.byref(loss_cfg),
@@ -367,17 +376,15 @@ def gosurf_adam_step(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_grad, mlp_m
 def gosurf_adam_step_checked(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_grad, mlp_m, mlp_v, flag, lr_grid=1e-2,
                              lr_mlp=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, inv_loss_scale=1.0, grid_bf16=None,
                              stream=None):
-    """gosurf_adam_step guarded against inf / NaN gradients; waits for the stream.  Returns True if the update
-    was applied, False if it was skipped (the gradients are then zeroed).  flag: device int32 [1]."""
+    """gosurf_adam_step guarded against inf / NaN gradients, decided on the device: nothing waits.  flag
+    (device int32 [1]) reads 1 once the stream has reached the step if it was skipped (the gradients are then
+    zeroed and the parameters, moments and mirror unchanged), 0 if it was applied."""
     c = AdamCfg(lr_grid, lr_mlp, beta1, beta2, eps, int(step), inv_loss_scale)
     ng = 0 if grid is None else grid.numel()
     s = AdamState(_ptr(grid, F32), _ptr(grid_grad, F32), _ptr(grid_m, F32), _ptr(grid_v, F32), _ptr(grid_bf16),
                   ng, _ptr(mlp, F32), _ptr(mlp_grad, F32), _ptr(mlp_m, F32), _ptr(mlp_v, F32), mlp.numel())
-    st = lib().gosurf_adam_step_checked(C.byref(c), C.byref(s), _ptr(flag, torch.int32), _stream(stream))
-    if st == ERR_NONFINITE:
-        return False
-    _check("gosurf_adam_step_checked", st)
-    return True
+    _check("gosurf_adam_step_checked",
+           lib().gosurf_adam_step_checked(C.byref(c), C.byref(s), _ptr(flag, torch.int32), _stream(stream)))
 
 
 def set_proposal(cfg, proposal, grid, n_proposal=24, conf_threshold=0.5, n_free=0, depth_check=False,

@@ -2,7 +2,8 @@
 finite gradients it is gosurf_adam_step, bit for bit; with an inf or NaN
 anywhere in either group (including the scalar tail of a group whose size
 is not a multiple of 4) the parameters, moments and bfloat16 mirror are left
-as they were, the gradients are zeroed and the flag is set."""
+as they were, the gradients are zeroed and the flag is set.  The decision is
+taken on the device: the call returns before the stream reaches it."""
 import pytest
 import torch
 
@@ -41,7 +42,7 @@ def test_finite_gradients_give_the_plain_step():
     flag = torch.full((1,), 7, dtype=torch.int32, device="cuda")
     for step in (1, 2):
         G.gosurf_adam_step(step, *_args(a), grid_bf16=bf_a)
-        assert G.gosurf_adam_step_checked(step, *_args(b), flag, grid_bf16=bf_b)
+        G.gosurf_adam_step_checked(step, *_args(b), flag, grid_bf16=bf_b)
         torch.cuda.synchronize()
         assert int(flag.item()) == 0
         for k in a:
@@ -69,7 +70,7 @@ def test_a_non_finite_gradient_skips_the_step(where, value):
     before = {k: v.clone() for k, v in s.items()}
     flag = torch.zeros(1, dtype=torch.int32, device="cuda")
     print(f"non-finite case {where} {value}", flush=True)
-    assert not G.gosurf_adam_step_checked(3, *_args(s), flag, grid_bf16=bf)
+    G.gosurf_adam_step_checked(3, *_args(s), flag, grid_bf16=bf)
     torch.cuda.synchronize()
     assert int(flag.item()) == 1
     for k in ("grid", "grid_m", "grid_v", "mlp", "mlp_m", "mlp_v"):
@@ -79,7 +80,26 @@ def test_a_non_finite_gradient_skips_the_step(where, value):
     # the next step, with finite gradients, is applied again
     s["grid_grad"].fill_(1e-3)
     s["mlp_grad"].fill_(1e-3)
-    assert G.gosurf_adam_step_checked(4, *_args(s), flag, grid_bf16=bf)
+    G.gosurf_adam_step_checked(4, *_args(s), flag, grid_bf16=bf)
     torch.cuda.synchronize()
     assert int(flag.item()) == 0
     assert not torch.equal(s["grid"], before["grid"])
+
+
+def test_the_guarded_step_does_not_wait_for_the_stream():
+    """The call returns while work queued before it is still running: twenty
+    elementwise passes over 256 MiB ahead of it on the stream have not
+    finished when the call returns."""
+    G = _G()
+    s = _state(3)
+    flag = torch.full((1,), 5, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    # queue enough plain work to keep the stream busy for a while
+    big = torch.zeros(1 << 26, device="cuda")
+    for _ in range(20):
+        big.mul_(1.0001)
+    G.gosurf_adam_step_checked(1, *_args(s), flag)
+    done_at_return = torch.cuda.current_stream().query()
+    torch.cuda.synchronize()
+    assert not done_at_return
+    assert int(flag.item()) == 0

@@ -5,7 +5,8 @@ import torch
 
 import synth
 from oracle import sampler as osampler, step as ostep
-from tests.helpers import FWD_TOL, GRAD_TOL, check_close, f32_layout, oracle_weights_of, room_case, sphere_case
+from tests.helpers import (FWD_TOL, GRAD_TOL, check_close, check_parity, clear_of_kinks, f32_layout,
+                           oracle_weights_of, room_case, sphere_case)
 
 pytestmark = pytest.mark.gpu
 
@@ -26,7 +27,7 @@ def run_device(L, b, grid, mlp, lambdas=LAMBDAS, loss_scale=1.0, trunc=0.1):
     ws = G.workspace_for(model, db.M, db.total, db.S)
     g = grid.cuda().contiguous()
     m = mlp.cuda().contiguous()
-    out = G.gosurf_forward(model, g, m, db, lc, ws, weights=True)
+    out = G.gosurf_forward(model, g, m, db, lc, ws, weights=True, grad_phi=True)
     gg = torch.zeros_like(g)
     gm = torch.zeros_like(m)
     G.gosurf_backward(model, g, m, db, lc, out, loss_scale, gg, gm, ws)
@@ -35,45 +36,79 @@ def run_device(L, b, grid, mlp, lambdas=LAMBDAS, loss_scale=1.0, trunc=0.1):
     return dict(phi=phi.cpu().numpy(), col=col.cpu().numpy(), eik=out.saved[4 * db.total:].cpu().numpy(),
                 c_hat=out.rgb_hat.cpu().numpy(), d_hat=out.depth_hat.cpu().numpy(),
                 wsum=out.wsum.cpu().numpy(), w=out.weights.cpu().numpy(), losses=out.losses.cpu().numpy(),
+                grad_phi=out.grad_phi[:db.total].cpu().numpy(),
+                grad_phi_pairs=out.grad_phi[db.total:].view(-1, 2, 3).cpu().numpy(),
                 grad_grid=(gg / loss_scale).cpu().numpy(), grad_mlp=(gm / loss_scale).cpu().numpy())
 
 
-def compare(dev, ref, grads=True, fwd_tol=FWD_TOL, grad_tol=GRAD_TOL, case=None, lambdas=LAMBDAS):
+def oracle_pair(grid, mlp, L, b, lambdas=LAMBDAS, trunc=0.1):
+    """The oracle in float64 (the reference) and the same definition in float32."""
+    cfg = ostep.LossCfg(lambdas=lambdas, trunc=trunc)
+    return (ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, cfg),
+            ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, cfg, dtype=torch.float32))
+
+
+def _np(x):
+    return x.double().numpy() if isinstance(x, torch.Tensor) else np.asarray(x, dtype=np.float64)
+
+
+def compare(dev, ref, ref32, grads=True, fwd_tol=FWD_TOL, grad_tol=GRAD_TOL, case=None, lambdas=LAMBDAS):
+    """Every forward value, the per-sample d(phi)/dx at the samples and the
+    smoothness points, the eight loss slots and both gradients, each against
+    the float64 oracle at the stated tolerance (forward 1e-5, gradients 1e-4),
+    or at twice the error of the float32 evaluation of the same definition
+    where that is larger (see check_parity)."""
     v = ref["valid"].numpy()
-    check_close("phi", dev["phi"][v], ref["phi"].numpy()[v], fwd_tol)
-    check_close("colour", dev["col"][v], ref["col"].numpy()[v], fwd_tol)
-    check_close("c_hat", dev["c_hat"], ref["c_hat"].numpy(), fwd_tol)
-    check_close("d_hat", dev["d_hat"], ref["d_hat"].numpy(), fwd_tol)
-    check_close("wsum", dev["wsum"], ref["wsum"].numpy(), fwd_tol)
-    # Per-sample weights of near-zero opacity are ill-conditioned in phi (alpha
-    # depends on phi_{i+1} - phi_i), so float32 decoder rounding alone moves
-    # them by more than 1e-5 relative.  The render stage itself is held to the
-    # forward tolerance on the device's own SDF values; the end-to-end weights
-    # to 1e-4.
+    for key, name in (("phi", "phi"), ("col", "colour")):
+        check_parity(name, dev[key][v], _np(ref[key])[v], _np(ref32[key])[v], fwd_tol)
+    for key in ("c_hat", "d_hat", "wsum", "w"):
+        check_parity(key, dev[key], _np(ref[key]), _np(ref32[key]), fwd_tol)
+    if lambdas[4] != 0:
+        # d(phi)/dx at every sample inside the box, and the per-sample Eikonal residual
+        check_parity("grad phi (samples)", dev["grad_phi"][v], _np(ref["grad_phi"])[v],
+                     _np(ref32["grad_phi"])[v], fwd_tol)
+        res = lambda g: (1.0 - np.linalg.norm(g, axis=1)) ** 2  # noqa: E731
+        check_parity("Eikonal residual", dev["eik"][v], res(_np(ref["grad_phi"]))[v],
+                     res(_np(ref32["grad_phi"]))[v], fwd_tol)
+    if lambdas[5] != 0 and len(ref["grad_phi_pairs"]):
+        ok = ref["pair_ok"].numpy()
+        check_parity("grad phi (smoothness points)", dev["grad_phi_pairs"][ok], _np(ref["grad_phi_pairs"])[ok],
+                     _np(ref32["grad_phi_pairs"])[ok], fwd_tol)
+    # the render stage alone, on the device's own SDF values
     if case is not None:
         L, b, mlp = case
         w_ref, c_ref, d_ref = oracle_weights_of(dev["phi"], dev["col"], L, b, mlp[-1])
-        check_close("weights (render stage)", dev["w"], w_ref, fwd_tol)
-        check_close("d_hat (render stage)", dev["d_hat"], d_ref, fwd_tol)
-    check_close("weights", dev["w"], ref["w"].numpy(), 10 * fwd_tol, max_bad_frac=0.02)
+        check_close("weights (render stage)", dev["w"], w_ref, fwd_tol, entry_tol=fwd_tol)
+        check_close("d_hat (render stage)", dev["d_hat"], d_ref, fwd_tol, entry_tol=fwd_tol)
     names = ["rgb", "depth", "sdf", "fs", "eik", "smooth"]
     for k, n in enumerate(names):
         # the Eikonal and smoothness terms are not evaluated when their weight is 0
         r = 0.0 if (k >= 4 and lambdas[k] == 0) else ref["losses"][n]
-        assert abs(dev["losses"][k] - r) <= fwd_tol * max(abs(r), 1e-6), (n, dev["losses"][k], r)
-    assert abs(dev["losses"][6] - ref["total"]) <= fwd_tol * abs(ref["total"])
+        r32 = 0.0 if (k >= 4 and lambdas[k] == 0) else ref32["losses"][n]
+        bound = max(fwd_tol * max(abs(r), 1e-6), 2 * abs(r32 - r))
+        assert abs(dev["losses"][k] - r) <= bound, (n, dev["losses"][k], r, r32)
+    assert abs(dev["losses"][6] - ref["total"]) <= max(fwd_tol * abs(ref["total"]), 2 * abs(ref32["total"] - ref["total"]))
     if grads:
-        check_close("grad_mlp", dev["grad_mlp"], ref["grad_mlp"].numpy(), grad_tol, max_bad_frac=0.002)
-        check_close("grad_grid", dev["grad_grid"], ref["grad_grid"].numpy(), grad_tol, max_bad_frac=0.002)
+        check_parity("grad_mlp", dev["grad_mlp"], _np(ref["grad_mlp"]), _np(ref32["grad_mlp"]), grad_tol)
+        check_parity("grad_grid", dev["grad_grid"], _np(ref["grad_grid"]), _np(ref32["grad_grid"]), grad_tol)
         # entries no sample touches must be exactly zero
         untouched = ref["grad_grid"].numpy() == 0
         assert np.all(dev["grad_grid"][untouched] == 0)
 
 
+def _clear(grid, mlp, L, b):
+    """The batch without rays and pairs within float32 reach of a kink of the
+    method (a ReLU unit at 0, the opacity clamp): there the derivative jumps
+    and the float32 and float64 sides may take different one-sided values."""
+    b2, nr, npairs = clear_of_kinks(grid.numpy(), mlp.numpy(), L, b)
+    print(f"{nr} rays and {npairs} pairs at a kink left out", flush=True)
+    return b2
+
+
 def test_sphere_step_matches_oracle():
     L, fr, b, grid, mlp = sphere_case(grid_std=0.3)
-    ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b)
-    compare(run_device(L, b, grid, mlp), ref, case=(L, b, mlp))
+    b = _clear(grid, mlp, L, b)
+    compare(run_device(L, b, grid, mlp), *oracle_pair(grid, mlp, L, b), case=(L, b, mlp))
 
 
 def test_sphere_flat_initialisation():
@@ -81,33 +116,39 @@ def test_sphere_flat_initialisation():
 
     The SDF is then almost constant along every ray, so each opacity is
     proportional to phi_{i+1} - phi_i ~ 1e-4 while float32 rounds phi to
-    ~1e-8: the per-sample weights, and through them the colour term's
-    gradient (dL/dc_i = dL/dc_hat * w_i), are conditioning-limited to ~1e-3
-    relative.  Every other term is held to the gradient tolerance; the full
-    objective's grid gradient to 5e-4."""
+    ~1e-8: the per-sample weights, and through them the grid gradient, are
+    conditioning-limited in float32 (the oracle's own float32 evaluation is
+    1.2e-4 off in the grid gradient).  The device is held to the stated
+    tolerances or twice that float32 error, whichever is larger, with and
+    without the colour term."""
     L, fr, b, grid, mlp = sphere_case(grid_std=0.01)
+    b = _clear(grid, mlp, L, b)
     no_rgb = (0.0,) + LAMBDAS[1:]
-    ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, ostep.LossCfg(lambdas=no_rgb))
-    compare(run_device(L, b, grid, mlp, lambdas=no_rgb), ref, case=(L, b, mlp), lambdas=no_rgb)
-    ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b)
-    dev = run_device(L, b, grid, mlp)
-    check_close("grad_mlp (all terms)", dev["grad_mlp"], ref["grad_mlp"].numpy(), GRAD_TOL, max_bad_frac=0.01)
-    check_close("grad_grid (all terms)", dev["grad_grid"], ref["grad_grid"].numpy(), 5 * GRAD_TOL,
-                max_bad_frac=0.01)
+    compare(run_device(L, b, grid, mlp, lambdas=no_rgb), *oracle_pair(grid, mlp, L, b, no_rgb), case=(L, b, mlp),
+            lambdas=no_rgb)
+    compare(run_device(L, b, grid, mlp), *oracle_pair(grid, mlp, L, b), case=(L, b, mlp))
+
+
+def test_room_flat_initialisation():
+    """The room with grid features ~ N(0, 0.01^2), as the sphere above."""
+    L, fr, b, grid, mlp = room_case(M=256, S=512, grid_std=0.01)
+    b = _clear(grid, mlp, L, b)
+    compare(run_device(L, b, grid, mlp), *oracle_pair(grid, mlp, L, b), case=(L, b, mlp))
 
 
 def test_room_ragged_batch_matches_oracle():
     # 203 rays x (61 + 30) samples: ragged wave tiles; 301 smoothness pairs
     L, fr, b, grid, mlp = room_case(M=203, S=301, n_strat=61, n_near=30)
-    ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b)
-    compare(run_device(L, b, grid, mlp), ref, case=(L, b, mlp))
+    b = _clear(grid, mlp, L, b)
+    compare(run_device(L, b, grid, mlp), *oracle_pair(grid, mlp, L, b), case=(L, b, mlp))
 
 
 def test_loss_scale_and_disabled_terms():
     L, fr, b, grid, mlp = sphere_case(M=300, S=100, grid_std=0.2)
+    b = _clear(grid, mlp, L, b)
     lam = (10.0, 1.0, 10.0, 1.0, 0.0, 0.0)
-    ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, ostep.LossCfg(lambdas=lam))
-    compare(run_device(L, b, grid, mlp, lambdas=lam, loss_scale=1024.0), ref, case=(L, b, mlp), lambdas=lam)
+    compare(run_device(L, b, grid, mlp, lambdas=lam, loss_scale=1024.0), *oracle_pair(grid, mlp, L, b, lam),
+            case=(L, b, mlp), lambdas=lam)
 
 
 def test_variable_length_rays_and_no_smoothness():
@@ -121,9 +162,12 @@ def test_variable_length_rays_and_no_smoothness():
     t = np.concatenate([np.sort(rng.uniform(0.1, 3.0, n)) for n in lens]).astype(np.float32)
     b = ostep.Batch(b0.o, b0.r, b0.rgb, b0.depth, t, seg, np.zeros((0, 3), np.float32),
                     np.zeros((0, 3), np.float32))
-    ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b)
+    relu, clamp, _ = __import__("tests.helpers", fromlist=["kink_margins"]).kink_margins(grid.numpy(), mlp.numpy(),
+                                                                                          L, b)
+    assert relu.min() >= 2e-7 and clamp.min() >= 5e-7          # every ray clear of kinks
+    ref, ref32 = oracle_pair(grid, mlp, L, b)
     assert not ref["valid"].all()
-    compare(run_device(L, b, grid, mlp), ref, case=(L, b, mlp))
+    compare(run_device(L, b, grid, mlp), ref, ref32, case=(L, b, mlp))
 
 
 def test_sampler_matches_oracle():
@@ -221,3 +265,78 @@ def test_autograd_function_matches_direct_calls():
     assert abs(float(loss) - ref["losses"][6]) <= 1e-6 * abs(ref["losses"][6])
     check_close("grad_mlp", m.grad.cpu().numpy() / 3.0, ref["grad_mlp"], GRAD_TOL)
     check_close("grad_grid", g.grad.cpu().numpy() / 3.0, ref["grad_grid"], GRAD_TOL, max_bad_frac=0.002)
+
+
+@pytest.mark.parametrize("upstream", [-2.0, 0.0])
+def test_autograd_function_negative_and_zero_upstream(upstream):
+    """A negative incoming gradient gives the negated gradients (the library
+    takes any finite loss scale); a zero one gives zero gradients."""
+    G = _G()
+    from paper_2206_14735_amd.autograd import gosurf_loss
+    L, fr, b, grid, mlp = sphere_case(M=256, S=512, grid_std=0.3)
+    model = G.make_model(L)
+    db = G.RayBatch.from_host(b)
+    lc = G.make_loss_cfg(LAMBDAS)
+    ws = G.workspace_for(model, db.M, db.total, db.S)
+    g = grid.cuda().requires_grad_(True)
+    m = mlp.cuda().requires_grad_(True)
+    loss = gosurf_loss(g, m, model, db, lc, ws)
+    (upstream * loss).backward()
+    torch.cuda.synchronize()
+    if upstream == 0.0:
+        assert torch.count_nonzero(g.grad) == 0 and torch.count_nonzero(m.grad) == 0
+        return
+    ref = run_device(L, b, grid, mlp)
+    check_close("grad_mlp", m.grad.cpu().numpy() / upstream, ref["grad_mlp"], GRAD_TOL)
+    check_close("grad_grid", g.grad.cpu().numpy() / upstream, ref["grad_grid"], GRAD_TOL, max_bad_frac=0.002)
+
+
+def test_ray_longer_than_the_cap_ends_at_the_cap():
+    """A ray of 300 samples (above GOSURF_MAX_SAMPLES_PER_RAY = 256) is rendered
+    and differentiated as the ray of its first 256 samples: the device result
+    on the long batch equals the oracle's on the batch cut to 256, and the
+    samples past the cap get weight 0 and contribute no gradient (the
+    workspace is first filled by a different batch, so stale seeds would
+    show)."""
+    G = _G()
+    L, fr, b0, grid, mlp = sphere_case(M=3, S=0, grid_std=0.3)
+    rng = np.random.default_rng(11)
+    lens_long = np.array([300, 50, 260])
+    t_long = [np.sort(rng.uniform(0.1, 3.0, n)).astype(np.float32) for n in lens_long]
+    lens_cut = np.minimum(lens_long, 256)
+    t_cut = [t[:n] for t, n in zip(t_long, lens_cut)]
+
+    def batch(ts, lens):
+        seg = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+        return ostep.Batch(b0.o, b0.r, b0.rgb, b0.depth, np.concatenate(ts), seg, np.zeros((0, 3), np.float32),
+                           np.zeros((0, 3), np.float32))
+
+    b_long, b_cut = batch(t_long, lens_long), batch(t_cut, lens_cut)
+    # a first backward with other samples along the same rays leaves seeds in the workspace
+    b_other = batch([np.sort(rng.uniform(0.1, 3.0, n)).astype(np.float32) for n in lens_long], lens_long)
+    model = G.make_model(L)
+    lc = G.make_loss_cfg(LAMBDAS)
+    db_o, db_l = G.RayBatch.from_host(b_other), G.RayBatch.from_host(b_long)
+    ws = G.workspace_for(model, db_l.M, db_l.total, db_l.S)
+    g, m = grid.cuda(), mlp.cuda()
+    out = G.gosurf_forward(model, g, m, db_o, lc, ws)
+    G.gosurf_backward(model, g, m, db_o, lc, out, 1.0, torch.zeros_like(g), torch.zeros_like(m), ws)
+    out = G.gosurf_forward(model, g, m, db_l, lc, ws, weights=True)
+    gg, gm = torch.zeros_like(g), torch.zeros_like(m)
+    G.gosurf_backward(model, g, m, db_l, lc, out, 1.0, gg, gm, ws)
+    torch.cuda.synchronize()
+    ref, ref32 = oracle_pair(grid, mlp, L, b_cut)
+    check_parity("c_hat", out.rgb_hat.cpu().numpy(), _np(ref["c_hat"]), _np(ref32["c_hat"]), FWD_TOL)
+    check_parity("d_hat", out.depth_hat.cpu().numpy(), _np(ref["d_hat"]), _np(ref32["d_hat"]), FWD_TOL)
+    w = out.weights.cpu().numpy()
+    seg_l = np.concatenate([[0], np.cumsum(lens_long)])
+    keep = np.concatenate([np.arange(seg_l[i], seg_l[i] + lens_cut[i]) for i in range(3)])
+    drop = np.setdiff1d(np.arange(seg_l[-1]), keep)
+    assert drop.size == 48 and np.all(w[drop] == 0)
+    check_parity("weights", w[keep], _np(ref["w"]), _np(ref32["w"]), FWD_TOL)
+    for k, n in enumerate(["rgb", "depth", "sdf", "fs", "eik"]):
+        r = ref["losses"][n]
+        assert abs(float(out.losses[k]) - r) <= FWD_TOL * max(abs(r), 1e-6), n
+    check_parity("grad_mlp", gm.cpu().numpy(), _np(ref["grad_mlp"]), _np(ref32["grad_mlp"]), GRAD_TOL)
+    check_parity("grad_grid", gg.cpu().numpy(), _np(ref["grad_grid"]), _np(ref32["grad_grid"]), GRAD_TOL)
+    assert np.all(gg.cpu().numpy()[ref["grad_grid"].numpy() == 0] == 0)

@@ -1,10 +1,18 @@
 """The stress configuration at its full size (0.02 m finest level, 117 M grid
 parameters, 65536 rays x (96 + 32) samples, 2^20 smoothness pairs) in the
-launch configuration the benchmark times: the device forward of the whole
-batch against the FP64 oracle on sampled rays, and device gradients against
-the oracle on a small subset of the batch over the full grid.  The kernels
-are the same code as at the room size; these cases add the large grid
-offsets and the full sample and pair counts.  60 frames stand in for the
+launch configuration the benchmark times:
+
+* the device forward of the whole batch against the FP64 oracle on sampled
+  rays (rays are independent, so the oracle evaluates only those);
+* device gradients against the oracle on a 1/64 subset of the batch (1024
+  rays and 16384 smoothness pairs) over the full grid;
+* device gradients of the full batch against central differences (h = 1e-3)
+  of the device's own loss on 1000 grid entries (250 per level) and on
+  decoder weights, and every grid entry that no sample or smoothness point
+  reaches exactly 0.
+
+The kernels are the same code as at the room size; these cases add the large
+grid offsets and the full sample and pair counts.  60 frames stand in for the
 1000 of the benchmark (the frame count changes only which pixels are drawn)."""
 import numpy as np
 import pytest
@@ -12,9 +20,11 @@ import torch
 
 import synth
 from oracle import step as ostep
-from tests.helpers import FWD_TOL, GRAD_TOL, check_close, f32_layout  # noqa: F401
+from tests.helpers import CLAMP_MARGIN, FWD_TOL, GRAD_TOL, RELU_MARGIN, check_parity, f32_layout, kink_margins
 
 pytestmark = pytest.mark.gpu
+
+LAMS = (10.0, 1.0, 10.0, 1.0, 1.0, 1.0)    # rgb, depth, sdf, free space, Eikonal, smoothness
 
 
 @pytest.fixture(scope="module")
@@ -47,136 +57,324 @@ def _subset(host, rays, pairs):
                        host["xs"][pairs].reshape(-1, 3), host["eps"][pairs].reshape(-1, 3))
 
 
+def _np(x):
+    return x.double().numpy() if isinstance(x, torch.Tensor) else np.asarray(x, dtype=np.float64)
+
+
 def test_stress_forward_matches_oracle_on_sampled_rays(stress_full):
     R = stress_full
     rng = np.random.default_rng(4)
     M = R["host"]["o"].shape[0]
     rays = np.sort(np.concatenate([rng.choice(M - 1, 31, replace=False), [M - 1]]))   # the last ray included
     sub = _subset(R["host"], rays, np.zeros(0, dtype=np.int64))
-    ref = ostep.evaluate(R["grid"].double().numpy(), R["mlp"].double().numpy(), R["L"], sub, want_grads=False)
+    g64, m64 = R["grid"].double().numpy(), R["mlp"].double().numpy()
+    ref = ostep.evaluate(g64, m64, R["L"], sub, want_grads=False)
+    ref32 = ostep.evaluate(g64, m64, R["L"], sub, want_grads=False, dtype=torch.float32)
     out, seg = R["out"], R["host"]["seg"]
     phi, col = out.sample_values(int(seg[-1]))
     phi, col = phi.cpu().numpy(), col.cpu().numpy()
     idx = np.concatenate([np.arange(seg[m], seg[m + 1]) for m in rays])
     v = ref["valid"].numpy()
     assert v.any()
-    check_close("phi", phi[idx][v], ref["phi"].numpy()[v], FWD_TOL)
-    check_close("colour", col[idx][v], ref["col"].numpy()[v], FWD_TOL)
-    check_close("c_hat", out.rgb_hat.cpu().numpy()[rays], ref["c_hat"].numpy(), FWD_TOL)
-    check_close("d_hat", out.depth_hat.cpu().numpy()[rays], ref["d_hat"].numpy(), FWD_TOL)
-    check_close("wsum", out.wsum.cpu().numpy()[rays], ref["wsum"].numpy(), FWD_TOL)
-    check_close("weights", out.weights.cpu().numpy()[idx], ref["w"].numpy(), 10 * FWD_TOL, max_bad_frac=0.02)
+    check_parity("phi", phi[idx][v], _np(ref["phi"])[v], _np(ref32["phi"])[v], FWD_TOL)
+    check_parity("colour", col[idx][v], _np(ref["col"])[v], _np(ref32["col"])[v], FWD_TOL)
+    for key, dev in (("c_hat", out.rgb_hat), ("d_hat", out.depth_hat), ("wsum", out.wsum)):
+        check_parity(key, dev.cpu().numpy()[rays], _np(ref[key]), _np(ref32[key]), FWD_TOL)
+    check_parity("weights", out.weights.cpu().numpy()[idx], _np(ref["w"]), _np(ref32["w"]), FWD_TOL)
 
 
-LAMS = (10.0, 1.0, 10.0, 1.0, 1.0, 1.0)    # rgb, depth, sdf, free space, Eikonal, smoothness
-
-
-def _gradient_errors(R, sub, lams):
-    """Device gradients of the subset batch against the oracle's: relative L2
-    and largest error / rms of the decoder gradient and of each grid level."""
+def test_stress_gradients_on_a_1_64_subset_match_oracle(stress_full):
+    """Gradients of a 1/64 subset (1024 rays, 16384 pairs) over the full
+    117 M-entry grid.  Rays and pairs within one float32 rounding of a kink of
+    the method (a ReLU pre-activation at 0, the opacity clamp at alpha = 0)
+    are left out: there the derivative jumps, and where float32 and float64
+    land on different sides both gradients are valid and differ."""
+    R = stress_full
     G = R["G"]
+    rng = np.random.default_rng(5)
+    M = R["host"]["o"].shape[0]
+    S = R["host"]["xs"].shape[0]
+    rays = np.sort(rng.choice(M, M // 64, replace=False))
+    pairs = np.sort(rng.choice(S, S // 64, replace=False))
+    relu, clamp, pm = kink_margins(R["grid"].numpy(), R["mlp"].numpy(), R["L"], _subset(R["host"], rays, pairs))
+    near_r = (relu < RELU_MARGIN) | (clamp < CLAMP_MARGIN)
+    near_p = pm < RELU_MARGIN
+    print(f"1/64 subset: {near_r.sum()} of {len(rays)} rays and {near_p.sum()} of {len(pairs)} pairs at a kink",
+          flush=True)
+    assert near_r.sum() <= len(rays) // 16 and near_p.sum() <= len(pairs) // 16
+    sub = _subset(R["host"], rays[~near_r], pairs[~near_p])
     db = G.RayBatch.from_host(sub)
-    lc = G.make_loss_cfg(lams)
+    lc = G.make_loss_cfg(LAMS)
     ws = G.workspace_for(R["rec"].model, db.M, db.total, db.S)
     g, m = R["rec"].grid, R["rec"].mlp
     o = G.gosurf_forward(R["rec"].model, g, m, db, lc, ws)
     gg, gm = torch.zeros_like(g), torch.zeros_like(m)
     G.gosurf_backward(R["rec"].model, g, m, db, lc, o, 1.0, gg, gm, ws)
     torch.cuda.synchronize()
-    ref = ostep.evaluate(R["grid"].double().numpy(), R["mlp"].double().numpy(), R["L"], sub, ostep.LossCfg(lams))
-    out = {"loss": (float(o.losses[6]), ref["total"])}
-    dm, rm = gm.cpu().numpy().astype(np.float64), ref["grad_mlp"].numpy()
-    rms = np.sqrt(np.mean(rm ** 2))
-    out["mlp"] = (np.linalg.norm(dm - rm) / np.linalg.norm(rm), np.abs(dm - rm).max() / rms)
-    rg, dg = ref["grad_grid"].numpy(), gg.cpu().numpy()
+    g64, m64 = R["grid"].double().numpy(), R["mlp"].double().numpy()
+    ref = ostep.evaluate(g64, m64, R["L"], sub, ostep.LossCfg(LAMS))
+    ref32 = ostep.evaluate(g64, m64, R["L"], sub, ostep.LossCfg(LAMS), dtype=torch.float32)
+    tot, tot32 = ref["total"], ref32["total"]
+    assert abs(float(o.losses[6]) - tot) <= max(FWD_TOL * abs(tot), 2 * abs(tot32 - tot))
+    e = check_parity("grad_mlp", gm.cpu().numpy(), _np(ref["grad_mlp"]), _np(ref32["grad_mlp"]), GRAD_TOL)
+    print(f"decoder gradient: relative L2 {e[0]:.2e} (float32 evaluation {e[1]:.2e})", flush=True)
+    rg, rg32, dg = _np(ref["grad_grid"]), _np(ref32["grad_grid"]), gg.cpu().numpy()
     touched = rg != 0
-    out["untouched_zero"] = bool(np.all(dg[~touched] == 0))
+    assert np.all(dg[~touched] == 0)
     L = R["L"]
     for lv in range(4):
         a_, b_ = L.offsets[lv], L.offsets[lv] + int(np.prod(L.dims[lv]))
         t = touched[a_:b_]
-        r, d = rg[a_:b_][t], dg[a_:b_][t]
-        rms = np.sqrt(np.mean(r ** 2))
-        err = np.abs(d - r)
-        out[f"level{lv}"] = (np.linalg.norm(d - r) / np.linalg.norm(r), err.max() / rms,
-                             float(np.mean(err > 10 * GRAD_TOL * np.maximum(np.abs(r), 1e-2 * rms))))
-    return out
+        e = check_parity(f"grad_grid level {lv}", dg[a_:b_][t], rg[a_:b_][t], rg32[a_:b_][t], GRAD_TOL)
+        print(f"level {lv}: {int(t.sum())} touched entries, relative L2 {e[0]:.2e} (float32 evaluation {e[1]:.2e})",
+              flush=True)
 
 
-def _kink_margins(R, sub):
-    """Per ray, from oracle values: the smallest |pre-activation| of any ReLU
-    unit of the two decoders at its valid samples, and the smallest
-    |1 - Phi_s(phi_{i+1}) / Phi_s(phi_i)| over its pairs of consecutive valid
-    samples (the distance from the max(., 0) clamp of Eq.
-    volume_rendering_alpha)."""
-    from oracle import decoder as OD, grid as OG
-    g64 = torch.as_tensor(R["grid"].double().numpy())
-    P = OD.unpack(torch.as_tensor(R["mlp"].numpy(), dtype=torch.float64))
-    ref = ostep.evaluate(g64.numpy(), R["mlp"].double().numpy(), R["L"], sub, want_grads=False)
-    s = float(OD.sharpness(P))
-    phi, valid = ref["phi"].numpy(), ref["valid"].numpy()
-    ray = np.repeat(np.arange(len(sub.seg) - 1), np.diff(sub.seg))
-    x = (np.asarray(sub.o, np.float64)[ray] + np.asarray(sub.t, np.float64)[:, None] * np.asarray(sub.r, np.float64)[ray])
-    z = OG.interp_all(g64, R["L"], torch.as_tensor(x[valid]))
-    p1 = z @ P["W1"].T + P["b1"]
-    p2 = torch.relu(p1) @ P["W2"].T + P["b2"]
-    o = torch.relu(p2) @ P["W3"].T + P["b3"]
-    pc = o[:, 1:] @ P["U1"].T + P["c1"]
-    pre = np.full(len(valid), np.inf)
-    pre[valid] = torch.cat([p1, p2, pc], 1).abs().min(1).values.numpy()
-    relu, clamp = [], []
-    for m in range(len(sub.seg) - 1):
-        sl = slice(sub.seg[m], sub.seg[m + 1])
-        v = valid[sl]
-        relu.append(pre[sl][v].min() if v.any() else np.inf)
-        ls = -np.logaddexp(0.0, -s * phi[sl])                  # log Phi_s
-        a = -np.expm1(ls[1:] - ls[:-1])
-        pair = v[1:] & v[:-1]
-        clamp.append(np.abs(a[pair]).min() if pair.any() else np.inf)
-    return np.array(relu), np.array(clamp)
+def _touched_rows(R, loose=False):
+    """Grid rows reached by the full batch: the 8 corners, per level, of every
+    sample inside the box and of both points of every pair inside it (positions
+    rounded as the device rounds them).  loose: every point, cells decided in
+    float64 and widened by one cell (a diagnostic superset)."""
+    L, h = R["L"], R["host"]
+    seg = h["seg"].astype(np.int64)
+    ray = np.repeat(np.arange(len(seg) - 1), np.diff(seg))
+    t = h["t"][: seg[-1]].astype(np.float32)
+    x = (h["o"][ray] + (t[:, None] * h["r"][ray]).astype(np.float32)).astype(np.float32)
+    xs = h["xs"].astype(np.float32)
+    x2 = (xs + h["eps"].astype(np.float32)).astype(np.float32)
+    lo, hi = np.asarray(L.p0, np.float32), np.asarray(L.p1, np.float32)
+    inside = lambda p: np.all((p >= lo) & (p <= hi), axis=1)  # noqa: E731
+    pv = inside(xs) & inside(x2)
+    if loose:
+        pts = np.concatenate([x, xs, x2]).astype(np.float64)
+    else:
+        pts = np.concatenate([x[inside(x)], xs[pv], x2[pv]]).astype(np.float32)
+    mask = np.zeros(int(L.offsets[-1] + np.prod(L.dims[-1])), dtype=bool)
+    for lv in range(4):
+        nx, ny, nz = L.dims[lv]
+        u = (pts - np.asarray(L.p0, pts.dtype)) / pts.dtype.type(L.voxels[lv])    # float32, as the device
+        i0 = np.clip(np.floor(u).astype(np.int64), 0, np.array([nx - 2, ny - 2, nz - 2]))
+        shifts = (-1, 0, 1, 2) if loose else (0, 1)
+        for bx in shifts:
+            for by in shifts:
+                for bz in shifts:
+                    ix = np.clip(i0[:, 0] + bx, 0, nx - 1)
+                    iy = np.clip(i0[:, 1] + by, 0, ny - 1)
+                    iz = np.clip(i0[:, 2] + bz, 0, nz - 1)
+                    mask[L.offsets[lv] + (iz * ny + iy) * nx + ix] = True
+    return mask
 
 
-def test_stress_gradients_on_a_subset_match_oracle(stress_full):
-    """Gradients are compared on rays clear of the method's kinks (a ReLU
-    unit's pre-activation at 0, the opacity clamp at alpha = 0): there the
-    derivative jumps, so where float32 and float64 land on different sides
-    the two gradients are both valid and differ.  Of the 64 rays drawn here
-    one has a geometry-decoder pre-activation 5e-8 from 0 (the next smallest
-    margin is 4e-7); it alone differed, by 3e-3 in the decoder gradient."""
+def _explain_rows(R, rows):
+    """Diagnostic: the points nearest to the given finest-level rows."""
+    L, h = R["L"], R["host"]
+    seg = h["seg"].astype(np.int64)
+    ray = np.repeat(np.arange(len(seg) - 1), np.diff(seg))
+    t = h["t"][: seg[-1]].astype(np.float32)
+    x = (h["o"][ray] + (t[:, None] * h["r"][ray]).astype(np.float32)).astype(np.float32)
+    xs = h["xs"].astype(np.float32)
+    x2 = (xs + h["eps"].astype(np.float32)).astype(np.float32)
+    lv = 3
+    nx, ny, nz = L.dims[lv]
+    for row in rows:
+        rl = int(row) - L.offsets[lv]
+        vi = np.array([rl % nx, (rl // nx) % ny, rl // (nx * ny)])
+        vpos = np.asarray(L.p0, np.float64) + vi * L.voxels[lv]
+        for name, P in (("sample", x), ("pair x", xs), ("pair x+eps", x2)):
+            d = np.abs(P.astype(np.float64) - vpos).max(1)
+            k = int(np.argmin(d))
+            u = (P[k] - np.asarray(L.p0, np.float32)) / np.float32(L.voxels[lv])
+            extra = ""
+            if name == "sample":
+                extra = f" ray {ray[k]} t {t[k]!r}"
+            else:
+                extra = f" pair {k} xs {xs[k]!r} eps {h['eps'][k]!r}"
+            print(f"row {row} vertex {vi}: nearest {name} at {d[k]:.4f} m, u {u!r}{extra}", flush=True)
+
+
+def test_stress_gradients_match_central_differences_at_full_size(stress_full):
+    """Central differences of the device loss of the FULL batch.
+
+    In float32 the total loss (a mean over 65536 rays and 2^20 pairs) cannot
+    resolve one entry's effect (about 1e-9 against a rounding of 6e-8), so
+    each difference is taken on the per-ray terms and per-pair smoothness
+    values the forward reports, differenced in float64 and weighted as the
+    total weights them: rays and pairs the probe does not reach give
+    bit-identical terms.
+
+    The loss is piecewise smooth (ReLU units, |.|, max, the opacity clamp): a
+    step that carries a sample across a kink gives a quotient that is no
+    derivative.  Each probe therefore takes the quotients D(h), D(h/2) and
+    D(h/4) with h = 1e-3; a kink crossed at distance x moves exactly those
+    whose step exceeds x, so the probe is clear of kinks when the three agree
+    within 0.5 % (plus the rounding noise of the terms that moved), and then
+    D(h/4) must match the analytic gradient within 1 % plus that noise.
+
+    Probes: 250 grid entries per level (half uniformly among the entries whose
+    gradient is at least 1e-2 of the level's rms, below which an entry moves
+    the terms by less than their rounding, half among the 10 % largest) and
+    40 decoder weights.
+    At the two coarse levels (0.96 and 0.24 m) an entry reaches 10^5 - 10^6
+    samples of this unconverged field, and some hundred of them sit within
+    the step's reach of a kink of |phi - b| alone (a slope jump of about 5e-6
+    each, against gradients of 1e-4 .. 1e-3): no step of usable size is clear
+    of kinks there, so those probes are reported and the coarse levels are
+    held to the subset decomposition below instead.  Finally every grid entry
+    that no sample or pair point reaches is exactly 0."""
     R = stress_full
-    rng = np.random.default_rng(5)
-    M = R["host"]["o"].shape[0]
-    S = R["host"]["xs"].shape[0]
-    rays = np.sort(rng.choice(M, M // 1024, replace=False))
-    pairs = np.sort(rng.choice(S, S // 4096, replace=False))
-    relu, clamp = _kink_margins(R, _subset(R["host"], rays, np.zeros(0, dtype=np.int64)))
-    # about one float32 rounding of an O(1) sum: closer than this, the two
-    # precisions may take different branches
-    near = (relu < 2e-7) | (clamp < 2e-7)
-    print(f"smallest ReLU margins {np.sort(relu)[:4]}, smallest clamp margins {np.sort(clamp)[:4]}; rays at a kink "
-          "(ray, ReLU margin, clamp margin): "
-          + ", ".join(f"({r}, {a_:.1e}, {c_:.1e})" for r, a_, c_ in zip(rays[near], relu[near], clamp[near])),
+    G, rec = R["G"], R["rec"]
+    g, m, db, lc, ws = rec.grid, rec.mlp, rec.batch, rec.loss_cfg, rec.ws
+    Mr, S = db.M, db.S
+    o = G.gosurf_forward(rec.model, g, m, db, lc, ws)
+    gg, gm = torch.zeros_like(g), torch.zeros_like(m)
+    G.gosurf_backward(rec.model, g, m, db, lc, o, 1.0, gg, gm, ws)
+    torch.cuda.synchronize()
+    nd = float(o.losses[7])
+    lam = LAMS
+    wcol = torch.tensor([lam[0] / Mr, lam[1] / nd, lam[2] / Mr, lam[3] / Mr, lam[4] / Mr, 0, 0, 0],
+                        dtype=torch.float64, device=g.device)
+    fo = G.FwdOut.empty(Mr, db.total, g.device, terms_S=S)
+    ulp = 8 * 2.0 ** -24     # rounding of a per-ray or per-pair term (a few ulps of a short sum)
+
+    def terms():
+        G.gosurf_forward(rec.model, g, m, db, lc, ws, out=fo)
+        return fo.ray_terms.double(), fo.pair_terms.double()
+
+    def quotient(set_value, v0, step):
+        """D(step) and the standard deviation of its rounding noise."""
+        set_value(v0 + step)
+        rp, pp = terms()
+        set_value(v0 - step)
+        rn, pn = terms()
+        set_value(v0)
+        d = ((rp - rn) * wcol).sum() + lam[5] / S * (pp - pn).sum()
+        moved_r = torch.any(rp != rn, dim=1, keepdim=True)
+        var = (((rp.abs() * wcol * moved_r) ** 2).sum() * 2
+               + (lam[5] / S) ** 2 * ((pp.abs() * (pp != pn)) ** 2).sum() * 2) * ulp ** 2
+        return float(d) / (2 * step), float(var) ** 0.5 / (2 * step)
+
+    h = 1e-3
+    gh = gg.view(-1).cpu().numpy()
+    L = R["L"]
+    rng = np.random.default_rng(7)
+    probes = []
+    for lv in range(4):
+        a_, b_ = 4 * L.offsets[lv], 4 * (L.offsets[lv] + int(np.prod(L.dims[lv])))
+        nz = gh[a_:b_][gh[a_:b_] != 0]
+        rms = float(np.sqrt(np.mean(nz.astype(np.float64) ** 2)))
+        # entries far below the level's rms move the terms by less than their rounding
+        idx = a_ + np.nonzero(np.abs(gh[a_:b_]) >= 1e-2 * rms)[0]
+        assert len(idx) >= 250, lv
+        big = idx[np.argsort(-np.abs(gh[idx]))[: max(125, len(idx) // 10)]]
+        pick = np.unique(np.concatenate([rng.choice(idx, 125, replace=False), rng.choice(big, 125, replace=False)]))
+        probes += [("grid", lv, int(i)) for i in pick]
+    gmh = gm.cpu().numpy()
+    cand = np.nonzero(np.abs(gmh) > 1e-4 * np.abs(gmh).max())[0]
+    probes += [("mlp", -1, int(i)) for i in rng.choice(cand, 40, replace=False)]
+    stable, bad, errs = {}, [], {}
+    for kind, lv, i in probes:
+        if kind == "grid":
+            v0, an = float(g.view(-1)[i]), float(gh[i])
+
+            def set_value(v, i=i):
+                g.view(-1)[i] = v
+        else:
+            v0, an = float(m[i]), float(gmh[i])
+
+            def set_value(v, i=i):
+                m[i] = v
+        (d1, s1), (d2, s2), (d4, s4) = (quotient(set_value, v0, h / k) for k in (1, 2, 4))
+        # clear of kinks: the three quotients agree (a kink crossed at distance
+        # x from 0 moves exactly the quotients whose step exceeds x)
+        if max(d1, d2, d4) - min(d1, d2, d4) > 5e-3 * max(abs(d1), abs(an)) + 6 * (s1 + s2 + s4):
+            continue
+        stable[lv] = stable.get(lv, 0) + 1
+        err = abs(d4 - an) / (1e-2 * abs(an) + 6 * s4 + 1e-30)
+        errs.setdefault(lv, []).append(err)
+        if err > 1:
+            bad.append((kind, lv, i, an, d4, d1, s4))
+    torch.cuda.synchronize()
+    nbad = {lv: sum(1 for b in bad if b[1] == lv) for lv in (-1, 0, 1, 2, 3)}
+    q = {lv: tuple(np.round(np.quantile(e, [0.5, 0.9, 1.0]), 3)) for lv, e in errs.items()}
+    print(f"central differences: clear probes per level (-1 = decoder) {stable}, outside the bound {nbad}; "
+          f"error / bound (median, 90 %, max) {q}; outside: {[b for b in bad if b[1] in (-1, 2, 3)][:6]}",
           flush=True)
-    assert near.sum() <= 2
-    sub = _subset(R["host"], rays[~near], pairs)
-    res = {}
-    for name, lams in (("all terms", LAMS), ("no smoothness", LAMS[:5] + (0.0,)),
-                       ("no Eikonal, no smoothness", LAMS[:4] + (0.0, 0.0))):
-        res[name] = e = _gradient_errors(R, sub, lams)
-        print(f"{name}: loss {e['loss'][0]:.6g} vs {e['loss'][1]:.6g}; decoder relative L2 {e['mlp'][0]:.2e}, "
-              f"largest {e['mlp'][1]:.2e} rms; levels "
-              + ", ".join(f"{e[f'level{lv}'][0]:.1e}/{e[f'level{lv}'][1]:.1e}/{e[f'level{lv}'][2]:.3f}"
-                          for lv in range(4)), flush=True)
-    for name, e in res.items():
-        assert abs(e["loss"][0] - e["loss"][1]) <= FWD_TOL * abs(e["loss"][1]), name
-        assert e["untouched_zero"], name
-        assert e["mlp"][0] <= GRAD_TOL, name
-        # per level: the relative L2 bound and at most 1 % of entries beyond
-        # 10x the tolerance (as at the room size); the largest error within
-        # 1e-2 of the level's rms.  At the coarse levels each entry sums every
-        # sample of a 0.24 or 0.96 m cell, and the few that cancel carry the
-        # largest errors (measured: 4e-3 rms at the 0.96 m level, at a
-        # relative L2 of 3e-5)
-        for lv in range(4):
-            rel, largest, far = e[f"level{lv}"]
-            assert rel <= GRAD_TOL and largest <= 1e-2 and far <= 0.01, (name, lv)
+    # The two fine levels and the decoder: most probes clear of kinks, their
+    # median error a small fraction of the bound and at most 10 % of them
+    # outside it (kinks that the three steps do not reveal: the noise
+    # allowance of the agreement test is a worst-case sum, and a decoder
+    # weight reaches every sample of the batch).  A wrong gradient (a lost
+    # term, a wrong scale, a misplaced scatter) puts most probes outside.
+    for lv, n in ((2, 250), (3, 250), (-1, 40)):
+        assert stable.get(lv, 0) >= 0.6 * n, (lv, stable)
+        assert np.median(errs[lv]) <= 0.1, (lv, q)
+        assert nbad[lv] <= max(1, stable[lv] // 10), (lv, nbad, bad)
+    # every entry that no sample or point reaches holds exactly 0
+    mask = np.repeat(_touched_rows(R), 4)
+    off = np.nonzero((gh != 0) & ~mask)[0]
+    if len(off):
+        rows = np.unique(off // 4)
+        lvls = np.searchsorted(np.asarray(L.offsets[1:]), rows, side="right")
+        print(f"{len(off)} entries in {len(rows)} rows nonzero outside the reach of the batch; per level "
+              f"{np.bincount(lvls, minlength=4)}; rows {rows[:8]}; values {gh[off[:8]]}", flush=True)
+        loose = np.repeat(_touched_rows(R, loose=True), 4)
+        print(f"of these, inside the reach of all points with float64 cells and no pair test: "
+              f"{int(loose[off].sum())}", flush=True)
+        _explain_rows(R, rows[:4])
+    assert len(off) == 0
+    untouched = np.nonzero(~mask)[0]
+    print(f"{len(untouched)} untouched grid entries, all exactly 0", flush=True)
+    assert len(untouched) >= 100
+
+
+def test_stress_full_batch_gradient_is_the_sum_of_its_subsets(stress_full):
+    """The loss is a sum over rays and pairs, each weighted by 1/M, 1/|R_d|
+    or 1/S.  So the gradient of the full batch equals the sum of the
+    gradients of 64 disjoint subsets (1024 rays and 16384 pairs each) when
+    subset k's weights are scaled as the full loss weights its terms: by
+    M_k / M for the per-ray means, by |R_d,k| / |R_d| for the depth term and by
+    S_k / S for the smoothness term.  Subsets of this size are checked against
+    the oracle above; the sum checks the full-batch launch (every level of
+    the grid scatter at full contention, the block partials of the decoder
+    gradient and of the LDS-accumulated levels) against them."""
+    R = stress_full
+    G, rec = R["G"], R["rec"]
+    g, m = rec.grid, rec.mlp
+    host = R["host"]
+    M, S = host["o"].shape[0], host["xs"].shape[0]
+    o = G.gosurf_forward(rec.model, g, m, rec.batch, rec.loss_cfg, rec.ws)
+    gg, gm = torch.zeros_like(g), torch.zeros_like(m)
+    G.gosurf_backward(rec.model, g, m, rec.batch, rec.loss_cfg, o, 1.0, gg, gm, rec.ws)
+    nd = float(o.losses[7])
+    rng = np.random.default_rng(9)
+    rays_k = np.array_split(rng.permutation(M), 64)
+    pairs_k = np.array_split(rng.permutation(S), 64)
+    sg, sm = torch.zeros_like(g), torch.zeros_like(m)
+    ws = None
+    for rk, pk in zip(rays_k, pairs_k):
+        rk, pk = np.sort(rk), np.sort(pk)
+        sub = _subset(host, rk, pk)
+        db = G.RayBatch.from_host(sub)
+        nd_k = float(np.sum(host["depth"][rk] > 0))
+        f = len(rk) / M
+        lam = (LAMS[0] * f, LAMS[1] * nd_k / nd, LAMS[2] * f, LAMS[3] * f, LAMS[4] * f, LAMS[5] * len(pk) / S)
+        lc = G.make_loss_cfg(lam)
+        need = G.gosurf_workspace_bytes(rec.model, db.M, db.total, db.S)
+        if ws is None or ws.numel() < need:
+            ws = G.workspace_for(rec.model, db.M, db.total, db.S)
+        ok = G.gosurf_forward(rec.model, g, m, db, lc, ws)
+        G.gosurf_backward(rec.model, g, m, db, lc, ok, 1.0, sg, sm, ws)
+    torch.cuda.synchronize()
+    rel = lambda a, b: float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))  # noqa
+    e_m = rel(gm, sm)
+    print(f"decoder gradient: full batch vs sum of 64 subsets, relative L2 {e_m:.2e}", flush=True)
+    assert e_m <= GRAD_TOL
+    L = R["L"]
+    for lv in range(4):
+        a_, b_ = L.offsets[lv], L.offsets[lv] + int(np.prod(L.dims[lv]))
+        full, parts = gg[a_:b_], sg[a_:b_]
+        e = rel(full, parts)
+        print(f"level {lv}: full batch vs sum of 64 subsets, relative L2 {e:.2e}", flush=True)
+        assert e <= GRAD_TOL, lv
+        # the same entries are reached
+        assert torch.equal(full != 0, parts != 0), lv
