@@ -76,6 +76,7 @@ extern "C" {
 #define GOSURF_MAX_SAMPLES_PER_RAY 256
 #define GOSURF_N_LOSSES 8
 #define GOSURF_PROPOSAL_NUMEL 6851
+#define GOSURF_STATIC_MAX_RAYS 65536
 
 typedef enum {
   GOSURF_OK = 0,
@@ -338,6 +339,22 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
                              const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
                              gosurf_fwd_out* out, void* workspace, size_t workspace_bytes,
                              void* stream);
+
+/* gosurf_forward for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same computation and outputs, with the workspace replaced by a scratch
+   array that the library holds on each GPU it runs on until the process
+   ends (2.1 MB: sized for GOSURF_STATIC_MAX_RAYS rays).  The caller still
+   passes every input and output; nothing is allocated and no workspace
+   argument is taken.  Every call on a GPU uses that GPU's one scratch array,
+   so calls whose work overlaps on one GPU (other threads, other streams)
+   race and must be ordered by the caller; each call writes every scratch
+   entry it reads, so nothing carries over between calls.  The first call on
+   a device looks up the array's device address (device to be current).
+   Errors: as gosurf_forward; SHAPE if M > GOSURF_STATIC_MAX_RAYS. */
+gosurf_status gosurf_forward_static(const gosurf_model* model, const gosurf_params* params,
+                                    const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
+                                    gosurf_fwd_out* out, void* stream);
 
 /* Backward pass: ADDS loss_scale * d(total)/d(params) into grads (loss_scale
    any finite value: a negative one gives the gradient of -scale * total, 0

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "device.h"
 
@@ -289,9 +290,22 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
   return ok();
 }
 
-gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* params, const gosurf_ray_batch* b,
-                             const gosurf_loss_cfg* loss, gosurf_fwd_out* out, void* ws, size_t ws_bytes,
-                             void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The forward's scratch: per-ray loss partials [M][8], the field kernel's
+// per-block smoothness partials [4096] and the block partials of the sums
+// over rays [64][8].  Every entry that is read is written first by the same
+// call, so nothing needs clearing.
+struct FwdScratch {
+  float* ray_partial;
+  float* smooth_partial;
+  float* ray_part;
+};
+
+gosurf_status forward_checks(const gosurf_model* model, const gosurf_params* params, const gosurf_ray_batch* b,
+                             const gosurf_loss_cfg* loss, const gosurf_fwd_out* out) {
   gosurf_status st;
   if ((st = check_model(model)) != GOSURF_OK) return st;
   if ((st = check_params(model, params)) != GOSURF_OK) return st;
@@ -300,11 +314,12 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
   if (!out || !out->rgb_hat || !out->depth_hat || !out->wsum || !out->losses || !out->saved)
     return fail(GOSURF_ERR_NULL, "a forward output array is NULL");
   if (!aligned(out->saved, 16)) return fail(GOSURF_ERR_ALIGN, "out.saved must be 16-byte aligned");
-  const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
-  if (!ws || ws_bytes < w.bytes)
-    return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
-                w.bytes);
-  hipStream_t s = (hipStream_t)stream;
+  return GOSURF_OK;
+}
+
+gosurf_status forward_launch(const gosurf_model* model, const gosurf_params* params, const gosurf_ray_batch* b,
+                             const gosurf_loss_cfg* loss, gosurf_fwd_out* out, const FwdScratch& w, hipStream_t s) {
+  gosurf_status st;
   const gs::Grid g = to_grid(model);
   const bool need_gx = loss->lambda[4] != 0.f;
   float* eik = out->saved + 4 * (size_t)b->total;
@@ -336,6 +351,73 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
                       "loss reduce")) != GOSURF_OK)
     return st;
   return ok();
+}
+
+// ---------------------------------------------------------------- allocation-free forward
+// The scratch of gosurf_forward_static: a file-scope device array, one copy
+// per GPU, sized for GOSURF_STATIC_MAX_RAYS rays.  In host code its name
+// stands for a host-side shadow, so its device address is looked up once per
+// device (hipGetSymbolAddress, with that device current) and only that
+// address is handed to kernels.
+constexpr size_t kStaticRayPartialBytes = (size_t)32 * GOSURF_STATIC_MAX_RAYS;
+constexpr size_t kStaticSmoothBytes = (size_t)4 * 4096;
+constexpr size_t kStaticRayPartBytes = (size_t)4 * 64 * 8;
+constexpr size_t kStaticScratchBytes = kStaticRayPartialBytes + kStaticSmoothBytes + kStaticRayPartBytes;
+static_assert(kStaticRayPartialBytes % 256 == 0 && kStaticSmoothBytes % 256 == 0, "scratch alignment");
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+gosurf_status static_scratch(void** out) {
+  int dev = 0;
+  gosurf_status st;
+  if ((st = hip_check(hipGetDevice(&dev), "hipGetDevice")) != GOSURF_OK) return st;
+  if (dev < 0 || dev >= kMaxDevices) return fail(GOSURF_ERR_VALUE, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if ((st = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "scratch address")) != GOSURF_OK) return st;
+    if (!p) return fail(GOSURF_ERR_HIP, "scratch address: null");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return GOSURF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* params, const gosurf_ray_batch* b,
+                             const gosurf_loss_cfg* loss, gosurf_fwd_out* out, void* ws, size_t ws_bytes,
+                             void* stream) {
+  gosurf_status st;
+  if ((st = forward_checks(model, params, b, loss, out)) != GOSURF_OK) return st;
+  const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
+  if (!ws || ws_bytes < w.bytes)
+    return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                w.bytes);
+  return forward_launch(model, params, b, loss, out, FwdScratch{w.ray_partial, w.smooth_partial, w.ray_part},
+                        (hipStream_t)stream);
+}
+
+gosurf_status gosurf_forward_static(const gosurf_model* model, const gosurf_params* params,
+                                    const gosurf_ray_batch* b, const gosurf_loss_cfg* loss, gosurf_fwd_out* out,
+                                    void* stream) {
+  gosurf_status st;
+  if ((st = forward_checks(model, params, b, loss, out)) != GOSURF_OK) return st;
+  if (b->M > GOSURF_STATIC_MAX_RAYS)
+    return fail(GOSURF_ERR_SHAPE, "gosurf_forward_static: %d rays exceed its scratch of %d rays", b->M,
+                GOSURF_STATIC_MAX_RAYS);
+  void* base = nullptr;
+  if ((st = static_scratch(&base)) != GOSURF_OK) return st;
+  char* c = static_cast<char*>(base);
+  const FwdScratch w{reinterpret_cast<float*>(c), reinterpret_cast<float*>(c + kStaticRayPartialBytes),
+                     reinterpret_cast<float*>(c + kStaticRayPartialBytes + kStaticSmoothBytes)};
+  return forward_launch(model, params, b, loss, out, w, (hipStream_t)stream);
 }
 
 gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* params, const gosurf_ray_batch* b,

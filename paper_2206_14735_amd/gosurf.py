@@ -22,6 +22,7 @@ MLP_NUMEL = 2740
 PROPOSAL_NUMEL = 6851
 N_LOSSES = 8
 MAX_SAMPLES_PER_RAY = 256
+STATIC_MAX_RAYS = 65536       # GOSURF_STATIC_MAX_RAYS: rays of gosurf_forward_static's scratch
 FP32, BF16 = 0, 1
 SPAN_FIXED, SPAN_BOX = 0, 1
 STATUS = {0: "OK", 1: "ERR_NULL", 2: "ERR_SHAPE", 3: "ERR_ALIGN", 4: "ERR_VALUE",
@@ -99,7 +100,7 @@ EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "g
            "gosurf_proposal_forward", "gosurf_proposal_targets", "gosurf_proposal_workspace_bytes",
            "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_workspace_bytes",
            "gosurf_importance_step", "gosurf_importance_sample", "gosurf_lattice_workspace_bytes",
-           "gosurf_sdf_lattice", "gosurf_marching_tetrahedra")
+           "gosurf_sdf_lattice", "gosurf_marching_tetrahedra", "gosurf_forward_static")
 
 _lib = None
 
@@ -120,6 +121,8 @@ def lib():
                                          C.POINTER(RayBatchC), C.c_void_p]
         L.gosurf_forward.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
                                      C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_void_p, C.c_size_t, C.c_void_p]
+        L.gosurf_forward_static.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
+                                            C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_void_p]
         L.gosurf_backward.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
                                       C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_float, C.POINTER(GradsC),
                                       C.c_void_p, C.c_size_t, C.c_void_p]
@@ -154,7 +157,8 @@ def lib():
                   "gosurf_adam_step_checked",
                   "gosurf_refresh_bf16", "gosurf_proposal_forward", "gosurf_proposal_targets",
                   "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_step",
-                  "gosurf_importance_sample", "gosurf_sdf_lattice", "gosurf_marching_tetrahedra"):
+                  "gosurf_importance_sample", "gosurf_sdf_lattice", "gosurf_marching_tetrahedra",
+                  "gosurf_forward_static"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -350,6 +354,18 @@ def gosurf_forward(model, grid, mlp, batch, loss_cfg, workspace, out=None, grid_
     _check("gosurf_forward", lib().gosurf_forward(C.byref(model), C.byref(p), C.byref(bc), C.byref(loss_cfg),
                                                   C.byref(oc), _ptr(workspace), workspace.numel(),
                                                   _stream(stream)))
+    return out
+
+
+def gosurf_forward_static(model, grid, mlp, batch, loss_cfg, out=None, grid_bf16=None, weights=False, stream=None):
+    """gosurf_forward without a workspace: the library's per-GPU scratch array
+    serves instead (at most STATIC_MAX_RAYS rays; calls overlapping on one GPU race)."""
+    if out is None:
+        out = FwdOut.empty(batch.M, batch.total, grid.device, weights)
+    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
+    bc, oc = batch.c(), out.c()
+    _check("gosurf_forward_static", lib().gosurf_forward_static(C.byref(model), C.byref(p), C.byref(bc),
+                                                                C.byref(loss_cfg), C.byref(oc), _stream(stream)))
     return out
 
 
