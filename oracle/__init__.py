@@ -16,4 +16,4 @@ nothing of the HIP library: the two share no code.  The one thing they share
 is the seeded input module ``synth``, which contains no method arithmetic.
 """
 from .philox import philox4x32_10, uniform01  # noqa: F401
-from . import grid, decoder, render, objective, sampler, step, proposal  # noqa: F401
+from . import grid, decoder, render, objective, sampler, step, proposal, pose  # noqa: F401

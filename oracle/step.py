@@ -57,27 +57,33 @@ def _pad(batch):
 
 def _gradient_at(gridv, mlpP, layout, x, x32=None):
     """phi(x), decoder output and d phi/d x with a differentiable graph (x32:
-    the float32 positions that decide each point's cell)."""
-    x = x.detach().requires_grad_(True)
+    the float32 positions that decide each point's cell).  A point that is
+    already a function of other variables (ray origins and directions) stays
+    one, so that the loss differentiates through it."""
+    if not x.requires_grad:
+        x = x.detach().requires_grad_(True)
     z = G.interp_all(gridv, layout, x, x32)
     out = decoder.geometry(z, mlpP)
     gphi, = torch.autograd.grad(out[:, 0].sum(), x, create_graph=True)
     return out, gphi
 
 
-def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=torch.float64):
+def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=torch.float64, ray_grads=False):
     """grid [V, 4], mlp [P] (any float array) -> dict of results (float64).
 
     dtype selects the arithmetic: float64 is the reference; float32 runs the
     same definition in single precision, which measures how much float32
-    rounding alone moves each result (the conditioning of the problem)."""
+    rounding alone moves each result (the conditioning of the problem).
+    ray_grads: also the derivatives of the total with respect to each ray's
+    origin and direction ("grad_o", "grad_r" [M, 3]; the sample points are
+    o + t r, Sec. 3.2), which camera pose refinement needs."""
     gridv = torch.as_tensor(np.asarray(grid), dtype=dtype).clone().requires_grad_(want_grads)
     mlpv = torch.as_tensor(np.asarray(mlp), dtype=dtype).clone().requires_grad_(want_grads)
     P = decoder.unpack(mlpv)
     s = decoder.sharpness(P)
     ray_of, slot, M, N = _pad(batch)
-    o = torch.as_tensor(batch.o, dtype=dtype)
-    r = torch.as_tensor(batch.r, dtype=dtype)
+    o = torch.as_tensor(batch.o, dtype=dtype).clone().requires_grad_(ray_grads)
+    r = torch.as_tensor(batch.r, dtype=dtype).clone().requires_grad_(ray_grads)
     t = torch.as_tensor(batch.t, dtype=dtype)
     depth = torch.as_tensor(batch.depth, dtype=dtype)
     rgb = torch.as_tensor(batch.rgb, dtype=dtype)
@@ -91,6 +97,10 @@ def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=tor
     x32 = G.position_fp32(batch.o[ray_of], batch.t, batch.r[ray_of])
     x = torch.as_tensor(x32, dtype=dtype)
     with torch.enable_grad():
+        if ray_grads:
+            # the value stays the float32 point; the derivative is that of o + t r
+            lin = o[ray_of] + t[:, None] * r[ray_of]
+            x = x + (lin - lin.detach())
         out, gphi = _gradient_at(gridv, P, layout, x, x32)
         phi = out[:, 0]
         col = decoder.colour(out[:, 1:], P)
@@ -145,7 +155,11 @@ def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=tor
             "s": float(s.detach()),
         }
         if want_grads:
-            gg, gm = torch.autograd.grad(loss, [gridv, mlpv])
+            if ray_grads:
+                gg, gm, go, gr = torch.autograd.grad(loss, [gridv, mlpv, o, r])
+                res["grad_o"], res["grad_r"] = go.detach(), gr.detach()
+            else:
+                gg, gm = torch.autograd.grad(loss, [gridv, mlpv])
             res["grad_grid"] = gg.detach()
             res["grad_mlp"] = gm.detach()
     return res
