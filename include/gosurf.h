@@ -214,6 +214,8 @@ typedef struct {
 typedef struct {
   float* grid;          /* [n_vertices][4] */
   float* mlp;           /* [GOSURF_MLP_NUMEL] */
+  float* ray_o;         /* [M][3] dL/d(ray origin), or NULL (camera pose refinement; with ray_r) */
+  float* ray_r;         /* [M][3] dL/d(ray direction), or NULL */
 } gosurf_grads;
 
 typedef struct {
@@ -361,7 +363,11 @@ gosurf_status gosurf_forward_static(const gosurf_model* model, const gosurf_para
    adds zeros).  Must follow the gosurf_forward call that produced `fwd` with
    the same params, batch, loss config and workspace.  Grid gradients are
    accumulated with float32 atomics (summation order varies between runs);
-   decoder gradients are reduced in a fixed order.  A ray holding more than
+   decoder gradients are reduced in a fixed order.  With grads.ray_o and
+   grads.ray_r, the derivatives of the same scaled total with respect to each
+   ray's origin and direction are ADDED there too (sample points o + t r; the
+   Eikonal term contributes through the second derivatives of the
+   interpolation, supplementary Eq. second_sdf_grad_x).  A ray holding more than
    GOSURF_MAX_SAMPLES_PER_RAY samples ends at that many: forward and backward
    treat it as the ray of its first GOSURF_MAX_SAMPLES_PER_RAY samples (the
    rest get weight 0, no loss and no gradient).  Device offsets seg[] beyond
@@ -370,6 +376,35 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
                               const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
                               const gosurf_fwd_out* fwd, float loss_scale, gosurf_grads* grads,
                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Camera pose refinement (Sec. 3, first paragraph, and Sec. 3.5: the poses are
+ * optimised with the grids and decoders; the implementation details give a
+ * pose as a translation t and a rotation nu in so(3), learning rate 5e-4).
+ * Each frame carries a correction pose[t] = (tau, nu) (float32 [T][6], zero
+ * at the start) of its initial camera-to-world pose: R = Exp(nu) R0 and
+ * c = c0 + tau, Exp the exponential map of so(3).  One step with refinement:
+ * gosurf_pose_apply, gosurf_sample_rays on the refined poses (with
+ * out.pixel), gosurf_forward, gosurf_backward with grads.ray_o/ray_r,
+ * gosurf_pose_backward, and gosurf_adam_step on the pose group.  The
+ * smoothness points are inputs of the step and carry no pose gradient.
+ * ------------------------------------------------------------------------- */
+
+/* c2w[t] = [Exp(nu_t) R0_t | c0_t + tau_t; 0 0 0 1] for t < T (row-major
+   [T][4][4], last row copied from c2w0).  Errors: NULL, SHAPE, HIP. */
+gosurf_status gosurf_pose_apply(const float* c2w0, const float* pose, int32_t T, float* c2w, void* stream);
+
+/* ADDS the pose gradient of the rays of a batch to grad_pose [T][6]: ray m of
+   frame f = pixel[m] / HW (pixel as written by gosurf_sample_rays; rays whose
+   index names no frame below T are skipped) contributes dL/do to
+   grad_pose[f][0..2] and J_l(nu_f)^T (r_m x dL/dr) to grad_pose[f][3..5],
+   J_l the left Jacobian of SO(3).  r [M][3] are the batch's ray directions,
+   grad_o and grad_r [M][3] what gosurf_backward accumulated in grads.ray_o
+   and grads.ray_r.  Float32 atomics: the summation order varies.
+   Errors: NULL, SHAPE, HIP. */
+gosurf_status gosurf_pose_backward(const float* pose, int32_t T, const int64_t* pixel, int64_t HW, const float* r,
+                                   const float* grad_o, const float* grad_r, int32_t M, float* grad_pose,
+                                   void* stream);
 
 /* ---------------------------------------------------------------------------
  * Learned proposal sampler.  Not part of the paper: a small network trained

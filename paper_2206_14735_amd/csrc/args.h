@@ -35,6 +35,7 @@ struct FieldArgs {
   float* grad_grid;       // [V][4]
   float* mlp_partial;     // [gridDim.x][kMlpNumel]
   int need_gx;            // ray mode: compute grad phi for the Eikonal term
+  float* grad_x;          // backward, optional: [total][4] dL/dx of each sample (x, y, z, 0)
   const int* seg_end;     // ray mode: device copy of the sample count (seg[M]); total is then a capacity
   // levels whose gradient is accumulated in LDS per block (bit l) and the
   // float offset of each such level inside the block's LDS area

@@ -44,6 +44,11 @@ hipError_t launch_importance_merge(const ImpMergeArgs& a, hipStream_t st);
 hipError_t launch_lattice_rays(const LatticeArgs& a, hipStream_t st);
 hipError_t launch_phi_copy(const float* out4, long long n, float* phi, hipStream_t st);
 hipError_t launch_marching_tets(const MtArgs& a, hipStream_t st);
+hipError_t launch_pose_apply(const float* c2w0, const float* pose, int T, float* c2w, hipStream_t st);
+hipError_t launch_ray_xgrad(const float* dx, const float* t, const int* seg, int M, int total, float* grad_o,
+                            float* grad_r, hipStream_t st);
+hipError_t launch_pose_grad(const float* pose, int T, const long long* pixel, long long HW, const float* r,
+                            const float* grad_o, const float* grad_r, int M, float* grad_pose, hipStream_t st);
 
 }  // namespace gs
 
@@ -430,6 +435,8 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   if ((st = check_loss(loss)) != GOSURF_OK) return st;
   if (!fwd || !fwd->saved || !fwd->losses) return fail(GOSURF_ERR_NULL, "forward outputs are NULL");
   if (!grads || !grads->grid || !grads->mlp) return fail(GOSURF_ERR_NULL, "gradient buffers are NULL");
+  if ((grads->ray_o == nullptr) != (grads->ray_r == nullptr))
+    return fail(GOSURF_ERR_NULL, "grads.ray_o and grads.ray_r are both given or both NULL");
   if (!aligned(grads->grid, 16)) return fail(GOSURF_ERR_ALIGN, "grads.grid must be 16-byte aligned");
   if (!std::isfinite(loss_scale)) return fail(GOSURF_ERR_VALUE, "loss_scale must be finite");
   const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
@@ -455,6 +462,8 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.seed4 = w.seed4; fa.posw = w.posw; fa.need_gx = need_gx;
+  const bool ray_grads = grads->ray_o != nullptr;
+  fa.grad_x = ray_grads ? w.seed4 : nullptr;   // dL/dx per sample replaces the sample's seeds once read
   fa.grad_grid = grads->grid; fa.mlp_partial = w.mlp_partial;
   fa.smooth_coef = b->S > 0 ? 2.f * loss->lambda[5] * loss_scale / (float)b->S : 0.f;
   if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped
@@ -467,6 +476,10 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   if ((st = hip_check(gs::launch_field(fa, true, nb, s), "field bwd")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_FIELD_BWD, false, s);
   if ((st = hip_check(gs::launch_priv_reduce(fa, nb, counts, w.colsum_tmp, s), "level reduce")) != GOSURF_OK)
+    return st;
+  if (ray_grads &&
+      (st = hip_check(gs::launch_ray_xgrad(w.seed4, b->t, b->seg, b->M, b->total, grads->ray_o, grads->ray_r, s),
+                      "ray gradients")) != GOSURF_OK)
     return st;
   if ((st = hip_check(gs::launch_grad_reduce(w.mlp_partial, nb, w.ray_dv, b->M, grads->mlp, w.colsum_tmp,
                                              w.ray_part, s),
@@ -623,6 +636,35 @@ gosurf_status gosurf_adam_step_checked(const gosurf_adam_cfg* c, gosurf_adam_sta
   mark(GOSURF_KERNEL_ADAM, true, h);
   if ((st = hip_check(gs::launch_adam(*c, copy, flag, h), "adam")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_ADAM, false, h);
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- camera pose refinement
+extern "C" {
+
+gosurf_status gosurf_pose_apply(const float* c2w0, const float* pose, int32_t T, float* c2w, void* stream) {
+  if (!c2w0 || !pose || !c2w) return fail(GOSURF_ERR_NULL, "c2w0, pose and c2w must not be NULL");
+  if (T < 1) return fail(GOSURF_ERR_SHAPE, "T = %d < 1", T);
+  gosurf_status st;
+  if ((st = hip_check(gs::launch_pose_apply(c2w0, pose, T, c2w, (hipStream_t)stream), "pose apply")) != GOSURF_OK)
+    return st;
+  return ok();
+}
+
+gosurf_status gosurf_pose_backward(const float* pose, int32_t T, const int64_t* pixel, int64_t HW, const float* r,
+                                   const float* grad_o, const float* grad_r, int32_t M, float* grad_pose,
+                                   void* stream) {
+  if (!pose || !pixel || !r || !grad_o || !grad_r || !grad_pose)
+    return fail(GOSURF_ERR_NULL, "a pose-gradient array is NULL");
+  if (T < 1 || M < 1 || HW < 1) return fail(GOSURF_ERR_SHAPE, "need T, M, HW >= 1 (got %d, %d, %lld)", T, M,
+                                           (long long)HW);
+  gosurf_status st;
+  if ((st = hip_check(gs::launch_pose_grad(pose, T, reinterpret_cast<const long long*>(pixel), HW, r, grad_o,
+                                           grad_r, M, grad_pose, (hipStream_t)stream),
+                      "pose gradient")) != GOSURF_OK)
+    return st;
   return ok();
 }
 

@@ -235,14 +235,15 @@ constexpr int kFieldMaxBlocksFwd = 4096;   // rows of the smoothness partials in
 constexpr int kFieldMaxBlocksBwd = 2048;   // rows of the decoder / level partials in the workspace   // LDS budget for privatised levels (1024 vertices)
 
 // One wave-tile: MODE 0 = 16 ray samples, MODE 1 = 8 smoothness pairs (lanes
-// j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).
-template <int MODE, bool BWD, bool BF, class Smem>
+// j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).  POSE (backward
+// only): also dL/dx of every ray sample, for camera pose refinement.
+template <int MODE, bool BWD, bool BF, bool POSE, class Smem>
 __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, int tile, int total, int lane, int q,
                                            int j, const LevelConst& lc, int po, float* scrA, float* scrB,
                                            const ScatterStage& stage, float* priv,
                                            v4f (&aW1)[2], v4f (&aW2)[4], v4f (&aW3)[2], v4f (&aU1)[2], v4f& aS,
                                            float& smooth_acc) {
-  const bool need_g = (MODE == 1) || A.need_gx;
+  const bool need_g = (MODE == 1) || A.need_gx || POSE;
   // ---------------- sample position
   int item;
   float px, py, pz;
@@ -287,7 +288,9 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
   LevelSample ls;
   locate(A.g, lc, px, py, pz, ls);
   float zl[4], G[4][3];
-  if (need_g) interp<true, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
+  LevelHess hs;   // second derivatives of this level's features (pose refinement)
+  if constexpr (POSE && MODE == 0) interp<true, BF, true>(A.grid, A.grid_bf16, ls, valid, zl, G, &hs);
+  else if (need_g) interp<true, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
   else interp<false, BF>(A.grid, A.grid_bf16, ls, valid, zl, G);
 
   // ---------------- geometry decoder
@@ -402,6 +405,34 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
     for (int b = 0; b < 2; ++b) dh1[b] = relu_mask(dh1[b], h1[b]);
     layer<BF, 1, 2>(sm, T_L1T, dh1, &dz, lane);
 
+    if constexpr (POSE) {
+      // dL/dx = sum over levels and features of dL/dz_k dz_k/dx, plus, through
+      // the Eikonal residual, (d^2 phi/dx^2) dL/d(grad phi) with
+      // d^2 phi/dx^2 = sum_k (df/dz_k) d^2 z_k/dx^2 (the decoder's own second
+      // derivative vanishes for ReLU units; supplementary Eq.
+      // second_sdf_grad_x and the h12, h13, h23 block)
+      float dxv[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dxv[a] = dz[0] * G[0][a] + dz[1] * G[1][a] + dz[2] * G[2][a] + dz[3] * G[3][a];
+      if (A.need_gx) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float ak = ab[k], h12 = hs.h[k][0], h13 = hs.h[k][1], h23 = hs.h[k][2];
+          dxv[0] += ak * (h12 * gv[1] + h13 * gv[2]);
+          dxv[1] += ak * (h12 * gv[0] + h23 * gv[2]);
+          dxv[2] += ak * (h13 * gv[0] + h23 * gv[1]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        dxv[a] += __shfl_xor(dxv[a], 16, 64);
+        dxv[a] += __shfl_xor(dxv[a], 32, 64);
+      }
+      // the seeds of this sample were read at the start of the tile by this wave
+      // alone; their slot takes dL/dx
+      if (q == 0 && live) *reinterpret_cast<float4*>(A.grad_x + 4 * (size_t)item) = make_float4(dxv[0], dxv[1], dxv[2], 0.f);
+    }
+
     // weight gradients (sums over the tile's samples, the MFMA K axis)
     float4 tX[2], tY[2];
     // U2 and c2: U2[c][k] = sum_s dc2[c][s] hc[k][s] goes to column 10 + 3b + c
@@ -515,7 +546,7 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
 // overlap with the ray tiles of other waves.
 // At least two waves per SIMD: the backward kernels then fit 256 registers
 // without spilling, and a second wave hides the gather and atomic latency.
-template <bool BWD, bool BF>
+template <bool BWD, bool BF, bool POSE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void field_kernel(FieldArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   FieldSmem<BF, BWD>& sm = *reinterpret_cast<FieldSmem<BF, BWD>*>(smem_raw);
@@ -575,11 +606,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 
   for (int tile = blockIdx.x * kWavesPerBlock + wave; tile < n_tiles; tile += gridDim.x * kWavesPerBlock) {
     if (tile < n_pair_tiles)
-      field_tile<1, BWD, BF>(A, sm, tile, total, lane, q, j, lc, po, scrA, scrB, stage, priv, aW1, aW2, aW3, aU1,
-                             aS, smooth_acc);
+      field_tile<1, BWD, BF, POSE>(A, sm, tile, total, lane, q, j, lc, po, scrA, scrB, stage, priv, aW1, aW2, aW3,
+                                   aU1, aS, smooth_acc);
     else
-      field_tile<0, BWD, BF>(A, sm, tile - n_pair_tiles, total, lane, q, j, lc, po, scrA, scrB, stage, priv, aW1,
-                             aW2, aW3, aU1, aS, smooth_acc);
+      field_tile<0, BWD, BF, POSE>(A, sm, tile - n_pair_tiles, total, lane, q, j, lc, po, scrA, scrB, stage, priv,
+                                   aW1, aW2, aW3, aU1, aS, smooth_acc);
   }
 
   if constexpr (!BWD) {
@@ -718,7 +749,7 @@ static size_t field_smem(const FieldArgs& a) {
 
 // Blocks that are resident at once on the current device for this kernel and
 // LDS size (CUs x blocks per CU), queried once per (device, kernel, LDS size).
-template <bool BWD, bool BF>
+template <bool BWD, bool BF, bool POSE>
 static int resident_blocks(size_t smem) {
   struct Entry { int dev; size_t smem; int blocks; };
   thread_local Entry cache[8];
@@ -727,7 +758,7 @@ static int resident_blocks(size_t smem) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   for (int i = 0; i < n_cached; ++i)
     if (cache[i].dev == dev && cache[i].smem == smem) return cache[i].blocks;
-  const void* fn = reinterpret_cast<const void*>(&field_kernel<BWD, BF>);
+  const void* fn = reinterpret_cast<const void*>(&field_kernel<BWD, BF, POSE>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 0;
   int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
@@ -746,10 +777,13 @@ int field_grid(const FieldArgs& a, bool bwd) {
   const int tiles = (a.total + 15) / 16 + (a.S + 7) / 8;
   int blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   int resident;
-  if (bwd) resident = bf ? resident_blocks<true, true>(field_smem<true, true>(a))
-                         : resident_blocks<true, false>(field_smem<true, false>(a));
-  else resident = bf ? resident_blocks<false, true>(field_smem<false, true>(a))
-                     : resident_blocks<false, false>(field_smem<false, false>(a));
+  const bool pose = bwd && a.grad_x != nullptr;
+  if (pose) resident = bf ? resident_blocks<true, true, true>(field_smem<true, true>(a))
+                          : resident_blocks<true, false, true>(field_smem<true, false>(a));
+  else if (bwd) resident = bf ? resident_blocks<true, true, false>(field_smem<true, true>(a))
+                              : resident_blocks<true, false, false>(field_smem<true, false>(a));
+  else resident = bf ? resident_blocks<false, true, false>(field_smem<false, true>(a))
+                     : resident_blocks<false, false, false>(field_smem<false, false>(a));
   if (resident <= 0) return 0;
   const int cap = bwd ? kFieldMaxBlocksBwd : kFieldMaxBlocksFwd;
   if (blocks > resident) blocks = resident;
@@ -757,20 +791,23 @@ int field_grid(const FieldArgs& a, bool bwd) {
   return blocks < 1 ? 1 : blocks;
 }
 
-template <bool BWD, bool BF>
+template <bool BWD, bool BF, bool POSE>
 static hipError_t launch_field_t(const FieldArgs& a, int blocks, hipStream_t st) {
   const size_t smem = field_smem<BWD, BF>(a);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<BWD, BF>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<BWD, BF, POSE>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((field_kernel<BWD, BF>), dim3(blocks), dim3(kBlock), smem, st, a);
+  hipLaunchKernelGGL((field_kernel<BWD, BF, POSE>), dim3(blocks), dim3(kBlock), smem, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_field(const FieldArgs& a, bool bwd, int blocks, hipStream_t st) {
   const bool bf = a.grid_bf16 != nullptr;
-  if (bwd) return bf ? launch_field_t<true, true>(a, blocks, st) : launch_field_t<true, false>(a, blocks, st);
-  return bf ? launch_field_t<false, true>(a, blocks, st) : launch_field_t<false, false>(a, blocks, st);
+  if (bwd && a.grad_x)
+    return bf ? launch_field_t<true, true, true>(a, blocks, st) : launch_field_t<true, false, true>(a, blocks, st);
+  if (bwd)
+    return bf ? launch_field_t<true, true, false>(a, blocks, st) : launch_field_t<true, false, false>(a, blocks, st);
+  return bf ? launch_field_t<false, true, false>(a, blocks, st) : launch_field_t<false, false, false>(a, blocks, st);
 }
 
 }  // namespace gs

@@ -65,12 +65,28 @@ __device__ __forceinline__ void locate(const Grid& g, const LevelConst& lc, floa
   ls.inv_v = 1.f / v;
 }
 
-// trilinear value (z) and, optionally, dz/dx (G[k][axis]) of one level
-template <bool NEED_G, bool BF>
+__device__ __forceinline__ float comp(const float4& v, int k) {
+  return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+}
+
+// Off-diagonal second derivatives d^2 z_k / dx_a dx_b of one level (the
+// supplementary's h12, h13, h23; the diagonal is zero), in world units.
+struct LevelHess {
+  float h[4][3];   // [feature][h12, h13, h23]
+};
+
+// trilinear value (z) and, optionally, dz/dx (G[k][axis]) and the second
+// derivatives (H) of one level
+template <bool NEED_G, bool BF, bool NEED_H = false>
 __device__ __forceinline__ void interp(const float* __restrict__ grid, const uint16_t* __restrict__ grid_bf,
-                                       const LevelSample& ls, bool valid, float z[4], float G[4][3]) {
+                                       const LevelSample& ls, bool valid, float z[4], float G[4][3],
+                                       LevelHess* H = nullptr) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) { z[k] = 0.f; G[k][0] = G[k][1] = G[k][2] = 0.f; }
+  if constexpr (NEED_H) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) H->h[k][0] = H->h[k][1] = H->h[k][2] = 0.f;
+  }
   if (!valid) return;
   const float fx = ls.f[0], fy = ls.f[1], fz = ls.f[2];
   float4 th[8];
@@ -108,6 +124,18 @@ __device__ __forceinline__ void interp(const float* __restrict__ grid, const uin
   if (NEED_G) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) { G[k][0] *= ls.inv_v; G[k][1] *= ls.inv_v; G[k][2] *= ls.inv_v; }
+  }
+  if constexpr (NEED_H) {
+    // corner c = 4 bx + 2 by + bz; h12 mixes x and y at the two z faces, etc.
+    const float iv2 = ls.inv_v * ls.inv_v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float t0 = comp(th[0], k), t1 = comp(th[1], k), t2 = comp(th[2], k), t3 = comp(th[3], k);
+      const float t4 = comp(th[4], k), t5 = comp(th[5], k), t6 = comp(th[6], k), t7 = comp(th[7], k);
+      H->h[k][0] = ((1.f - fz) * (t0 + t6 - t2 - t4) + fz * (t1 + t7 - t3 - t5)) * iv2;
+      H->h[k][1] = ((1.f - fy) * (t0 + t5 - t1 - t4) + fy * (t2 + t7 - t3 - t6)) * iv2;
+      H->h[k][2] = ((1.f - fx) * (t0 + t3 - t1 - t2) + fx * (t4 + t7 - t5 - t6)) * iv2;
+    }
   }
 }
 

@@ -80,7 +80,7 @@ class FwdOutC(C.Structure):
 
 
 class GradsC(C.Structure):
-    _fields_ = [("grid", C.c_void_p), ("mlp", C.c_void_p)]
+    _fields_ = [("grid", C.c_void_p), ("mlp", C.c_void_p), ("ray_o", C.c_void_p), ("ray_r", C.c_void_p)]
 
 
 class AdamCfg(C.Structure):
@@ -100,7 +100,8 @@ EXPORTS = ("gosurf_last_error", "gosurf_batch_samples", "gosurf_sample_rays", "g
            "gosurf_proposal_forward", "gosurf_proposal_targets", "gosurf_proposal_workspace_bytes",
            "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_workspace_bytes",
            "gosurf_importance_step", "gosurf_importance_sample", "gosurf_lattice_workspace_bytes",
-           "gosurf_sdf_lattice", "gosurf_marching_tetrahedra", "gosurf_forward_static")
+           "gosurf_sdf_lattice", "gosurf_marching_tetrahedra", "gosurf_forward_static", "gosurf_pose_apply",
+           "gosurf_pose_backward")
 
 _lib = None
 
@@ -121,6 +122,9 @@ def lib():
                                          C.POINTER(RayBatchC), C.c_void_p]
         L.gosurf_forward.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
                                      C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_void_p, C.c_size_t, C.c_void_p]
+        L.gosurf_pose_apply.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.gosurf_pose_backward.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.gosurf_forward_static.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
                                             C.POINTER(LossCfg), C.POINTER(FwdOutC), C.c_void_p]
         L.gosurf_backward.argtypes = [C.POINTER(Model), C.POINTER(Params), C.POINTER(RayBatchC),
@@ -158,7 +162,7 @@ def lib():
                   "gosurf_refresh_bf16", "gosurf_proposal_forward", "gosurf_proposal_targets",
                   "gosurf_proposal_backward", "gosurf_time_kernel", "gosurf_importance_step",
                   "gosurf_importance_sample", "gosurf_sdf_lattice", "gosurf_marching_tetrahedra",
-                  "gosurf_forward_static"):
+                  "gosurf_forward_static", "gosurf_pose_apply", "gosurf_pose_backward"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -370,13 +374,32 @@ def gosurf_forward_static(model, grid, mlp, batch, loss_cfg, out=None, grid_bf16
 
 
 def gosurf_backward(model, grid, mlp, batch, loss_cfg, fwd, loss_scale, grad_grid, grad_mlp, workspace,
-                    grid_bf16=None, stream=None):
+                    grid_bf16=None, stream=None, grad_o=None, grad_r=None):
+    """grad_o, grad_r: optional [M, 3] accumulators of dL/d(ray origin) and dL/d(ray direction)."""
     p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
-    g = GradsC(_ptr(grad_grid, F32), _ptr(grad_mlp, F32))
+    g = GradsC(_ptr(grad_grid, F32), _ptr(grad_mlp, F32), _ptr(grad_o, F32), _ptr(grad_r, F32))
     bc, oc = batch.c(), fwd.c()
     _check("gosurf_backward", lib().gosurf_backward(C.byref(model), C.byref(p), C.byref(bc), C.byref(loss_cfg),
                                                     C.byref(oc), float(loss_scale), C.byref(g),
                                                     _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def gosurf_pose_apply(c2w0, pose, out=None, stream=None):
+    """Refined poses [T, 4, 4]: rotation Exp(nu) R0, centre c0 + tau, pose [T, 6] = (tau, nu)."""
+    T = c2w0.shape[0]
+    if out is None:
+        out = torch.empty_like(c2w0)
+    _check("gosurf_pose_apply", lib().gosurf_pose_apply(_ptr(c2w0, F32), _ptr(pose, F32), T, _ptr(out, F32),
+                                                        _stream(stream)))
+    return out
+
+
+def gosurf_pose_backward(pose, pixel, HW, r, grad_o, grad_r, grad_pose, stream=None):
+    """ADDS the pose gradient of a batch's rays to grad_pose [T, 6]."""
+    _check("gosurf_pose_backward",
+           lib().gosurf_pose_backward(_ptr(pose, F32), pose.shape[0], _ptr(pixel, torch.int64), int(HW), _ptr(r, F32),
+                                      _ptr(grad_o, F32), _ptr(grad_r, F32), r.shape[0], _ptr(grad_pose, F32),
+                                      _stream(stream)))
 
 
 def gosurf_adam_step(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_grad, mlp_m, mlp_v, lr_grid=1e-2,

@@ -45,6 +45,7 @@ class Reconstruction:
         self.lr_grid, self.lr_mlp = lr_grid, lr_mlp
         self.loss_scale = loss_scale
         self.importance = None
+        self.poses = None
         self.it = 0
 
     @classmethod
@@ -57,8 +58,29 @@ class Reconstruction:
             rec.use_importance(w.extra["importance_steps"], w.extra["importance_add"])
         return rec
 
+    def use_pose_refinement(self, lr_pose=5e-4, pose=None):
+        """Optimise a per-frame pose correction (tau, nu) with the field from
+        now on (Adam at lr_pose, 5e-4 in the paper): the rays of each step are
+        drawn from the refined poses, and the backward adds the pose gradient."""
+        import synth
+        T = self.frames.c2w.shape[0]
+        dev = self.device
+        f = self.frames
+        self.c2w0 = f.c2w.clone()
+        # the refined poses get a buffer of their own (the caller's frames keep theirs)
+        self.frames = synth.Frames(f.rgb, f.depth, f.c2w.clone(), f.fx, f.fy, f.cx, f.cy, f.depth_gt)
+        self.poses = (torch.zeros(T, 6, device=dev) if pose is None else pose.to(dev, torch.float32).clone())
+        self.pose_grad = torch.zeros_like(self.poses)
+        self.pose_m = torch.zeros_like(self.poses)
+        self.pose_v = torch.zeros_like(self.poses)
+        self.lr_pose = lr_pose
+        self.ray_go = torch.zeros(self.cfg.M, 3, device=dev)
+        self.ray_gr = torch.zeros(self.cfg.M, 3, device=dev)
+
     def sample(self):
         self.cfg.step = self.it
+        if self.poses is not None:
+            G.gosurf_pose_apply(self.c2w0, self.poses, out=self.frames.c2w)
         if self.importance is None:
             G.gosurf_sample_rays(self.model, self.frames, self.cfg, out=self.batch)
             return
@@ -72,13 +94,28 @@ class Reconstruction:
                                 out=self.fwd, grid_bf16=self.grid_bf16)
 
     def backward(self):
+        if self.poses is None:
+            G.gosurf_backward(self.model, self.grid, self.mlp, self.batch, self.loss_cfg, self.fwd,
+                              self.loss_scale, self.grid_grad, self.mlp_grad, self.ws, grid_bf16=self.grid_bf16)
+            return
+        self.ray_go.zero_()
+        self.ray_gr.zero_()
         G.gosurf_backward(self.model, self.grid, self.mlp, self.batch, self.loss_cfg, self.fwd,
-                          self.loss_scale, self.grid_grad, self.mlp_grad, self.ws, grid_bf16=self.grid_bf16)
+                          self.loss_scale, self.grid_grad, self.mlp_grad, self.ws, grid_bf16=self.grid_bf16,
+                          grad_o=self.ray_go, grad_r=self.ray_gr)
+        T, H, W = self.frames.depth.shape
+        G.gosurf_pose_backward(self.poses, self.batch.pixel, H * W, self.batch.r, self.ray_go, self.ray_gr,
+                               self.pose_grad)
 
     def adam(self):
         G.gosurf_adam_step(self.it + 1, self.grid, self.grid_grad, self.grid_m, self.grid_v, self.mlp,
                            self.mlp_grad, self.mlp_m, self.mlp_v, self.lr_grid, self.lr_mlp,
                            inv_loss_scale=1.0 / self.loss_scale, grid_bf16=self.grid_bf16)
+        if self.poses is not None:
+            # the pose group: no grid entries, the [T, 6] corrections as the second group
+            G.gosurf_adam_step(self.it + 1, None, None, None, None, self.poses.view(-1), self.pose_grad.view(-1),
+                               self.pose_m.view(-1), self.pose_v.view(-1), 0.0, self.lr_pose,
+                               inv_loss_scale=1.0 / self.loss_scale)
 
     def step(self):
         self.sample()

@@ -1,0 +1,209 @@
+"""Camera pose refinement on the device against the FP64 oracle: the refined
+poses, the per-ray origin and direction gradients of the loss (through the
+backward field kernel, including the second-order interpolation block of the
+Eikonal term), the per-frame pose gradient, the whole chain from pose to
+gradient, and a run that recovers perturbed poses."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import synth
+from oracle import pose as OP, step as ostep
+from tests.helpers import (CLAMP_MARGIN, GRAD_TOL, RELU_MARGIN, check_parity, clear_of_kinks, f32_layout,
+                           kink_margins, room_case, sphere_case, subset_batch)
+
+pytestmark = pytest.mark.gpu
+LAMBDAS = (10.0, 1.0, 10.0, 1.0, 1.0, 1.0)
+
+
+def _G():
+    from paper_2206_14735_amd import gosurf as G
+    G.lib()
+    return G
+
+
+def _np(x):
+    return x.double().numpy() if isinstance(x, torch.Tensor) else np.asarray(x, dtype=np.float64)
+
+
+def _random_poses(T, seed):
+    g = np.random.default_rng(seed)
+    c2w0 = np.tile(np.eye(4), (T, 1, 1))
+    c2w0[:, :3, :3] = Rotation.from_rotvec(g.normal(size=(T, 3)) * 0.8).as_matrix()
+    c2w0[:, :3, 3] = g.normal(size=(T, 3)) * 2
+    ang = np.concatenate([[0.0, 1e-9, 1e-4, 0.05, 0.099, 0.101], g.uniform(0, 1.5, T - 6)])
+    ax = g.normal(size=(T, 3))
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    pose = np.concatenate([g.normal(size=(T, 3)) * 0.05, ax * ang[:, None]], 1)
+    return c2w0.astype(np.float32), pose.astype(np.float32)
+
+
+def test_pose_apply_matches_oracle():
+    G = _G()
+    c2w0, pose = _random_poses(37, 1)
+    dev = G.gosurf_pose_apply(torch.from_numpy(c2w0).cuda(), torch.from_numpy(pose).cuda()).cpu().numpy()
+    ref = OP.apply(torch.from_numpy(c2w0).double(), torch.from_numpy(pose).double()).numpy()
+    err = np.abs(dev - ref)
+    assert err[:, :3, :3].max() < 2e-6, err[:, :3, :3].max()          # rotations (entries <= 1)
+    assert err[:, :3, 3].max() < 4e-6 * np.abs(ref[:, :3, 3]).max()
+    assert np.array_equal(dev[:, 3], c2w0[:, 3])
+
+
+def test_pose_backward_matches_oracle():
+    G = _G()
+    T, H, W, M = 29, 6, 8, 5000
+    g = np.random.default_rng(2)
+    _, pose = _random_poses(T, 3)
+    pixel = g.integers(0, T * H * W, M).astype(np.int64)
+    pixel[:3] = [-1, T * H * W, T * H * W + 5]                      # name no frame: skipped
+    r = g.normal(size=(M, 3)).astype(np.float32)
+    go = g.normal(size=(M, 3)).astype(np.float32)
+    gr = g.normal(size=(M, 3)).astype(np.float32)
+    out = torch.zeros(T, 6, device="cuda")
+    c = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    G.gosurf_pose_backward(c(pose), c(pixel), H * W, c(r), c(go), c(gr), out)
+    keep = (pixel >= 0) & (pixel < T * H * W)
+    ref = OP.gradient_from_rays(pose.astype(np.float64), pixel[keep] // (H * W), r[keep], go[keep], gr[keep], T)
+    d = out.cpu().double().numpy()
+    assert np.abs(d - ref.numpy()).max() <= 1e-5 * np.abs(ref.numpy()).max()
+
+
+def _ray_grads_device(L, b, grid, mlp, lambdas=LAMBDAS):
+    G = _G()
+    model = G.make_model(L)
+    db = G.RayBatch.from_host(b)
+    lc = G.make_loss_cfg(lambdas)
+    ws = G.workspace_for(model, db.M, db.total, db.S)
+    g, m = grid.cuda(), mlp.cuda()
+    out = G.gosurf_forward(model, g, m, db, lc, ws)
+    gg, gm = torch.zeros_like(g), torch.zeros_like(m)
+    go, gr = torch.zeros(db.M, 3, device="cuda"), torch.zeros(db.M, 3, device="cuda")
+    G.gosurf_backward(model, g, m, db, lc, out, 1.0, gg, gm, ws, grad_o=go, grad_r=gr)
+    gg2, gm2 = torch.zeros_like(g), torch.zeros_like(m)
+    G.gosurf_backward(model, g, m, db, lc, out, 1.0, gg2, gm2, ws)       # the same call without ray gradients
+    torch.cuda.synchronize()
+    return go.cpu().numpy(), gr.cpu().numpy(), gg.cpu().numpy(), gm.cpu().numpy(), gg2.cpu().numpy(), gm2.cpu().numpy()
+
+
+@pytest.mark.parametrize("case,lambdas", [("sphere", LAMBDAS), ("room", LAMBDAS), ("room", LAMBDAS[:4] + (0.0, 1.0)),
+                                          ("room", (0.0, 0.0, 0.0, 0.0, 1.0, 0.0))])
+def test_ray_gradients_match_oracle(case, lambdas):
+    """dL/do and dL/dr of every ray against the oracle (all terms; without
+    the Eikonal term; the Eikonal term alone, whose x-derivative is the
+    second-order interpolation block), and the grid and decoder gradients of
+    the same call unchanged by computing them."""
+    L, fr, b, grid, mlp = (sphere_case(M=256, S=256, grid_std=0.3) if case == "sphere"
+                           else room_case(M=203, S=301, n_strat=61, n_near=30))
+    b, nr, _ = clear_of_kinks(grid.numpy(), mlp.numpy(), L, b)
+    cfg = ostep.LossCfg(lambdas=lambdas)
+    ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, cfg, ray_grads=True)
+    ref32 = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, cfg, ray_grads=True, dtype=torch.float32)
+    go, gr, gg, gm, gg2, gm2 = _ray_grads_device(L, b, grid, mlp, lambdas)
+    print(f"{case} {lambdas}: {nr} rays at a kink left out", flush=True)
+    check_parity("dL/do", go, _np(ref["grad_o"]), _np(ref32["grad_o"]), GRAD_TOL)
+    check_parity("dL/dr", gr, _np(ref["grad_r"]), _np(ref32["grad_r"]), GRAD_TOL)
+    assert np.array_equal(gm, gm2)
+    assert np.abs(gg - gg2).max() <= 1e-6 * np.abs(gg2).max()          # atomic order only
+
+
+def test_pose_gradient_chain_matches_oracle():
+    """Pose corrections -> refined poses -> sampled rays -> loss -> pose
+    gradient, on the device, against the oracle's reverse mode through the
+    exponential map on the same batch."""
+    G = _G()
+    L = f32_layout(synth.padded_layout((0.0, 0.0, 0.0), (8.0, 6.0, 3.0), (0.03, 0.06, 0.24, 0.96)))
+    T, H, W = 5, 96, 128
+    fr, _ = synth.room_frames(T, H=H, W=W, f=525.0 * W / 640.0, seed=4)
+    grid, mlp = synth.init_params(L, seed=4, grid_std=0.05)
+    g = np.random.default_rng(4)
+    pose = np.concatenate([g.normal(size=(T, 3)) * 0.01, g.normal(size=(T, 3)) * 0.01], 1).astype(np.float32)
+    frd = fr.to("cuda")
+    c2w0 = frd.c2w.clone()
+    posed = torch.from_numpy(pose).cuda()
+    c2w = G.gosurf_pose_apply(c2w0, posed)
+    frp = synth.Frames(frd.rgb, frd.depth, c2w, frd.fx, frd.fy, frd.cx, frd.cy)
+    model = G.make_model(L)
+    M, S = 300, 200
+    cfg = G.SampleCfg(M, 61, 30, G.SPAN_BOX, 0.1, 1e9, 0.1, S, 0.004, 4, 0)
+    db = G.gosurf_sample_rays(model, frp, cfg)
+    host = {k: getattr(db, k).cpu().numpy() for k in ("o", "r", "rgb", "depth", "t", "seg", "xs", "eps", "pixel")}
+    b = ostep.Batch(host["o"], host["r"], host["rgb"], host["depth"], host["t"], host["seg"], host["xs"], host["eps"])
+    relu, clamp, pm = kink_margins(grid.numpy(), mlp.numpy(), L, b)
+    keep = ~((relu < RELU_MARGIN) | (clamp < CLAMP_MARGIN))
+    nr = int((~keep).sum())
+    assert nr <= M // 20
+    b = subset_batch(b, np.nonzero(keep)[0], np.nonzero(pm >= RELU_MARGIN)[0])
+    pixel = host["pixel"][keep]
+    # device chain on the (kink-free) batch
+    dbk = G.RayBatch.from_host(b)
+    dbk.pixel = torch.from_numpy(pixel).cuda()
+    lc = G.make_loss_cfg(LAMBDAS)
+    ws = G.workspace_for(model, dbk.M, dbk.total, dbk.S)
+    gd, md = grid.cuda(), mlp.cuda()
+    out = G.gosurf_forward(model, gd, md, dbk, lc, ws)
+    go, gr = torch.zeros(dbk.M, 3, device="cuda"), torch.zeros(dbk.M, 3, device="cuda")
+    G.gosurf_backward(model, gd, md, dbk, lc, out, 1.0, torch.zeros_like(gd), torch.zeros_like(md), ws,
+                      grad_o=go, grad_r=gr)
+    gpose = torch.zeros(T, 6, device="cuda")
+    G.gosurf_pose_backward(posed, dbk.pixel, H * W, dbk.r, go, gr, gpose)
+    torch.cuda.synchronize()
+    # oracle: ray gradients at the batch's points, then reverse mode through the refined rays
+    frame, dcam = OP.camera_directions(fr, pixel)
+
+    def oracle(dtype):
+        res = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, ray_grads=True, dtype=dtype)
+        pv = torch.tensor(pose, dtype=torch.float64, requires_grad=True)
+        o, r = OP.rays_of(torch.as_tensor(fr.c2w, dtype=torch.float64), pv, frame, dcam)
+        ((o * res["grad_o"].double()).sum() + (r * res["grad_r"].double()).sum()).backward()
+        return pv.grad.numpy()
+
+    print(f"pose chain: {len(pixel)} rays, {nr} left out at a kink", flush=True)
+    check_parity("pose gradient", gpose.cpu().numpy(), oracle(torch.float64), oracle(torch.float32), GRAD_TOL)
+
+
+def _pose_errors(c2w, true):
+    dt = np.linalg.norm(c2w[:, :3, 3] - true[:, :3, 3], axis=1)
+    rel = np.einsum("nij,nkj->nik", c2w[:, :3, :3], true[:, :3, :3])
+    ang = np.arccos(np.clip((np.trace(rel, axis1=1, axis2=2) - 1) / 2, -1, 1))
+    return float(dt.mean()), float(np.degrees(ang).mean())
+
+
+def test_pose_refinement_recovers_perturbed_poses():
+    """The field is trained on the true poses; then every frame's pose is
+    perturbed (2 cm and 0.5 degrees) and the poses alone are optimised (Adam,
+    learning rate 5e-4, the paper's; the field held fixed, so that only the
+    pose gradients act): the refined poses move back towards the true ones."""
+    G = _G()
+    from paper_2206_14735_amd.train import Reconstruction
+    L = f32_layout(synth.padded_layout((0.0, 0.0, 0.0), (8.0, 6.0, 3.0), (0.03, 0.06, 0.24, 0.96)))
+    T, H, W = 12, 120, 160
+    fr, _ = synth.room_frames(T, H=H, W=W, f=525.0 * W / 640.0, seed=6, device="cuda")
+    rec = Reconstruction(L, fr, 64, 32, 8192, 4096, G.SPAN_BOX, 0.1, 1e9, 0.1, seed=6)
+    for _ in range(400):
+        rec.step()
+    g = np.random.default_rng(6)
+    true = fr.c2w.cpu().numpy().astype(np.float64)
+    pert = true.copy()
+    dt = g.normal(size=(T, 3))
+    dt *= 0.02 / np.linalg.norm(dt, axis=1, keepdims=True)
+    dr = g.normal(size=(T, 3))
+    dr *= math.radians(0.5) / np.linalg.norm(dr, axis=1, keepdims=True)
+    for t in range(T):
+        pert[t, :3, :3] = Rotation.from_rotvec(dr[t]).as_matrix() @ true[t, :3, :3]
+        pert[t, :3, 3] += dt[t]
+    fp = synth.Frames(fr.rgb, fr.depth, torch.from_numpy(pert.astype(np.float32)).cuda(), fr.fx, fr.fy, fr.cx, fr.cy)
+    rec.frames = fp
+    rec.use_pose_refinement(lr_pose=5e-4)
+    rec.lr_grid = rec.lr_mlp = 0.0
+    e0 = _pose_errors(pert, true)
+    for _ in range(400):
+        rec.step()
+    G.gosurf_pose_apply(rec.c2w0, rec.poses, out=rec.frames.c2w)
+    torch.cuda.synchronize()
+    e1 = _pose_errors(rec.frames.c2w.cpu().numpy().astype(np.float64), true)
+    print(f"pose error before {e0[0] * 1e3:.2f} mm / {e0[1]:.3f} deg, after {e1[0] * 1e3:.2f} mm / {e1[1]:.3f} deg",
+          flush=True)
+    assert e1[0] < 0.5 * e0[0] and e1[1] < 0.5 * e0[1]
