@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="room")
     ap.add_argument("--frames", type=int, default=None, help="override the number of frames")
+    ap.add_argument("--poses", action="store_true",
+                    help="optimise per-frame camera poses with the field (pose refinement, Adam at 5e-4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=0,
                     help="rays of the oracle baseline's sample (0: the workload's whole batch)")
@@ -418,6 +420,8 @@ def main():
     print(f"# frames ready: {n_frames} x {w.H}x{w.W} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     grid, mlp = synth.init_params(w.layout(), seed=0)
     rec = Reconstruction.from_workload(w, frames, seed=0, grid=grid.clone(), mlp=mlp.clone())
+    if a.poses:
+        rec.use_pose_refinement(lr_pose=5e-4)
 
     t0 = time.time()
     for _ in range(a.warmup):
@@ -563,7 +567,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.M} rays x {sampling}, {w.S} smoothness "
                                f"pairs, grid {'/'.join(str(v) for v in sorted(w.voxels))} m "
-                               f"({n_par / 1e6:.2f} M params), {n_frames} frames {w.W}x{w.H}, {w.precision}",
+                               f"({n_par / 1e6:.2f} M params), {n_frames} frames {w.W}x{w.H}, {w.precision}"
+                               + (", with camera pose refinement" if a.poses else ""),
                    "rays": w.M, "samples_per_ray": spr, "smoothness_pairs": w.S,
                    "grid_params": grid_numel, "frames": n_frames},
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},

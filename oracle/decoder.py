@@ -49,3 +49,39 @@ def colour(g, P):
 def sharpness(P):
     """s = exp(10 v)."""
     return torch.exp(10.0 * P["v"][0])
+
+
+# ---------------------------------------------------------------- the paper's colour path
+# Sec. 3.1, Eq. COLOR_MLP and the architecture details: colour is decoded from
+# a separate colour grid W_beta at the finest level (h_c = 6 features per
+# vertex) and the viewing direction d, by g_gamma with 2 hidden layers of 32:
+# (6 + 3) -> 32 -> 32 -> 3, ReLU hidden, sigmoid output (the output
+# activation, unstated, as for the other decoder).  Packed
+# V1[32][9] e1[32] V2[32][32] e2[32] V3[3][32] e3[3]; inputs ordered as the
+# 6 colour features, then d.
+COLOUR_FEAT = 6
+_COLOUR_LAYOUT = [("V1", (32, 9)), ("e1", (32,)), ("V2", (32, 32)), ("e2", (32,)), ("V3", (3, 32)), ("e3", (3,))]
+
+
+def colour_unpack(vec):
+    out, off = {}, 0
+    for name, shp in _COLOUR_LAYOUT:
+        n = shp[0] * (shp[1] if len(shp) > 1 else 1)
+        out[name] = vec[off:off + n].reshape(shp)
+        off += n
+    if off != vec.numel():
+        raise ValueError(f"packed colour decoder has {vec.numel()} entries, expected {off}")
+    return out
+
+
+def colour_numel():
+    return sum(s[0] * (s[1] if len(s) > 1 else 1) for _, s in _COLOUR_LAYOUT)
+
+
+def colour_from_grid(cf, d, Pc):
+    """g_gamma: colour features cf [..., 6] and viewing directions d [..., 3]
+    (unit length) -> colour [..., 3] in (0, 1)."""
+    x = torch.cat([cf, d], -1)
+    h1 = torch.relu(x @ Pc["V1"].T + Pc["e1"])
+    h2 = torch.relu(h1 @ Pc["V2"].T + Pc["e2"])
+    return torch.sigmoid(h2 @ Pc["V3"].T + Pc["e3"])

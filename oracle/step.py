@@ -68,7 +68,8 @@ def _gradient_at(gridv, mlpP, layout, x, x32=None):
     return out, gphi
 
 
-def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=torch.float64, ray_grads=False):
+def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=torch.float64, ray_grads=False,
+             colour_grid=None, colour_mlp=None):
     """grid [V, 4], mlp [P] (any float array) -> dict of results (float64).
 
     dtype selects the arithmetic: float64 is the reference; float32 runs the
@@ -76,9 +77,19 @@ def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=tor
     rounding alone moves each result (the conditioning of the problem).
     ray_grads: also the derivatives of the total with respect to each ray's
     origin and direction ("grad_o", "grad_r" [M, 3]; the sample points are
-    o + t r, Sec. 3.2), which camera pose refinement needs."""
+    o + t r, Sec. 3.2), which camera pose refinement needs.
+    colour_grid [V_finest, 8] (6 features used) and colour_mlp: the paper's
+    colour path (Eq. COLOR_MLP): colour from the colour grid at the finest
+    level's vertices and the viewing direction r / |r|; the geometry
+    decoder's outputs 1..15 then feed nothing.  Their gradients come back as
+    "grad_colour_grid" and "grad_colour_mlp"."""
     gridv = torch.as_tensor(np.asarray(grid), dtype=dtype).clone().requires_grad_(want_grads)
     mlpv = torch.as_tensor(np.asarray(mlp), dtype=dtype).clone().requires_grad_(want_grads)
+    paper_colour = colour_grid is not None
+    if paper_colour:
+        cgv = torch.as_tensor(np.asarray(colour_grid), dtype=dtype).clone().requires_grad_(want_grads)
+        cmv = torch.as_tensor(np.asarray(colour_mlp), dtype=dtype).clone().requires_grad_(want_grads)
+        Pc = decoder.colour_unpack(cmv)
     P = decoder.unpack(mlpv)
     s = decoder.sharpness(P)
     ray_of, slot, M, N = _pad(batch)
@@ -103,7 +114,13 @@ def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=tor
             x = x + (lin - lin.detach())
         out, gphi = _gradient_at(gridv, P, layout, x, x32)
         phi = out[:, 0]
-        col = decoder.colour(out[:, 1:], P)
+        if paper_colour:
+            lf = layout.n_levels - 1
+            cf = G.interp_level(cgv[:, :decoder.COLOUR_FEAT], x, layout.p0, layout.voxels[lf], layout.dims[lf], x32)
+            rr = r[ray_of]
+            col = decoder.colour_from_grid(cf, rr / rr.norm(dim=-1, keepdim=True), Pc)
+        else:
+            col = decoder.colour(out[:, 1:], P)
 
         def pad(v, fill=0.0):
             shp = (M, N) + tuple(v.shape[1:])
@@ -155,13 +172,16 @@ def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=tor
             "s": float(s.detach()),
         }
         if want_grads:
+            wrt = [gridv, mlpv] + ([o, r] if ray_grads else []) + ([cgv, cmv] if paper_colour else [])
+            gs = list(torch.autograd.grad(loss, wrt, allow_unused=True))
+            gs = [torch.zeros_like(v) if g_ is None else g_ for g_, v in zip(gs, wrt)]
+            res["grad_grid"], res["grad_mlp"] = gs[0].detach(), gs[1].detach()
+            k = 2
             if ray_grads:
-                gg, gm, go, gr = torch.autograd.grad(loss, [gridv, mlpv, o, r])
-                res["grad_o"], res["grad_r"] = go.detach(), gr.detach()
-            else:
-                gg, gm = torch.autograd.grad(loss, [gridv, mlpv])
-            res["grad_grid"] = gg.detach()
-            res["grad_mlp"] = gm.detach()
+                res["grad_o"], res["grad_r"] = gs[2].detach(), gs[3].detach()
+                k = 4
+            if paper_colour:
+                res["grad_colour_grid"], res["grad_colour_mlp"] = gs[k].detach(), gs[k + 1].detach()
     return res
 
 
