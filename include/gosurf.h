@@ -77,6 +77,8 @@ extern "C" {
 #define GOSURF_N_LOSSES 8
 #define GOSURF_PROPOSAL_NUMEL 6851
 #define GOSURF_STATIC_MAX_RAYS 65536
+#define GOSURF_COLOUR_FEAT 6
+#define GOSURF_COLOUR_MLP_NUMEL 1475
 
 typedef enum {
   GOSURF_OK = 0,
@@ -91,6 +93,19 @@ typedef enum {
 
 typedef enum { GOSURF_FP32 = 0, GOSURF_BF16 = 1 } gosurf_precision;
 typedef enum { GOSURF_SPAN_FIXED = 0, GOSURF_SPAN_BOX = 1 } gosurf_span_mode;
+/* Where colour comes from.  DECODED: from the geometry decoder's outputs
+   1..15 through the colour decoder 15-32-3 (the layout below).  GRID: the
+   paper's path (Sec. 3.1, Eq. COLOR_MLP and the architecture details): a
+   colour grid W_beta of GOSURF_COLOUR_FEAT features per vertex of the finest
+   level, stored float32 [V_finest][8] (features 0..5, then two entries that
+   are never read), trilinearly interpolated at the sample and decoded with
+   the viewing direction d = r / |r| by g_gamma: (6 + 3) -> 32 -> 32 -> 3,
+   ReLU hidden, sigmoid output, packed V1[32][9] e1[32] V2[32][32] e2[32]
+   V3[3][32] e3[3] (GOSURF_COLOUR_MLP_NUMEL; inputs: the 6 features, then
+   d).  On the GRID path the geometry decoder's outputs 1..15 and the
+   DECODED colour decoder's parameters feed nothing (zero gradient).  GRID
+   needs precision GOSURF_FP32. */
+typedef enum { GOSURF_COLOUR_DECODED = 0, GOSURF_COLOUR_GRID = 1 } gosurf_colour_mode;
 
 /* Geometry of the grid (see "Grid layout" above). */
 typedef struct {
@@ -101,6 +116,7 @@ typedef struct {
   int64_t offset[GOSURF_LEVELS];      /* first vertex row of each level */
   int64_t n_vertices;                 /* rows of the concatenated table */
   int32_t precision;                  /* gosurf_precision of decoders and grid reads */
+  int32_t colour_mode;                /* gosurf_colour_mode */
 } gosurf_model;
 
 /* Parameters read by forward/backward. */
@@ -108,6 +124,8 @@ typedef struct {
   const float* grid;          /* [n_vertices][4] float32 master features */
   const uint16_t* grid_bf16;  /* [n_vertices][4] bfloat16 mirror; required for GOSURF_BF16 */
   const float* mlp;           /* [GOSURF_MLP_NUMEL] decoder parameters and v */
+  const float* colour_grid;   /* GOSURF_COLOUR_GRID: [V_finest][8], 16-byte aligned; else unused */
+  const float* colour_mlp;    /* GOSURF_COLOUR_GRID: [GOSURF_COLOUR_MLP_NUMEL]; else unused */
 } gosurf_params;
 
 /* An RGB-D sequence {I_t, D_t} with camera-to-world poses (Sec. 3, first para.). */
@@ -216,6 +234,8 @@ typedef struct {
   float* mlp;           /* [GOSURF_MLP_NUMEL] */
   float* ray_o;         /* [M][3] dL/d(ray origin), or NULL (camera pose refinement; with ray_r) */
   float* ray_r;         /* [M][3] dL/d(ray direction), or NULL */
+  float* colour_grid;   /* GOSURF_COLOUR_GRID: [V_finest][8] (entries 6, 7 untouched); else unused */
+  float* colour_mlp;    /* GOSURF_COLOUR_GRID: [GOSURF_COLOUR_MLP_NUMEL]; else unused */
 } gosurf_grads;
 
 typedef struct {

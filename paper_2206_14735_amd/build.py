@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgosurf.so")
 SOURCES = ["capi.hip", "field.hip", "render.hip", "sample.hip", "proposal.hip", "importance.hip", "mesh.hip",
-           "pose.hip"]
+           "pose.hip", "colour.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics", "-fgpu-flush-denormals-to-zero",

@@ -36,6 +36,8 @@ struct FieldArgs {
   float* mlp_partial;     // [gridDim.x][kMlpNumel]
   int need_gx;            // ray mode: compute grad phi for the Eikonal term
   float* grad_x;          // backward, optional: [total][4] dL/dx of each sample (x, y, z, 0)
+  int colour;             // ray mode: 1 = colour from the geometry decoder's features; 0 = no colour
+                          // here (the paper's colour path runs in its own kernel)
   const int* seg_end;     // ray mode: device copy of the sample count (seg[M]); total is then a capacity
   // levels whose gradient is accumulated in LDS per block (bit l) and the
   // float offset of each such level inside the block's LDS area
@@ -43,6 +45,24 @@ struct FieldArgs {
   int priv_off[4];
   int priv_floats;        // floats of the LDS area
   float* priv_partial;    // [gridDim.x][priv_floats] block partials
+};
+
+// the paper's colour path (colour grid at the finest level + view direction)
+struct ColourArgs {
+  Grid g;
+  const float* cgrid;     // [V_finest][8]: 6 features, 2 unused
+  const float* cmlp;      // packed V1 e1 V2 e2 V3 e3
+  const float* o;
+  const float* r;
+  const float* t;
+  const int* ray_of;
+  int total;
+  const int* seg_end;     // device copy of the sample count (seg[M]); total is then a capacity
+  float* out4;            // forward: colour into components 1..3 of [total][4]
+  const float* seed4;     // backward: [total][4] seeds (components 1..3: dL/dc, scaled)
+  const float* posw;      // backward: [total][4] sample positions
+  float* grad_cgrid;      // backward: [V_finest][8]
+  float* partial;         // backward: [gridDim.x][colour decoder size] block partials
 };
 
 struct RenderArgs {

@@ -45,6 +45,9 @@ hipError_t launch_lattice_rays(const LatticeArgs& a, hipStream_t st);
 hipError_t launch_phi_copy(const float* out4, long long n, float* phi, hipStream_t st);
 hipError_t launch_marching_tets(const MtArgs& a, hipStream_t st);
 hipError_t launch_pose_apply(const float* c2w0, const float* pose, int T, float* c2w, hipStream_t st);
+hipError_t launch_colour(const ColourArgs& a, bool bwd, int blocks, hipStream_t st);
+int colour_grid_blocks(int total, bool bwd);
+int colour_numel();
 hipError_t launch_ray_xgrad(const float* dx, const float* t, const int* seg, int M, int total, float* grad_o,
                             float* grad_r, hipStream_t st);
 hipError_t launch_pose_grad(const float* pose, int T, const long long* pixel, long long HW, const float* r,
@@ -92,6 +95,11 @@ gosurf_status check_model(const gosurf_model* m) {
   if (!m) return fail(GOSURF_ERR_NULL, "model is NULL");
   if (m->precision != GOSURF_FP32 && m->precision != GOSURF_BF16)
     return fail(GOSURF_ERR_VALUE, "precision %d is not GOSURF_FP32 or GOSURF_BF16", m->precision);
+  if (m->colour_mode != GOSURF_COLOUR_DECODED && m->colour_mode != GOSURF_COLOUR_GRID)
+    return fail(GOSURF_ERR_VALUE, "colour_mode %d is not GOSURF_COLOUR_DECODED or GOSURF_COLOUR_GRID",
+                m->colour_mode);
+  if (m->colour_mode == GOSURF_COLOUR_GRID && m->precision != GOSURF_FP32)
+    return fail(GOSURF_ERR_VALUE, "the colour-grid path runs in GOSURF_FP32 only");
   long long rows = 0;
   for (int l = 0; l < GOSURF_LEVELS; ++l) {
     if (!(m->voxel[l] > 0.f) || !std::isfinite(m->voxel[l]))
@@ -186,6 +194,11 @@ gosurf_status check_params(const gosurf_model* m, const gosurf_params* p) {
   if (!p) return fail(GOSURF_ERR_NULL, "params is NULL");
   if (!p->grid || !p->mlp) return fail(GOSURF_ERR_NULL, "params.grid / params.mlp is NULL");
   if (!aligned(p->grid, 16)) return fail(GOSURF_ERR_ALIGN, "params.grid must be 16-byte aligned");
+  if (m->colour_mode == GOSURF_COLOUR_GRID) {
+    if (!p->colour_grid || !p->colour_mlp)
+      return fail(GOSURF_ERR_NULL, "params.colour_grid and params.colour_mlp are required for GOSURF_COLOUR_GRID");
+    if (!aligned(p->colour_grid, 16)) return fail(GOSURF_ERR_ALIGN, "params.colour_grid must be 16-byte aligned");
+  }
   if (m->precision == GOSURF_BF16) {
     if (!p->grid_bf16) return fail(GOSURF_ERR_NULL, "params.grid_bf16 is required for GOSURF_BF16");
     if (!aligned(p->grid_bf16, 8)) return fail(GOSURF_ERR_ALIGN, "params.grid_bf16 must be 8-byte aligned");
@@ -336,12 +349,22 @@ gosurf_status forward_launch(const gosurf_model* model, const gosurf_params* par
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
   fa.grad_phi = out->grad_phi; fa.pair_terms = out->pair_terms;
+  fa.colour = model->colour_mode == GOSURF_COLOUR_DECODED;
   if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped
   const int nb = gs::field_grid(fa, false);
   if (nb <= 0) return fail(GOSURF_ERR_HIP, "field grid: the occupancy query failed");
   mark(GOSURF_KERNEL_FIELD_FWD, true, s);
   if ((st = hip_check(gs::launch_field(fa, false, nb, s), "field fwd")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_FIELD_FWD, false, s);
+  if (model->colour_mode == GOSURF_COLOUR_GRID) {
+    gs::ColourArgs ca{};
+    ca.g = g; ca.cgrid = params->colour_grid; ca.cmlp = params->colour_mlp;
+    ca.o = b->o; ca.r = b->r; ca.t = b->t; ca.ray_of = b->ray_of; ca.total = b->total; ca.seg_end = b->seg + b->M;
+    ca.out4 = out->saved;
+    const int cb = gs::colour_grid_blocks(b->total, false);
+    if (cb <= 0) return fail(GOSURF_ERR_HIP, "colour grid: the occupancy query failed");
+    if ((st = hip_check(gs::launch_colour(ca, false, cb, s), "colour fwd")) != GOSURF_OK) return st;
+  }
   const int n_sp = fa.S > 0 ? nb : 0;
   gs::RenderArgs ra{};
   ra.g = g; ra.o = b->o; ra.r = b->r; ra.rgb = b->rgb; ra.depth = b->depth; ra.t = b->t; ra.seg = b->seg;
@@ -435,6 +458,8 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   if ((st = check_loss(loss)) != GOSURF_OK) return st;
   if (!fwd || !fwd->saved || !fwd->losses) return fail(GOSURF_ERR_NULL, "forward outputs are NULL");
   if (!grads || !grads->grid || !grads->mlp) return fail(GOSURF_ERR_NULL, "gradient buffers are NULL");
+  if (model->colour_mode == GOSURF_COLOUR_GRID && (!grads->colour_grid || !grads->colour_mlp))
+    return fail(GOSURF_ERR_NULL, "grads.colour_grid and grads.colour_mlp are required for GOSURF_COLOUR_GRID");
   if ((grads->ray_o == nullptr) != (grads->ray_r == nullptr))
     return fail(GOSURF_ERR_NULL, "grads.ray_o and grads.ray_r are both given or both NULL");
   if (!aligned(grads->grid, 16)) return fail(GOSURF_ERR_ALIGN, "grads.grid must be 16-byte aligned");
@@ -463,7 +488,13 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.seed4 = w.seed4; fa.posw = w.posw; fa.need_gx = need_gx;
   const bool ray_grads = grads->ray_o != nullptr;
-  fa.grad_x = ray_grads ? w.seed4 : nullptr;   // dL/dx per sample replaces the sample's seeds once read
+  const bool cgrid = model->colour_mode == GOSURF_COLOUR_GRID;
+  fa.colour = !cgrid;
+  // dL/dx per sample replaces the sample's seeds once read (the colour kernel,
+  // which also reads the seeds, runs first then)
+  fa.grad_x = ray_grads ? w.seed4 : nullptr;
+  if (cgrid && ray_grads)
+    return fail(GOSURF_ERR_VALUE, "ray gradients (pose refinement) are not built for the colour-grid path");
   fa.grad_grid = grads->grid; fa.mlp_partial = w.mlp_partial;
   fa.smooth_coef = b->S > 0 ? 2.f * loss->lambda[5] * loss_scale / (float)b->S : 0.f;
   if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped
@@ -485,6 +516,21 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
                                              w.ray_part, s),
                       "grad reduce")) != GOSURF_OK)
     return st;
+  if (cgrid) {
+    // the colour path: its own kernel on the colour seeds; its decoder partials
+    // reuse the decoder-partial rows, whose reduction above is already enqueued
+    gs::ColourArgs ca{};
+    ca.g = g; ca.cgrid = params->colour_grid; ca.cmlp = params->colour_mlp;
+    ca.o = b->o; ca.r = b->r; ca.t = b->t; ca.ray_of = b->ray_of; ca.total = b->total; ca.seg_end = b->seg + b->M;
+    ca.seed4 = w.seed4; ca.posw = w.posw; ca.grad_cgrid = grads->colour_grid; ca.partial = w.mlp_partial;
+    const int cb = gs::colour_grid_blocks(b->total, true);
+    if (cb <= 0) return fail(GOSURF_ERR_HIP, "colour grid: the occupancy query failed");
+    if ((st = hip_check(gs::launch_colour(ca, true, cb, s), "colour bwd")) != GOSURF_OK) return st;
+    const int cn = gs::colour_numel();
+    if ((st = hip_check(gs::launch_colsum(w.mlp_partial, cb, cn, w.colsum_tmp, grads->colour_mlp, cn, nullptr, -1, s),
+                        "colour reduce")) != GOSURF_OK)
+      return st;
+  }
   return ok();
 }
 

@@ -311,7 +311,7 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
   for (int r = 0; r < 4; ++r) ob[r] += sm.bias[64 + 4 * q + r];
 
   // ---------------- colour decoder (ray mode)
-  if (MODE == 0) {
+  if (MODE == 0 && A.colour) {
     layer<BF, 2, 1>(sm, T_C1, &ob, hc, lane);
 #pragma unroll
     for (int b = 0; b < 2; ++b)
@@ -320,6 +320,8 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
     layer<BF, 1, 2>(sm, T_C2, hc, &cb, lane);
 #pragma unroll
     for (int r = 0; r < 4; ++r) cb[r] = sigmoidf_(cb[r] + sm.bias[112 + 4 * q + r]);
+  } else {
+    cb = v4f{0.f, 0.f, 0.f, 0.f};
   }
 
   // ---------------- d phi / d x
@@ -384,17 +386,20 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
       gv[0] = c * gx[0]; gv[1] = c * gx[1]; gv[2] = c * gx[2];
     }
     // colour: dL/d(pre-sigmoid) for rows 0..2 held by level-group 0
+    const bool col = A.colour != 0;
     v4f dc2 = v4f{0, 0, 0, 0};
-    if (q == 0) {
+    if (q == 0 && col) {
       dc2[0] = sd.y * cb[0] * (1.f - cb[0]);
       dc2[1] = sd.z * cb[1] * (1.f - cb[1]);
       dc2[2] = sd.w * cb[2] * (1.f - cb[2]);
     }
-    v4f dhc[2], dob;
-    layer<BF, 2, 1>(sm, T_C2T, &dc2, dhc, lane);
+    v4f dhc[2], dob = v4f{0, 0, 0, 0};
+    if (col) {
+      layer<BF, 2, 1>(sm, T_C2T, &dc2, dhc, lane);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) dhc[b] = relu_mask(dhc[b], hc[b]);
-    layer<BF, 1, 2>(sm, T_C1T, dhc, &dob, lane);
+      for (int b = 0; b < 2; ++b) dhc[b] = relu_mask(dhc[b], hc[b]);
+      layer<BF, 1, 2>(sm, T_C1T, dhc, &dob, lane);
+    }
     if (q == 0) dob[0] += sd.x;
     v4f dh2[2], dh1[2], dz;
     layer<BF, 2, 1>(sm, T_L3T, &dob, dh2, lane);
@@ -435,30 +440,32 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
 
     // weight gradients (sums over the tile's samples, the MFMA K axis)
     float4 tX[2], tY[2];
-    // U2 and c2: U2[c][k] = sum_s dc2[c][s] hc[k][s] goes to column 10 + 3b + c
-    // of aS (row k - 16b), with hc as the A operand and dc2 row c as the B
-    // operand of exactly those columns
-    rows_to_lanes<2>(scrA, hc, tX, q, j);
-    rows_to_lanes<1>(scrB, &dc2, tY, q, j);
-    colsum_into(tY[0], 5, aS, j);
-    {
-      const int c = j >= 13 ? j - 13 : (j >= 10 ? j - 10 : 0);
-      const float4 d = *reinterpret_cast<const float4*>(scrB + c * RSR + 4 * q);
+    if (col) {
+      // U2 and c2: U2[c][k] = sum_s dc2[c][s] hc[k][s] goes to column 10 + 3b + c
+      // of aS (row k - 16b), with hc as the A operand and dc2 row c as the B
+      // operand of exactly those columns
+      rows_to_lanes<2>(scrA, hc, tX, q, j);
+      rows_to_lanes<1>(scrB, &dc2, tY, q, j);
+      colsum_into(tY[0], 5, aS, j);
+      {
+        const int c = j >= 13 ? j - 13 : (j >= 10 ? j - 10 : 0);
+        const float4 d = *reinterpret_cast<const float4*>(scrB + c * RSR + 4 * q);
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const bool on = j >= 10 + 3 * b && j < 13 + 3 * b;
-        aS = mfma4(tX[b].x, on ? d.x : 0.f, aS);
-        aS = mfma4(tX[b].y, on ? d.y : 0.f, aS);
-        aS = mfma4(tX[b].z, on ? d.z : 0.f, aS);
-        aS = mfma4(tX[b].w, on ? d.w : 0.f, aS);
+        for (int b = 0; b < 2; ++b) {
+          const bool on = j >= 10 + 3 * b && j < 13 + 3 * b;
+          aS = mfma4(tX[b].x, on ? d.x : 0.f, aS);
+          aS = mfma4(tX[b].y, on ? d.y : 0.f, aS);
+          aS = mfma4(tX[b].z, on ? d.z : 0.f, aS);
+          aS = mfma4(tX[b].w, on ? d.w : 0.f, aS);
+        }
       }
+      // U1 and c1: o-index 0 (phi) does not feed the colour decoder; its
+      // operand row is replaced by ones, so column 0 of aU1 sums dhc (= dc1)
+      rows_to_lanes<2>(scrA, dhc, tX, q, j);
+      rows_to_lanes<1>(scrB, &ob, tY, q, j);
+      if (j == 0) tY[0] = make_float4(1.f, 1.f, 1.f, 1.f);
+      outer_lanes<BF, 2, 1>(tX, tY, aU1);
     }
-    // U1 and c1: o-index 0 (phi) does not feed the colour decoder; its
-    // operand row is replaced by ones, so column 0 of aU1 sums dhc (= dc1)
-    rows_to_lanes<2>(scrA, dhc, tX, q, j);
-    rows_to_lanes<1>(scrB, &ob, tY, q, j);
-    if (j == 0) tY[0] = make_float4(1.f, 1.f, 1.f, 1.f);
-    outer_lanes<BF, 2, 1>(tX, tY, aU1);
     // W3 and b3
     rows_to_lanes<1>(scrA, &dob, tX, q, j);
     rows_to_lanes<2>(scrB, h2, tY, q, j);

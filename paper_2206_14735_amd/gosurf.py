@@ -25,6 +25,8 @@ MAX_SAMPLES_PER_RAY = 256
 STATIC_MAX_RAYS = 65536       # GOSURF_STATIC_MAX_RAYS: rays of gosurf_forward_static's scratch
 FP32, BF16 = 0, 1
 SPAN_FIXED, SPAN_BOX = 0, 1
+COLOUR_DECODED, COLOUR_GRID = 0, 1
+COLOUR_MLP_NUMEL = 1475      # GOSURF_COLOUR_MLP_NUMEL
 STATUS = {0: "OK", 1: "ERR_NULL", 2: "ERR_SHAPE", 3: "ERR_ALIGN", 4: "ERR_VALUE",
           5: "ERR_WORKSPACE", 6: "ERR_HIP", 7: "ERR_NONFINITE"}
 ERR_NONFINITE = 7
@@ -40,11 +42,12 @@ class GosurfError(RuntimeError):
 class Model(C.Structure):
     _fields_ = [("p0", C.c_float * 3), ("p1", C.c_float * 3), ("voxel", C.c_float * LEVELS),
                 ("dims", (C.c_int32 * 3) * LEVELS), ("offset", C.c_int64 * LEVELS),
-                ("n_vertices", C.c_int64), ("precision", C.c_int32)]
+                ("n_vertices", C.c_int64), ("precision", C.c_int32), ("colour_mode", C.c_int32)]
 
 
 class Params(C.Structure):
-    _fields_ = [("grid", C.c_void_p), ("grid_bf16", C.c_void_p), ("mlp", C.c_void_p)]
+    _fields_ = [("grid", C.c_void_p), ("grid_bf16", C.c_void_p), ("mlp", C.c_void_p),
+                ("colour_grid", C.c_void_p), ("colour_mlp", C.c_void_p)]
 
 
 class FramesC(C.Structure):
@@ -80,7 +83,8 @@ class FwdOutC(C.Structure):
 
 
 class GradsC(C.Structure):
-    _fields_ = [("grid", C.c_void_p), ("mlp", C.c_void_p), ("ray_o", C.c_void_p), ("ray_r", C.c_void_p)]
+    _fields_ = [("grid", C.c_void_p), ("mlp", C.c_void_p), ("ray_o", C.c_void_p), ("ray_r", C.c_void_p),
+                ("colour_grid", C.c_void_p), ("colour_mlp", C.c_void_p)]
 
 
 class AdamCfg(C.Structure):
@@ -195,8 +199,9 @@ def _stream(stream):
 
 
 # ---------------------------------------------------------------- descriptors
-def make_model(layout, precision=FP32):
-    """gosurf_model from a synth.GridLayout (levels coarsest first)."""
+def make_model(layout, precision=FP32, colour_mode=0):
+    """gosurf_model from a synth.GridLayout (levels coarsest first); colour_mode
+    COLOUR_DECODED (0) or COLOUR_GRID (1, the paper's colour path)."""
     if layout.n_levels != LEVELS:
         raise ValueError(f"the library implements {LEVELS}-level grids")
     m = Model()
@@ -210,6 +215,7 @@ def make_model(layout, precision=FP32):
         m.offset[l] = layout.offsets[l]
     m.n_vertices = layout.n_vertices
     m.precision = precision
+    m.colour_mode = colour_mode
     return m
 
 
@@ -349,11 +355,11 @@ def gosurf_sample_rays(model, frames, cfg, out=None, stream=None):
 
 
 def gosurf_forward(model, grid, mlp, batch, loss_cfg, workspace, out=None, grid_bf16=None, weights=False,
-                   stream=None, grad_phi=False, terms=False):
+                   stream=None, grad_phi=False, terms=False, colour_grid=None, colour_mlp=None):
     if out is None:
         out = FwdOut.empty(batch.M, batch.total, grid.device, weights,
                            (batch.total + 2 * batch.S) if grad_phi else 0, batch.S if terms else None)
-    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
+    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32), _ptr(colour_grid, F32), _ptr(colour_mlp, F32))
     bc, oc = batch.c(), out.c()
     _check("gosurf_forward", lib().gosurf_forward(C.byref(model), C.byref(p), C.byref(bc), C.byref(loss_cfg),
                                                   C.byref(oc), _ptr(workspace), workspace.numel(),
@@ -361,12 +367,13 @@ def gosurf_forward(model, grid, mlp, batch, loss_cfg, workspace, out=None, grid_
     return out
 
 
-def gosurf_forward_static(model, grid, mlp, batch, loss_cfg, out=None, grid_bf16=None, weights=False, stream=None):
+def gosurf_forward_static(model, grid, mlp, batch, loss_cfg, out=None, grid_bf16=None, weights=False, stream=None,
+                          colour_grid=None, colour_mlp=None):
     """gosurf_forward without a workspace: the library's per-GPU scratch array
     serves instead (at most STATIC_MAX_RAYS rays; calls overlapping on one GPU race)."""
     if out is None:
         out = FwdOut.empty(batch.M, batch.total, grid.device, weights)
-    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
+    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32), _ptr(colour_grid, F32), _ptr(colour_mlp, F32))
     bc, oc = batch.c(), out.c()
     _check("gosurf_forward_static", lib().gosurf_forward_static(C.byref(model), C.byref(p), C.byref(bc),
                                                                 C.byref(loss_cfg), C.byref(oc), _stream(stream)))
@@ -374,10 +381,13 @@ def gosurf_forward_static(model, grid, mlp, batch, loss_cfg, out=None, grid_bf16
 
 
 def gosurf_backward(model, grid, mlp, batch, loss_cfg, fwd, loss_scale, grad_grid, grad_mlp, workspace,
-                    grid_bf16=None, stream=None, grad_o=None, grad_r=None):
-    """grad_o, grad_r: optional [M, 3] accumulators of dL/d(ray origin) and dL/d(ray direction)."""
-    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32))
-    g = GradsC(_ptr(grad_grid, F32), _ptr(grad_mlp, F32), _ptr(grad_o, F32), _ptr(grad_r, F32))
+                    grid_bf16=None, stream=None, grad_o=None, grad_r=None, colour_grid=None, colour_mlp=None,
+                    grad_colour_grid=None, grad_colour_mlp=None):
+    """grad_o, grad_r: optional [M, 3] accumulators of dL/d(ray origin) and dL/d(ray direction).
+    colour_grid, colour_mlp and their gradient accumulators: the colour-grid path."""
+    p = Params(_ptr(grid, F32), _ptr(grid_bf16), _ptr(mlp, F32), _ptr(colour_grid, F32), _ptr(colour_mlp, F32))
+    g = GradsC(_ptr(grad_grid, F32), _ptr(grad_mlp, F32), _ptr(grad_o, F32), _ptr(grad_r, F32),
+               _ptr(grad_colour_grid, F32), _ptr(grad_colour_mlp, F32))
     bc, oc = batch.c(), fwd.c()
     _check("gosurf_backward", lib().gosurf_backward(C.byref(model), C.byref(p), C.byref(bc), C.byref(loss_cfg),
                                                     C.byref(oc), float(loss_scale), C.byref(g),

@@ -22,6 +22,8 @@ MLP_SIZES = [("W1", (32, 16)), ("b1", (32,)), ("W2", (32, 32)), ("b2", (32,)),
              ("U2", (3, 32)), ("c2", (3,)), ("v", (1,))]
 PROPOSAL_SIZES = [("P1", (64, 38)), ("q1", (64,)), ("P2", (64, 64)), ("q2", (64,)),
                   ("P3", (3, 64)), ("q3", (3,))]
+# the colour-grid path's decoder: (6 features + 3 view direction) -> 32 -> 32 -> 3
+COLOUR_SIZES = [("V1", (32, 9)), ("e1", (32,)), ("V2", (32, 32)), ("e2", (32,)), ("V3", (3, 32)), ("e3", (3,))]
 
 
 def _slices(sizes):
@@ -39,6 +41,7 @@ def mlp_slices():
 
 MLP_NUMEL = _slices(MLP_SIZES)[1]
 PROPOSAL_NUMEL = _slices(PROPOSAL_SIZES)[1]
+COLOUR_MLP_NUMEL = _slices(COLOUR_SIZES)[1]
 
 
 def _uniform_fill(sizes, g):
@@ -65,3 +68,14 @@ def init_params(layout, seed=0, grid_std=0.01, v0=0.3):
 def init_proposal(seed=0):
     g = torch.Generator().manual_seed(seed + 90001)
     return _uniform_fill(PROPOSAL_SIZES, g)
+
+
+def init_colour(layout, seed=0, grid_std=0.01):
+    """The colour-grid path's parameters: a colour grid [V_finest, 8] with 6
+    features ~ N(0, grid_std^2) and two zero padding entries per vertex, and
+    its decoder ~ U(+-1/sqrt(fan_in))."""
+    g = torch.Generator().manual_seed(seed + 70001)
+    nv = math.prod(layout.dims[-1])
+    cg = torch.zeros(nv, 8)
+    cg[:, :6] = (torch.randn(nv, 6, generator=g, dtype=torch.float64) * grid_std).float()
+    return cg, _uniform_fill(COLOUR_SIZES, g)

@@ -142,14 +142,32 @@ def _relu_margins(P, z, colour):
     return torch.cat(pre, 1).abs().min(1).values.numpy()
 
 
-def kink_margins(grid, mlp, L, b):
+def _colour_grid_margins(cgrid, cmlp, L, x32):
+    """Smallest |pre-activation| of the colour-grid path's decoder units at
+    float32 points x32 (all rays' samples given with their directions)."""
+    from oracle import decoder as OD, grid as OG
+    cg = torch.as_tensor(np.asarray(cgrid, dtype=np.float64))
+    Pc = OD.colour_unpack(torch.as_tensor(np.asarray(cmlp, dtype=np.float64)))
+    lf = L.n_levels - 1
+    x, d = x32
+    cf = OG.interp_level(cg[:, :OD.COLOUR_FEAT], torch.as_tensor(x, dtype=torch.float64), L.p0, L.voxels[lf],
+                         L.dims[lf], x)
+    inp = torch.cat([cf, torch.as_tensor(d, dtype=torch.float64)], -1)
+    p1 = inp @ Pc["V1"].T + Pc["e1"]
+    p2 = torch.relu(p1) @ Pc["V2"].T + Pc["e2"]
+    return torch.cat([p1, p2], 1).abs().min(1).values.numpy()
+
+
+def kink_margins(grid, mlp, L, b, colour_grid=None, colour_mlp=None):
     """How close each ray and each smoothness pair lies to a kink of the
     method, from float64 oracle values: per ray, the smallest |pre-activation|
     of any ReLU unit of the two decoders at its samples inside the box, and the
     smallest |1 - Phi_s(phi_{i+1}) / Phi_s(phi_i)| over its pairs of consecutive
     samples inside the box (the distance from the max(., 0) clamp of Eq.
     volume_rendering_alpha); per pair, the smallest |pre-activation| of the
-    geometry decoder at its two points.  Returns (relu[M], clamp[M], pair[S])."""
+    geometry decoder at its two points.  With colour_grid and colour_mlp (the
+    paper's colour path) the colour units are those of its decoder.
+    Returns (relu[M], clamp[M], pair[S])."""
     from oracle import decoder as OD, grid as OG, step as OS
     g64 = torch.as_tensor(np.asarray(grid, dtype=np.float64))
     P = OD.unpack(torch.as_tensor(np.asarray(mlp, dtype=np.float64)))
@@ -163,8 +181,12 @@ def kink_margins(grid, mlp, L, b):
     if valid.any():
         xv = torch.as_tensor(x32[valid], dtype=torch.float64)
         z = OG.interp_all(g64, L, xv, x32[valid])
-        pre[valid] = _relu_margins(P, z, True)
+        pre[valid] = _relu_margins(P, z, colour_grid is None)
         phi[valid] = OD.geometry(z, P)[:, 0].numpy()
+        if colour_grid is not None:
+            rr = np.asarray(b.r, np.float64)[ray][valid]
+            d = rr / np.linalg.norm(rr, axis=1, keepdims=True)
+            pre[valid] = np.minimum(pre[valid], _colour_grid_margins(colour_grid, colour_mlp, L, (x32[valid], d)))
     relu, clamp = [], []
     for m in range(len(seg) - 1):
         sl = slice(seg[m], seg[m + 1])
@@ -204,10 +226,10 @@ def subset_batch(b, rays, pairs):
                     np.asarray(b.xs).reshape(-1, 3)[pairs], np.asarray(b.eps).reshape(-1, 3)[pairs])
 
 
-def clear_of_kinks(grid, mlp, L, b, max_frac=0.05):
+def clear_of_kinks(grid, mlp, L, b, max_frac=0.05, colour_grid=None, colour_mlp=None):
     """b without the rays and pairs that lie within float32 reach of a kink
     (see kink_margins); at most max_frac of either may go."""
-    relu, clamp, pm = kink_margins(grid, mlp, L, b)
+    relu, clamp, pm = kink_margins(grid, mlp, L, b, colour_grid, colour_mlp)
     near_r = (relu < RELU_MARGIN) | (clamp < CLAMP_MARGIN)
     near_p = pm < RELU_MARGIN
     M, S = len(relu), len(pm)
