@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--frames", type=int, default=None, help="override the number of frames")
     ap.add_argument("--poses", action="store_true",
                     help="optimise per-frame camera poses with the field (pose refinement, Adam at 5e-4)")
+    ap.add_argument("--colour-grid", action="store_true",
+                    help="the paper's colour path: colour grid at the finest level + view direction, 9-32-32-3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=0,
                     help="rays of the oracle baseline's sample (0: the workload's whole batch)")
@@ -44,9 +46,10 @@ def parse():
                     help="also run one plain 1 GiB device copy (reference for memory counters)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP32 vs BF16 + proposal comparison")
-    ap.add_argument("--compare-phase1", type=int, default=300,
+    ap.add_argument("--compare-seeds", type=int, default=3, help="seeds of the comparison")
+    ap.add_argument("--compare-phase1", type=int, default=600,
                     help="shared plain FP32 steps (65536 rays) before the two continuations")
-    ap.add_argument("--compare-phase2", type=int, default=300, help="steps of each continuation (timed)")
+    ap.add_argument("--compare-phase2", type=int, default=600, help="steps of each continuation (timed)")
     ap.add_argument("--mesh", type=float, default=0.0,
                     help="also extract the surface on a lattice of this spacing (m) after --mesh-train more steps")
     ap.add_argument("--mesh-train", type=int, default=10000,
@@ -134,6 +137,17 @@ def measured_traffic(kernel, workload):
     return entry.get("bytes_per_launch")
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or '' if unreadable."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def cpu_baseline(w, frames_cpu, grid, mlp, n_rays, reps=1):
     """FP64 oracle on a bounded sample of the same workload: `reps` steps,
     each a forward+backward on `n_rays` rays (with the proportional share of
@@ -163,7 +177,7 @@ def cpu_baseline(w, frames_cpu, grid, mlp, n_rays, reps=1):
     t_step = (t_fb * (w.M / n_rays) + t_adam) / reps
     scaled = f", scaled by {w.M}/{n_rays}" if n_rays != w.M else ""
     return {"value": w.M * w.n_samples / t_step, "unit": "ray-samples/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"{reps} step(s) of {n_rays} rays x {w.n_samples} samples + {S} smoothness pairs fwd+bwd "
                       f"over the full grid ({t_fb:.1f} s){scaled}, each with one dense Adam step over all "
                       f"{grid.numel() + mlp.numel()} parameters ({t_adam:.1f} s in all)"}
@@ -235,19 +249,28 @@ def mesh_measure(a, G, rec, w, scene, frames, torch):
             "reconstruction": quality}
 
 
+def subset_frames(synth, fr, idx):
+    """The frames `idx` of a sequence (device tensors)."""
+    return synth.Frames(fr.rgb[idx].contiguous(), fr.depth[idx].contiguous(), fr.c2w[idx].contiguous(), fr.fx, fr.fy,
+                        fr.cx, fr.cy, None if fr.depth_gt is None else fr.depth_gt[idx].contiguous())
+
+
 def compare(a, G, synth, Reconstruction, torch):
     """Plain FP32 against BF16 + learned proposal on the proposal workload
     (65536 rays per step, 2000 frames).
 
-    Protocol: plain FP32 steps train the field (phase 1); about 49k rays'
-    weight distributions are logged from it and the proposal is trained on
-    them; then the same state continues for the same number of steps once
-    with plain FP32 steps and once with BF16 + proposal steps (confident rays:
-    24 samples in the predicted interval, the others the plain 64 + 32).
-    Reported: iterations/s of the two continuations, the depth error of the
-    two resulting fields rendered by the same plain FP32 renderer (the
-    reconstruction error the proposal adds), and the depth error of the
-    proposal-sampled render itself."""
+    Every 50th frame (40 of 2000) is held out: the training steps draw rays
+    from the other 1960, and depth errors are measured on the held-out frames
+    against their noise-free depth.  Per seed: plain FP32 steps train the
+    field (phase 1); about 49k rays' weight distributions are logged from it
+    and the proposal is trained on them; then the same state continues for
+    the same number of steps once with plain FP32 steps and once with BF16 +
+    proposal steps (confident rays: 24 samples in the predicted interval, the
+    others the plain 64 + 32).  Reported per seed and summarised over the
+    seeds: iterations/s of the two continuations, the held-out depth error
+    of the two resulting fields rendered by the same plain FP32 renderer (the
+    reconstruction error the proposal adds), and the held-out depth error of
+    the proposal-sampled render itself."""
     from paper_2206_14735_amd.proposal import ProposalLog, ProposalTrainer
     wp = synth.configs.ROOM_PROPOSAL
     lay = wp.layout()
@@ -260,10 +283,18 @@ def compare(a, G, synth, Reconstruction, torch):
     cover_tol = wp.extra["cover_tol"]
     span = G.SPAN_BOX
     t0 = time.time()
-    frames, _ = synth.room_frames(wp.n_frames, H=wp.H, W=wp.W, f=wp.f, seed=1, device="cuda")
+    frames_all, _ = synth.room_frames(wp.n_frames, H=wp.H, W=wp.W, f=wp.f, seed=1, device="cuda")
+    T = wp.n_frames
+    held_idx = torch.arange(0, T, 50, device="cuda")
+    keep = torch.ones(T, dtype=torch.bool, device="cuda")
+    keep[held_idx] = False
+    frames = subset_frames(synth, frames_all, torch.nonzero(keep)[:, 0])
+    held = subset_frames(synth, frames_all, held_idx)
+    del frames_all
     torch.cuda.synchronize()
-    print(f"# compare: {wp.n_frames} frames in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
-    dgt = frames.depth_gt.reshape(-1)
+    print(f"# compare: {T} frames in {time.time() - t0:.1f} s ({len(held_idx)} held out)", file=sys.stderr,
+          flush=True)
+    dgt = held.depth_gt.reshape(-1)
 
     def new_rec(bf16, seed, src=None):
         rec = Reconstruction(lay, frames, 64, 32, M, S, span, wp.near, wp.far, wp.trunc, seed=seed,
@@ -277,60 +308,6 @@ def compare(a, G, synth, Reconstruction, torch):
             if bf16:
                 G.gosurf_refresh_bf16(rec.grid, rec.grid_bf16)
         return rec
-
-    # phase 1: plain FP32 training
-    base = new_rec(False, 0)
-    t0 = time.time()
-    for _ in range(a.compare_phase1):
-        base.step()
-    torch.cuda.synchronize()
-    print(f"# compare: phase 1, {a.compare_phase1} plain steps in {time.time() - t0:.1f} s, losses "
-          f"{base.losses()}", file=sys.stderr, flush=True)
-
-    # proposal: log weights of plain forwards, train on the device
-    logger = Reconstruction(lay, frames, 64, 32, 4096, 0, span, wp.near, wp.far, wp.trunc, seed=7,
-                            grid=base.grid, mlp=base.mlp)
-    log = ProposalLog()
-    for k in range(12):
-        logger.it = 50_000 + k
-        logger.sample()
-        log.add(logger, widen=0.05)
-    del logger
-    trainer = ProposalTrainer(base.model, base.cfg, synth.init_proposal(1), lr=3e-3, batch=8192,
-                              cover_tol=cover_tol)
-    t0 = time.time()
-    ploss = trainer.fit(base.grid, log, steps=12000)
-    torch.cuda.synchronize()
-    n_logged = log.tensors()[0].shape[0]
-    print(f"# compare: proposal trained on {n_logged} rays in {time.time() - t0:.1f} s (loss {ploss:.4f})",
-          file=sys.stderr, flush=True)
-
-    evaluator = Reconstruction(lay, frames, 64, 32, M, 0, span, wp.near, wp.far, wp.trunc, seed=11,
-                               grid=base.grid, mlp=base.mlp)
-
-    def depth_error(grid, mlp, proposal=None, n_batches=4):
-        """Rendered depth against the noise-free depth on rays with observed depth."""
-        evaluator.grid, evaluator.mlp = grid, mlp
-        evaluator.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr, n_free=n_free,
-                               depth_check=depth_check, depth_extend=depth_extend)
-        errs, spr, conf, net_conf = [], [], [], []
-        for k in range(n_batches):
-            evaluator.it = 300_000 + k
-            evaluator.sample()
-            evaluator.forward()
-            ok = evaluator.batch.depth > 0
-            errs.append((evaluator.fwd.depth_hat[ok] - dgt[evaluator.batch.pixel][ok]).abs())
-            spr.append(evaluator.batch.n_samples() / M)
-            if proposal is not None:
-                conf.append((evaluator.batch.prop[:, 2] >= thr).float().mean().item())
-                net_conf.append((evaluator.batch.prop[:, 2].abs() >= thr).float().mean().item())
-        e = torch.cat(errs)
-        out = {"depth_l1_mm": {"mean": round(1e3 * e.mean().item(), 3), "median": round(1e3 * e.median().item(), 3)},
-               "samples_per_ray": round(sum(spr) / len(spr), 2)}
-        if conf:
-            out["confident_fraction"] = round(sum(conf) / len(conf), 4)
-            out["network_confident_fraction"] = round(sum(net_conf) / len(net_conf), 4)
-        return out
 
     def run(rec, steps):
         for _ in range(3):
@@ -365,36 +342,109 @@ def compare(a, G, synth, Reconstruction, torch):
                 acc[nm] += ev[i].elapsed_time(ev[i + 1]) / n
         return ms, {k: round(v, 4) for k, v in acc.items()}, spr / n
 
-    res = {}
-    for name, bf16, prop in (("plain_fp32", False, None), ("bf16_proposal", True, trainer.prop)):
-        rec = new_rec(bf16, 3, base)
-        if prop is not None:
-            rec.use_proposal(prop, n_proposal=n_prop, conf_threshold=thr, n_free=n_free, depth_check=depth_check,
-                             depth_extend=depth_extend)
+    def one_seed(seed):
+        base = new_rec(False, seed)
         t0 = time.time()
-        ms, per_call, spr = run(rec, a.compare_phase2)
-        r = {"ms_per_step": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2), "per_call_ms": per_call,
-             "samples_per_ray": round(spr, 2), "ray_samples_per_s": round(M * spr / (ms * 1e-3)),
-             "plain_equivalent_ray_samples_per_s": round(M * 96 / (ms * 1e-3)),
-             "field": depth_error(rec.grid, rec.mlp)}
-        if prop is not None:
-            r["proposal_render"] = depth_error(rec.grid, rec.mlp, prop)
-        res[name] = r
-        print(f"# compare {name}: {r} ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
-        del rec
-        torch.cuda.empty_cache()
-    p, b = res["plain_fp32"], res["bf16_proposal"]
-    fp, fb = p["field"]["depth_l1_mm"], b["field"]["depth_l1_mm"]
+        for _ in range(a.compare_phase1):
+            base.step()
+        torch.cuda.synchronize()
+        print(f"# compare seed {seed}: phase 1, {a.compare_phase1} plain steps in {time.time() - t0:.1f} s, "
+              f"losses {base.losses()}", file=sys.stderr, flush=True)
+        # proposal: log weights of plain forwards on the training frames, train on the device
+        logger = Reconstruction(lay, frames, 64, 32, 4096, 0, span, wp.near, wp.far, wp.trunc, seed=7 + 100 * seed,
+                                grid=base.grid, mlp=base.mlp)
+        log = ProposalLog()
+        for k in range(12):
+            logger.it = 50_000 + k
+            logger.sample()
+            log.add(logger, widen=0.05)
+        del logger
+        trainer = ProposalTrainer(base.model, base.cfg, synth.init_proposal(1 + seed), lr=3e-3, batch=8192,
+                                  cover_tol=cover_tol)
+        t0 = time.time()
+        ploss = trainer.fit(base.grid, log, steps=12000)
+        torch.cuda.synchronize()
+        n_logged = log.tensors()[0].shape[0]
+        print(f"# compare seed {seed}: proposal trained on {n_logged} rays in {time.time() - t0:.1f} s "
+              f"(loss {ploss:.4f})", file=sys.stderr, flush=True)
+        evaluator = Reconstruction(lay, held, 64, 32, M, 0, span, wp.near, wp.far, wp.trunc, seed=11 + 100 * seed,
+                                   grid=base.grid, mlp=base.mlp)
+
+        def depth_error(grid, mlp, proposal=None, n_batches=4):
+            """Rendered depth against the noise-free depth of the held-out frames, on rays with observed depth."""
+            evaluator.grid, evaluator.mlp = grid, mlp
+            evaluator.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr, n_free=n_free,
+                                   depth_check=depth_check, depth_extend=depth_extend)
+            errs, spr, conf, net_conf = [], [], [], []
+            for k in range(n_batches):
+                evaluator.it = 300_000 + k
+                evaluator.sample()
+                evaluator.forward()
+                ok = evaluator.batch.depth > 0
+                errs.append((evaluator.fwd.depth_hat[ok] - dgt[evaluator.batch.pixel][ok]).abs())
+                spr.append(evaluator.batch.n_samples() / M)
+                if proposal is not None:
+                    conf.append((evaluator.batch.prop[:, 2] >= thr).float().mean().item())
+                    net_conf.append((evaluator.batch.prop[:, 2].abs() >= thr).float().mean().item())
+            e = torch.cat(errs)
+            out = {"depth_l1_mm": {"mean": round(1e3 * e.mean().item(), 3),
+                                   "median": round(1e3 * e.median().item(), 3),
+                                   "p90": round(1e3 * torch.quantile(e, 0.9).item(), 3)},
+                   "samples_per_ray": round(sum(spr) / len(spr), 2)}
+            if conf:
+                out["confident_fraction"] = round(sum(conf) / len(conf), 4)
+                out["network_confident_fraction"] = round(sum(net_conf) / len(net_conf), 4)
+            return out
+
+        res = {}
+        for name, bf16, prop in (("plain_fp32", False, None), ("bf16_proposal", True, trainer.prop)):
+            rec = new_rec(bf16, 3 + seed, base)
+            if prop is not None:
+                rec.use_proposal(prop, n_proposal=n_prop, conf_threshold=thr, n_free=n_free, depth_check=depth_check,
+                                 depth_extend=depth_extend)
+            t0 = time.time()
+            ms, per_call, spr = run(rec, a.compare_phase2)
+            r = {"ms_per_step": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2), "per_call_ms": per_call,
+                 "samples_per_ray": round(spr, 2), "ray_samples_per_s": round(M * spr / (ms * 1e-3)),
+                 "plain_equivalent_ray_samples_per_s": round(M * 96 / (ms * 1e-3)),
+                 "field": depth_error(rec.grid, rec.mlp)}
+            if prop is not None:
+                r["proposal_render"] = depth_error(rec.grid, rec.mlp, prop)
+            res[name] = r
+            print(f"# compare seed {seed} {name}: {r} ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+            del rec
+            torch.cuda.empty_cache()
+        p, b = res["plain_fp32"], res["bf16_proposal"]
+        fp, fb = p["field"]["depth_l1_mm"], b["field"]["depth_l1_mm"]
+        res["iterations_speedup"] = round(p["ms_per_step"] / b["ms_per_step"], 3)
+        res["field_depth_l1_gap_mm"] = {k: round(fb[k] - fp[k], 3) for k in ("mean", "median", "p90")}
+        res["n_logged"] = n_logged
+        return res
+
+    seeds = [one_seed(k) for k in range(a.compare_seeds)]
+
+    def summary(get):
+        v = [get(r) for r in seeds]
+        return {"mean": round(sum(v) / len(v), 3), "min": round(min(v), 3), "max": round(max(v), 3)}
+
     return {
         "workload": f"{wp.name}: {M} rays per step, plain 64+32 vs proposal {n_prop} in the interval + "
                     f"{n_free} on the free space before it per confident ray (confidence >= {thr}"
                     f"{f' and the observed depth within {depth_extend} m of the interval (stretched to it)' if depth_check else ''}, else plain "
-                    f"64+32), {S} smoothness pairs, {wp.n_frames} frames "
-                    f"{wp.W}x{wp.H}; {a.compare_phase1} shared plain steps, then {a.compare_phase2} steps of "
-                    f"each; proposal trained for 12000 steps on {n_logged} logged rays",
-        **res,
-        "iterations_speedup": round(p["ms_per_step"] / b["ms_per_step"], 3),
-        "field_depth_l1_gap_mm": {k: round(fb[k] - fp[k], 3) for k in ("mean", "median")},
+                    f"64+32), {S} smoothness pairs, {T} frames {wp.W}x{wp.H} of which every 50th is held out "
+                    f"for the depth error; per seed {a.compare_phase1} shared plain steps, then "
+                    f"{a.compare_phase2} steps of each; proposal trained for 12000 steps on "
+                    f"{seeds[0]['n_logged']} logged rays; {a.compare_seeds} seeds",
+        "plain_fp32": seeds[0]["plain_fp32"],
+        "bf16_proposal": seeds[0]["bf16_proposal"],
+        "iterations_speedup": summary(lambda r: r["iterations_speedup"]),
+        "field_depth_l1_gap_mm": {k: summary(lambda r, k=k: r["field_depth_l1_gap_mm"][k])
+                                  for k in ("mean", "median", "p90")},
+        "held_out_depth_l1_mm": {
+            "plain_field": summary(lambda r: r["plain_fp32"]["field"]["depth_l1_mm"]["mean"]),
+            "proposal_trained_field": summary(lambda r: r["bf16_proposal"]["field"]["depth_l1_mm"]["mean"]),
+            "proposal_render": summary(lambda r: r["bf16_proposal"]["proposal_render"]["depth_l1_mm"]["mean"])},
+        "seeds": [{k: v for k, v in r.items() if k != "n_logged"} for r in seeds],
     }
 
 
@@ -422,6 +472,8 @@ def main():
     rec = Reconstruction.from_workload(w, frames, seed=0, grid=grid.clone(), mlp=mlp.clone())
     if a.poses:
         rec.use_pose_refinement(lr_pose=5e-4)
+    if a.colour_grid:
+        rec.use_colour_grid(seed=0)
 
     t0 = time.time()
     for _ in range(a.warmup):
@@ -430,17 +482,26 @@ def main():
     print(f"# warmup done ({a.warmup} steps, {time.time() - t0:.2f} s), losses {rec.losses()}", file=sys.stderr,
           flush=True)
 
-    # timed region: K whole steps
+    # timed region: K whole steps, with an event between consecutive steps on
+    # the launch stream for the distribution of single-step times
+    st = torch.cuda.current_stream()
+    step_ev = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps + 1)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    step_ev[0].record(st)
+    for k in range(a.steps):
         rec.step()
+        step_ev[k + 1].record(st)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = 1e3 * dt / a.steps
-    print(f"# timed {a.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    step_ms = sorted(step_ev[k].elapsed_time(step_ev[k + 1]) for k in range(a.steps))
+    q = lambda f: step_ms[min(len(step_ms) - 1, int(round(f * (len(step_ms) - 1))))]  # noqa: E731
+    step_dist = {"median": round(q(0.5), 4), "p10": round(q(0.1), 4), "p90": round(q(0.9), 4), "steps": a.steps}
+    print(f"# timed {a.steps} steps: {ms:.3f} ms/step (median {step_dist['median']}, p10 {step_dist['p10']}, "
+          f"p90 {step_dist['p90']})", file=sys.stderr, flush=True)
 
     # per-call breakdown with HIP events on the launch stream (separate pass)
-    st = torch.cuda.current_stream()
     names = ["sample_rays", "forward", "backward", "adam_step"]
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(a.steps)]
     for k in range(a.steps):
@@ -477,7 +538,7 @@ def main():
         kern[name] = sum(x.elapsed_time(y) for x, y in pairs) / len(pairs)
     print(f"# per kernel (ms): {kern}", file=sys.stderr, flush=True)
 
-    n_par = rec.grid.numel() + rec.mlp.numel()
+    n_par = rec.grid.numel() + rec.mlp.numel() + (0 if rec.cgrid is None else rec.cgrid.numel() + rec.cmlp.numel())
     losses = rec.losses()
     grid_numel = rec.grid.numel()
     samples_now = rec.batch.n_samples()
@@ -532,6 +593,9 @@ def main():
     if "importance_steps" in w.extra and not a.no_cpu_baseline:
         # the oracle baseline covers the stratified step; this workload's step also samples by importance
         print("# oracle baseline: not run for the importance-sampling workload", file=sys.stderr, flush=True)
+    elif a.poses or a.colour_grid:
+        print("# oracle baseline: not run with --poses or --colour-grid (it times the plain step)", file=sys.stderr,
+              flush=True)
     elif not a.no_cpu_baseline:
         fr_cpu = synth.Frames(frames.rgb.cpu(), frames.depth.cpu(), frames.c2w.cpu(), frames.fx, frames.fy,
                               frames.cx, frames.cy)
@@ -562,13 +626,15 @@ def main():
     out = {
         "metric": "ray-samples/s per fwd+bwd step, plain FP32 vs BF16+proposal at equal depth L1",
         "value": samples / (ms * 1e-3), "unit": "ray-samples/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms, "iterations_per_s": 1e3 / ms, "higher_is_better": True,
+        "warmup": a.warmup, "ms_per_step": ms, "step_ms": step_dist, "iterations_per_s": 1e3 / ms,
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if w.precision == "fp32" else "bf16",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.M} rays x {sampling}, {w.S} smoothness "
                                f"pairs, grid {'/'.join(str(v) for v in sorted(w.voxels))} m "
                                f"({n_par / 1e6:.2f} M params), {n_frames} frames {w.W}x{w.H}, {w.precision}"
-                               + (", with camera pose refinement" if a.poses else ""),
+                               + (", with camera pose refinement" if a.poses else "")
+                               + (", colour from the colour grid (the paper's colour path)" if a.colour_grid else ""),
                    "rays": w.M, "samples_per_ray": spr, "smoothness_pairs": w.S,
                    "grid_params": grid_numel, "frames": n_frames},
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},

@@ -264,10 +264,11 @@ typedef enum {
   GOSURF_KERNEL_ADAM = 4           /* the dense Adam kernel of gosurf_adam_step */
 } gosurf_kernel_id;
 
-/* Measurement hook (this thread only): while set, every launch of `kernel` is
+/* Measurement hook (this thread only): the next launch of `kernel` is
    bracketed by hipEventRecord(start) and hipEventRecord(stop) on the launch
-   stream; start/stop are caller-created hipEvent_t handles.  kernel =
-   GOSURF_KERNEL_NONE (or NULL events) clears it.  Errors: VALUE. */
+   stream, after which the hook clears itself; start/stop are caller-created
+   hipEvent_t handles.  kernel = GOSURF_KERNEL_NONE (or NULL events) clears
+   it.  Errors: VALUE. */
 gosurf_status gosurf_time_kernel(int32_t kernel, void* start_event, void* stop_event);
 
 /* Thread-local description of the last error on this thread ("" if none). */

@@ -65,9 +65,13 @@ thread_local char g_err[512];
 thread_local int g_timed_kernel = GOSURF_KERNEL_NONE;
 thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
+// One shot: the first launch of the named kernel after gosurf_time_kernel is
+// bracketed, later launches are not (a step may launch a kernel more than once,
+// e.g. Adam once per parameter group).
 void mark(int kernel, bool start, hipStream_t s) {
   if (kernel != g_timed_kernel || !g_ev_start || !g_ev_stop) return;
   hipEventRecord(start ? g_ev_start : g_ev_stop, s);
+  if (!start) g_timed_kernel = GOSURF_KERNEL_NONE;
 }
 
 gosurf_status fail(gosurf_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));

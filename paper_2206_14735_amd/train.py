@@ -46,6 +46,7 @@ class Reconstruction:
         self.loss_scale = loss_scale
         self.importance = None
         self.poses = None
+        self.cgrid = None
         self.it = 0
 
     @classmethod
@@ -77,6 +78,24 @@ class Reconstruction:
         self.ray_go = torch.zeros(self.cfg.M, 3, device=dev)
         self.ray_gr = torch.zeros(self.cfg.M, 3, device=dev)
 
+    def use_colour_grid(self, seed=0, grid_std=0.01):
+        """The paper's colour path from now on: colour from a colour grid at the
+        finest level and the viewing direction (its own parameters, gradients
+        and Adam moments; learning rates as the grid's and the decoders')."""
+        import synth
+        if self.poses is not None:
+            raise ValueError("pose refinement is not built for the colour-grid path")
+        cg, cm = synth.init_colour(self.layout, seed=seed, grid_std=grid_std)
+        self.model = G.make_model(self.layout, self.model.precision, colour_mode=G.COLOUR_GRID)
+        self.cgrid = cg.to(self.device).contiguous()
+        self.cmlp = cm.to(self.device).contiguous()
+        self.cgrid_grad, self.cmlp_grad = torch.zeros_like(self.cgrid), torch.zeros_like(self.cmlp)
+        self.cgrid_m, self.cgrid_v = torch.zeros_like(self.cgrid), torch.zeros_like(self.cgrid)
+        self.cmlp_m, self.cmlp_v = torch.zeros_like(self.cmlp), torch.zeros_like(self.cmlp)
+
+    def _colour_kw(self):
+        return {} if self.cgrid is None else dict(colour_grid=self.cgrid, colour_mlp=self.cmlp)
+
     def sample(self):
         self.cfg.step = self.it
         if self.poses is not None:
@@ -91,12 +110,14 @@ class Reconstruction:
 
     def forward(self):
         return G.gosurf_forward(self.model, self.grid, self.mlp, self.batch, self.loss_cfg, self.ws,
-                                out=self.fwd, grid_bf16=self.grid_bf16)
+                                out=self.fwd, grid_bf16=self.grid_bf16, **self._colour_kw())
 
     def backward(self):
         if self.poses is None:
+            kw = {} if self.cgrid is None else dict(grad_colour_grid=self.cgrid_grad, grad_colour_mlp=self.cmlp_grad)
             G.gosurf_backward(self.model, self.grid, self.mlp, self.batch, self.loss_cfg, self.fwd,
-                              self.loss_scale, self.grid_grad, self.mlp_grad, self.ws, grid_bf16=self.grid_bf16)
+                              self.loss_scale, self.grid_grad, self.mlp_grad, self.ws, grid_bf16=self.grid_bf16,
+                              **self._colour_kw(), **kw)
             return
         self.ray_go.zero_()
         self.ray_gr.zero_()
@@ -111,6 +132,11 @@ class Reconstruction:
         G.gosurf_adam_step(self.it + 1, self.grid, self.grid_grad, self.grid_m, self.grid_v, self.mlp,
                            self.mlp_grad, self.mlp_m, self.mlp_v, self.lr_grid, self.lr_mlp,
                            inv_loss_scale=1.0 / self.loss_scale, grid_bf16=self.grid_bf16)
+        if self.cgrid is not None:
+            # the colour grid with the grids' rate, its decoder with the decoders'
+            G.gosurf_adam_step(self.it + 1, self.cgrid.view(-1), self.cgrid_grad.view(-1), self.cgrid_m.view(-1),
+                               self.cgrid_v.view(-1), self.cmlp, self.cmlp_grad, self.cmlp_m, self.cmlp_v,
+                               self.lr_grid, self.lr_mlp, inv_loss_scale=1.0 / self.loss_scale)
         if self.poses is not None:
             # the pose group: no grid entries, the [T, 6] corrections as the second group
             G.gosurf_adam_step(self.it + 1, None, None, None, None, self.poses.view(-1), self.pose_grad.view(-1),
