@@ -130,9 +130,8 @@ def measured_traffic(kernel, workload):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    data = json.load(open(path))
-    entry = data.get(kernel)
-    if not entry or entry.get("source_digest") != source_digest() or entry.get("workload") != workload:
+    entry = json.load(open(path)).get(f"{kernel}@{workload}")
+    if not entry or entry.get("source_digest") != source_digest():
         return None
     return entry.get("bytes_per_launch")
 
