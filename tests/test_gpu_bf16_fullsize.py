@@ -1,0 +1,210 @@
+"""The BF16 precision variant at its full size, on a trained field: the room
+at 65536 rays x (64 + 32) samples and 16384 smoothness pairs, decoders on
+bf16 MFMA with float32 accumulation, grid reads from the bf16 mirror, loss
+scale 2^10.  The field is first trained for 500 steps in this configuration
+(the grid is then far from its flat initialisation: surfaces are sharp, so
+opacities no longer hinge on tiny SDF differences).  Then:
+
+* the forward of one whole batch in the benchmark's launch configuration,
+  against the FP64 oracle on the float32 masters, on a 1/64 sample of its
+  rays (rays are independent): SDF, colour, rendered colour and depth;
+* the gradients of a 1/64 subset of a batch (1024 rays, 256 pairs) over the
+  full grid, per level, and the decoder gradient, against three references:
+  the oracle on the float32 masters; the oracle on the masters rounded as
+  the device reads them (grid features and decoder weight matrices to bf16,
+  biases and the sharpness in float32), which leaves only the rounding of
+  the activations; and the FP32 kernels on the same subset.
+
+At a trained field the batch gradient is a small residual of large per-sample
+contributions, while rounding the parameters to bf16 moves the whole function
+by about 1e-3: against the masters the gradient then changes by a sizeable
+fraction of itself, although each sample's contribution is accurate.  The
+second reference separates that shift from the arithmetic.
+
+The bounds are about twice the errors measured on MI355X, and the measured
+values are printed.  They state the precision cost of the variant, not a
+parity claim: the FP32 path carries the parity tests."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import step as ostep
+from tests.helpers import f32_layout, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TRAIN_STEPS = 500
+
+# relative L2 against the FP64 oracle, and depth errors in millimetres
+# About twice the largest error measured on MI355X over three trainings and
+# three subsets each (relative L2 against the FP64 oracle; depth in mm).
+BOUNDS = {"phi": 5e-3, "colour": 3e-3, "c_hat": 2.5e-3, "d_hat": 1e-3, "depth_mm_median": 1.0,
+          "depth_mm_p90": 2.0,
+          "total": 3e-2, "grad_grid_0": 0.8, "grad_grid_1": 0.8, "grad_grid_2": 0.8, "grad_grid_3": 0.8,
+          "q_total": 1.2e-2, "q_grad_grid_0": 0.6, "q_grad_grid_1": 0.6, "q_grad_grid_2": 0.6, "q_grad_grid_3": 0.6}
+# The decoder gradient is the smallest residual (every sample feeds it): its
+# relative L2 error reached 0.83 against the masters and 0.69 against the
+# rounded masters, so it is bounded by the angle instead (1 - cos at twice the
+# largest measured).
+COS_BOUND = {"grad_mlp": 0.37, "grad_grid_0": 0.83, "grad_grid_1": 0.83, "grad_grid_2": 0.83,
+             "grad_grid_3": 0.83,
+             "q_grad_mlp": 0.46, "q_grad_grid_0": 0.94, "q_grad_grid_1": 0.94, "q_grad_grid_2": 0.94,
+             "q_grad_grid_3": 0.94}
+MATRICES = ("W1", "W2", "W3", "U1", "U2")
+
+
+def _bf16(x):
+    return torch.as_tensor(x).float().to(torch.bfloat16).double()
+
+
+def _rounded_as_read(grid, mlp):
+    """The masters as the BF16 kernels read them: grid features and decoder
+    weight matrices rounded to bf16 (nearest even), biases and v kept."""
+    mq = mlp.double().clone()
+    for name, (off, shp) in synth.mlp_slices().items():
+        if name in MATRICES:
+            n = int(np.prod(shp))
+            mq[off:off + n] = _bf16(mlp[off:off + n])
+    return _bf16(grid).numpy(), mq.numpy()
+
+
+def train_c3(seed=7):
+    """The room field trained for TRAIN_STEPS BF16 steps, then the forward of
+    a fresh full batch."""
+    from paper_2206_14735_amd import gosurf as G
+    from paper_2206_14735_amd.train import Reconstruction
+    G.lib()
+    w = synth.configs.ROOM_BF16
+    fr, _ = synth.room_frames(200, H=w.H, W=w.W, f=w.f, seed=seed, device="cuda")
+    rec = Reconstruction.from_workload(w, fr, seed=seed)
+    assert rec.model.precision == G.BF16 and rec.loss_scale == 1024.0
+    for _ in range(TRAIN_STEPS):
+        rec.step()
+    rec.sample()
+    out = G.gosurf_forward(rec.model, rec.grid, rec.mlp, rec.batch, rec.loss_cfg, rec.ws, grid_bf16=rec.grid_bf16)
+    torch.cuda.synchronize()
+    b = rec.batch
+    host = {k: getattr(b, k).cpu().numpy() for k in ("o", "r", "rgb", "depth", "t", "seg", "xs", "eps")}
+    print(f"C3 batch after {TRAIN_STEPS} steps: {b.M} rays, {b.total} samples, {b.S} pairs, "
+          f"losses {rec.losses()}", flush=True)
+    return dict(G=G, w=w, L=f32_layout(w.layout()), rec=rec, out=out, host=host,
+                grid=rec.grid.cpu(), mlp=rec.mlp.cpu())
+
+
+@pytest.fixture(scope="module")
+def c3_trained():
+    return train_c3()
+
+
+def _subset(host, rays, pairs):
+    seg = host["seg"]
+    ts = [host["t"][seg[m]:seg[m + 1]] for m in rays]
+    lens = np.array([len(t) for t in ts])
+    return ostep.Batch(host["o"][rays], host["r"][rays], host["rgb"][rays], host["depth"][rays],
+                       np.concatenate(ts).astype(np.float32),
+                       np.concatenate([[0], np.cumsum(lens)]).astype(np.int32),
+                       host["xs"][pairs].reshape(-1, 3), host["eps"][pairs].reshape(-1, 3))
+
+
+def _check(errors):
+    for k, v in errors.items():
+        assert v <= BOUNDS[k], (k, v, BOUNDS[k])
+
+
+def test_c3_forward_on_a_trained_field(c3_trained):
+    R = c3_trained
+    rng = np.random.default_rng(8)
+    M = R["host"]["o"].shape[0]
+    rays = np.sort(rng.choice(M, M // 64, replace=False))
+    sub = _subset(R["host"], rays, np.zeros(0, dtype=np.int64))
+    ref = ostep.evaluate(R["grid"].double().numpy(), R["mlp"].double().numpy(), R["L"], sub, want_grads=False)
+    out, seg = R["out"], R["host"]["seg"]
+    phi, col = out.sample_values(int(seg[-1]))
+    phi, col = phi.cpu().numpy(), col.cpu().numpy()
+    idx = np.concatenate([np.arange(seg[m], seg[m + 1]) for m in rays])
+    v = ref["valid"].numpy()
+    d_dev = out.depth_hat.cpu().numpy()[rays].astype(np.float64)
+    d_ref = ref["d_hat"].numpy()
+    has_depth = R["host"]["depth"][rays] > 0
+    err_mm = 1e3 * np.abs(d_dev - d_ref)[has_depth]
+    e = {"phi": rel_l2(phi[idx][v], ref["phi"].numpy()[v]),
+            "colour": rel_l2(col[idx][v], ref["col"].numpy()[v]),
+            "c_hat": rel_l2(out.rgb_hat.cpu().numpy()[rays], ref["c_hat"].numpy()),
+            "d_hat": rel_l2(d_dev, d_ref),
+            "depth_mm_median": float(np.median(err_mm)),
+            "depth_mm_p90": float(np.percentile(err_mm, 90))}
+    print("C3 forward errors", json.dumps({k: float(f"{v:.3g}") for k, v in e.items()}), flush=True)
+    _check(e)
+
+
+def gradient_errors(R, seed):
+    """Errors of the BF16 gradients of one 1/64 subset against the oracle on
+    the masters, against the oracle on the masters rounded as read (prefix
+    q_), and of the FP32 kernels (prefix fp32_) beside the oracle's own
+    float32 evaluation (prefix o32_: the conditioning of the subset)."""
+    G, rec = R["G"], R["rec"]
+    rng = np.random.default_rng(seed)
+    M, S = R["host"]["o"].shape[0], R["host"]["xs"].shape[0]
+    rays = np.sort(rng.choice(M, M // 64, replace=False))
+    pairs = np.sort(rng.choice(S, S // 64, replace=False))
+    sub = _subset(R["host"], rays, pairs)
+    db = G.RayBatch.from_host(sub)
+    ws = G.workspace_for(rec.model, db.M, db.total, db.S)
+    o = G.gosurf_forward(rec.model, rec.grid, rec.mlp, db, rec.loss_cfg, ws, grid_bf16=rec.grid_bf16)
+    gg, gm = torch.zeros_like(rec.grid), torch.zeros_like(rec.mlp)
+    G.gosurf_backward(rec.model, rec.grid, rec.mlp, db, rec.loss_cfg, o, rec.loss_scale, gg, gm, ws,
+                      grid_bf16=rec.grid_bf16)
+    m32 = G.make_model(R["L"], G.FP32)
+    ws32 = G.workspace_for(m32, db.M, db.total, db.S)
+    o32 = G.gosurf_forward(m32, rec.grid, rec.mlp, db, rec.loss_cfg, ws32)
+    g32, gm32 = torch.zeros_like(rec.grid), torch.zeros_like(rec.mlp)
+    G.gosurf_backward(m32, rec.grid, rec.mlp, db, rec.loss_cfg, o32, 1.0, g32, gm32, ws32)
+    torch.cuda.synchronize()
+    cfg = ostep.LossCfg(R["w"].lambdas)
+    g64, m64 = R["grid"].double().numpy(), R["mlp"].double().numpy()
+    ref = ostep.evaluate(g64, m64, R["L"], sub, cfg)
+    ref32 = ostep.evaluate(g64, m64, R["L"], sub, cfg, dtype=torch.float32)
+    gq, mq = _rounded_as_read(R["grid"], R["mlp"])
+    ref_q = ostep.evaluate(gq, mq, R["L"], sub, cfg)
+    dg = (gg / rec.loss_scale).cpu().numpy()
+    dm = (gm / rec.loss_scale).cpu().numpy()
+    L = R["L"]
+    e, cos = {}, {}
+    for tag, r, dgx, dmx, tot in (("", ref, dg, dm, float(o.losses[6])), ("q_", ref_q, dg, dm, float(o.losses[6])),
+                                  ("fp32_", ref, g32.cpu().numpy(), gm32.cpu().numpy(), None),
+                                  ("o32_", ref, _np(ref32["grad_grid"]), _np(ref32["grad_mlp"]), None)):
+        if tot is not None:
+            e[tag + "total"] = abs(tot - r["total"]) / abs(r["total"])
+        rm = r["grad_mlp"].numpy()
+        e[tag + "grad_mlp"] = rel_l2(dmx, rm)
+        cos[tag + "grad_mlp"] = float(dmx @ rm / (np.linalg.norm(dmx) * np.linalg.norm(rm)))
+        rg = r["grad_grid"].numpy()
+        for lv in range(4):
+            a_, b_ = L.offsets[lv], L.offsets[lv] + int(np.prod(L.dims[lv]))
+            t = rg[a_:b_] != 0
+            x, y = dgx[a_:b_][t], rg[a_:b_][t]
+            e[f"{tag}grad_grid_{lv}"] = rel_l2(x, y)
+            cos[f"{tag}grad_grid_{lv}"] = float(x @ y / (np.linalg.norm(x) * np.linalg.norm(y)))
+    return e, cos
+
+
+def _np(x):
+    return x.double().numpy() if isinstance(x, torch.Tensor) else np.asarray(x, dtype=np.float64)
+
+
+def test_c3_gradients_on_a_trained_field(c3_trained):
+    for seed in (9, 10, 11):
+        e, cos = gradient_errors(c3_trained, seed)
+        print(f"subset {seed}: C3 gradient errors", json.dumps({k: float(f"{v:.3g}") for k, v in e.items()}),
+              flush=True)
+        print(f"subset {seed}: C3 gradient cosines", json.dumps({k: float(f"{v:.4g}") for k, v in cos.items()}),
+              flush=True)
+        # the FP32 kernels: as close to the oracle as the oracle's own float32 evaluation
+        for k in [k for k in e if k.startswith("fp32_")]:
+            assert e[k] <= max(1e-4, 3 * e["o32_" + k[5:]]), (k, e[k], e["o32_" + k[5:]])
+        for k in COS_BOUND:
+            assert cos[k] >= COS_BOUND[k], (k, cos[k], COS_BOUND[k])
+        _check({k: v for k, v in e.items() if k in BOUNDS})
