@@ -38,6 +38,8 @@ def parse():
                     help="optimise per-frame camera poses with the field (pose refinement, Adam at 5e-4)")
     ap.add_argument("--colour-grid", action="store_true",
                     help="the paper's colour path: colour grid at the finest level + view direction, 9-32-32-3")
+    ap.add_argument("--grad-copies", action="store_true",
+                    help="the backward scatters the large levels into x/y-parity gradient copies")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=0,
                     help="rays of the oracle baseline's sample (0: the workload's whole batch)")
@@ -468,7 +470,8 @@ def main():
     torch.cuda.synchronize()
     print(f"# frames ready: {n_frames} x {w.H}x{w.W} in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     grid, mlp = synth.init_params(w.layout(), seed=0)
-    rec = Reconstruction.from_workload(w, frames, seed=0, grid=grid.clone(), mlp=mlp.clone())
+    rec = Reconstruction.from_workload(w, frames, seed=0, grid=grid.clone(), mlp=mlp.clone(),
+                                       grad_copies=a.grad_copies)
     if a.poses:
         rec.use_pose_refinement(lr_pose=5e-4)
     if a.colour_grid:
@@ -544,7 +547,7 @@ def main():
 
     def roofline(name, bytes_per_launch, ms, label):
         gbs = bytes_per_launch / (ms * 1e-3) / 1e9
-        traffic = measured_traffic(name, w.name)
+        traffic = measured_traffic(name, w.name + ("+copies" if a.grad_copies else ""))
         return {"kernel": label, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": bytes_per_launch, "ms_per_launch": round(ms, 4)}
@@ -569,7 +572,7 @@ def main():
         flops = per_sample * samples_now + per_pair * pairs
         tfs = flops / (kern[k] * 1e-3) / 1e12
         peak = MFMA_PEAK_TFLOPS[w.precision]
-        issued, busy = measured_mfma(k, w.name)
+        issued, busy = measured_mfma(k, w.name + ("+copies" if a.grad_copies else ""))
         return {"kernel": label, "bound": "mfma", "achieved": round(tfs, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(tfs / peak, 4), "algorithmic_flops_per_launch": flops, "issued_flops_per_launch": issued,
                 "mfma_busy": busy, "ms_per_launch": round(kern[k], 4)}
@@ -633,7 +636,8 @@ def main():
                                f"pairs, grid {'/'.join(str(v) for v in sorted(w.voxels))} m "
                                f"({n_par / 1e6:.2f} M params), {n_frames} frames {w.W}x{w.H}, {w.precision}"
                                + (", with camera pose refinement" if a.poses else "")
-                               + (", colour from the colour grid (the paper's colour path)" if a.colour_grid else ""),
+                               + (", colour from the colour grid (the paper's colour path)" if a.colour_grid else "")
+                               + (", gradient copies" if a.grad_copies else ""),
                    "rays": w.M, "samples_per_ray": spr, "smoothness_pairs": w.S,
                    "grid_params": grid_numel, "frames": n_frames},
         "per_call_ms": {k: round(v, 4) for k, v in per.items()},

@@ -117,6 +117,10 @@ typedef struct {
   int64_t n_vertices;                 /* rows of the concatenated table */
   int32_t precision;                  /* gosurf_precision of decoders and grid reads */
   int32_t colour_mode;                /* gosurf_colour_mode */
+  int32_t grad_copies;                /* 0: the backward scatters into grads->grid; 1: it scatters the
+                                         levels it does not accumulate on chip into four gradient copies
+                                         in the workspace and adds them into grads->grid before it
+                                         returns (see gosurf_backward) */
 } gosurf_model;
 
 /* Parameters read by forward/backward. */
@@ -297,7 +301,12 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
                                  const gosurf_sample_cfg* cfg, gosurf_ray_batch* out,
                                  void* stream);
 
-/* Workspace bytes needed by forward/backward for a batch of these sizes. */
+/* Workspace bytes needed by forward/backward for a batch of these sizes.  With
+   model->grad_copies = 1 this includes the gradient copies, about 64 bytes
+   per vertex of every level the backward does not accumulate on chip (levels
+   are accumulated on chip, coarsest first, while their vertices add up to at
+   most 1024).
+   Returns 0 for negative sizes or a model the copies cannot serve. */
 size_t gosurf_workspace_bytes(const gosurf_model* model, int32_t M, int32_t total, int32_t S);
 
 /* Hierarchical importance sampling (Sec. 3.2, last paragraph: starting from
@@ -392,7 +401,18 @@ gosurf_status gosurf_forward_static(const gosurf_model* model, const gosurf_para
    GOSURF_MAX_SAMPLES_PER_RAY samples ends at that many: forward and backward
    treat it as the ray of its first GOSURF_MAX_SAMPLES_PER_RAY samples (the
    rest get weight 0, no loss and no gradient).  Device offsets seg[] beyond
-   `total` are clamped to it.  Errors: NULL, SHAPE, VALUE, WORKSPACE, HIP. */
+   `total` are clamped to it.
+   Gradient copies (model->grad_copies = 1): grid-gradient atomics are
+   processed per aligned 64-byte chunk, and in the grid layout a sample's eight
+   corners span about five.  With copies, the levels not accumulated on chip
+   are scattered into four copies held in the workspace, one per parity of the
+   cell's (x, y) index, laid out so a cell's four corners at one z are one
+   aligned 64-byte unit (two chunks per sample and level).  The backward zeroes
+   the copies first and adds them into grads->grid before it returns, so the
+   result is the same gradient up to the order of float32 additions.  It needs
+   each such level to have at most 2048 x 2048 x 512 vertices and all copies
+   to fit 2^31 floats (else VALUE).
+   Errors: NULL, SHAPE, VALUE, WORKSPACE, HIP. */
 gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* params,
                               const gosurf_ray_batch* batch, const gosurf_loss_cfg* loss,
                               const gosurf_fwd_out* fwd, float loss_scale, gosurf_grads* grads,

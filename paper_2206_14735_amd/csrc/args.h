@@ -45,6 +45,11 @@ struct FieldArgs {
   int priv_off[4];
   int priv_floats;        // floats of the LDS area
   float* priv_partial;    // [gridDim.x][priv_floats] block partials
+  // gradient copies (optional): the levels not accumulated in LDS scatter into
+  // four x/y-parity copies instead of grad_grid; copy_base[l] is the float
+  // offset of level l's four copies in `copies` (-1: no copies)
+  float* copies;
+  int copy_base[4];
 };
 
 // the paper's colour path (colour grid at the finest level + view direction)

@@ -16,6 +16,8 @@ namespace gs {
 hipError_t launch_field(const FieldArgs& a, bool bwd, int blocks, hipStream_t st);
 hipError_t launch_priv_reduce(const FieldArgs& a, int n_part, const int counts[4], float* tmp, hipStream_t st);
 void plan_privatised_levels(FieldArgs& a, int counts[4]);
+long long plan_copies(FieldArgs& a);
+hipError_t launch_copy_fold(const FieldArgs& a, hipStream_t st);
 int priv_max_floats();
 int field_grid(const FieldArgs& a, bool bwd);
 hipError_t launch_render(const RenderArgs& a, bool bwd, hipStream_t st);
@@ -104,6 +106,8 @@ gosurf_status check_model(const gosurf_model* m) {
                 m->colour_mode);
   if (m->colour_mode == GOSURF_COLOUR_GRID && m->precision != GOSURF_FP32)
     return fail(GOSURF_ERR_VALUE, "the colour-grid path runs in GOSURF_FP32 only");
+  if (m->grad_copies != 0 && m->grad_copies != 1)
+    return fail(GOSURF_ERR_VALUE, "grad_copies %d is not 0 or 1", m->grad_copies);
   long long rows = 0;
   for (int l = 0; l < GOSURF_LEVELS; ++l) {
     if (!(m->voxel[l] > 0.f) || !std::isfinite(m->voxel[l]))
@@ -149,10 +153,11 @@ struct Workspace {
   float* priv_partial;    // [2048][priv_max_floats]
   float* colsum_tmp;      // [64][max(kMlpNumel, priv_max_floats)]
   float* ray_part;        // [64][8] block partials of sums over rays
+  float* copies;          // gradient copies (grad_copies), else NULL
   size_t bytes;
 };
 
-Workspace layout(char* base, int M, int total, int S) {
+Workspace layout(char* base, int M, int total, int S, long long copy_floats) {
   (void)S;
   Workspace w{};
   size_t off = 0;
@@ -167,8 +172,20 @@ Workspace layout(char* base, int M, int total, int S) {
   w.ray_part = reinterpret_cast<float*>(take(sizeof(float) * 64 * 8));
   w.colsum_tmp = reinterpret_cast<float*>(
       take(sizeof(float) * 64 * (size_t)(gs::priv_max_floats() > gs::kMlpNumel ? gs::priv_max_floats() : gs::kMlpNumel)));
+  w.copies = copy_floats > 0 ? reinterpret_cast<float*>(take(sizeof(float) * (size_t)copy_floats)) : nullptr;
   w.bytes = off;
   return w;
+}
+
+// Floats of the model's gradient copies: 0 without copies, -1 if the model's
+// levels are too large for them.
+long long model_copy_floats(const gosurf_model* m) {
+  if (!m->grad_copies) return 0;
+  gs::FieldArgs fa{};
+  fa.g = to_grid(m);
+  int counts[4];
+  gs::plan_privatised_levels(fa, counts);
+  return gs::plan_copies(fa);
 }
 
 gosurf_status check_batch(const gosurf_ray_batch* b, bool need_outputs) {
@@ -234,9 +251,14 @@ int64_t gosurf_batch_samples(const gosurf_sample_cfg* cfg) {
 }
 
 size_t gosurf_workspace_bytes(const gosurf_model* model, int32_t M, int32_t total, int32_t S) {
-  (void)model;
   if (M < 0 || total < 0 || S < 0) return 0;
-  return layout(nullptr, M, total, S).bytes;
+  long long cf = 0;
+  if (model) {
+    if (check_model(model) != GOSURF_OK) return 0;
+    cf = model_copy_floats(model);
+    if (cf < 0) return 0;
+  }
+  return layout(nullptr, M, total, S, cf).bytes;
 }
 
 gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames* fr, const gosurf_sample_cfg* c,
@@ -428,7 +450,8 @@ gosurf_status gosurf_forward(const gosurf_model* model, const gosurf_params* par
                              void* stream) {
   gosurf_status st;
   if ((st = forward_checks(model, params, b, loss, out)) != GOSURF_OK) return st;
-  const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
+  // the forward uses the part before the gradient copies
+  const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S, 0);
   if (!ws || ws_bytes < w.bytes)
     return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
                 w.bytes);
@@ -468,7 +491,10 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
     return fail(GOSURF_ERR_NULL, "grads.ray_o and grads.ray_r are both given or both NULL");
   if (!aligned(grads->grid, 16)) return fail(GOSURF_ERR_ALIGN, "grads.grid must be 16-byte aligned");
   if (!std::isfinite(loss_scale)) return fail(GOSURF_ERR_VALUE, "loss_scale must be finite");
-  const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S);
+  const long long copy_floats = model_copy_floats(model);
+  if (copy_floats < 0)
+    return fail(GOSURF_ERR_VALUE, "gradient copies need levels of at most 2048 x 2048 x 512 vertices and 2^31 floats");
+  const Workspace w = layout(static_cast<char*>(ws), b->M, b->total, b->S, copy_floats);
   if (!ws || ws_bytes < w.bytes)
     return fail(GOSURF_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
                 w.bytes);
@@ -505,11 +531,18 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   int counts[4];
   gs::plan_privatised_levels(fa, counts);
   fa.priv_partial = w.priv_partial;
+  if (copy_floats > 0) {
+    fa.copies = w.copies;
+    gs::plan_copies(fa);
+    if ((st = hip_check(gs::launch_zero(w.copies, copy_floats, s), "zero gradient copies")) != GOSURF_OK) return st;
+  }
   const int nb = gs::field_grid(fa, true);
   if (nb <= 0) return fail(GOSURF_ERR_HIP, "field grid: the occupancy query failed");
   mark(GOSURF_KERNEL_FIELD_BWD, true, s);
   if ((st = hip_check(gs::launch_field(fa, true, nb, s), "field bwd")) != GOSURF_OK) return st;
   mark(GOSURF_KERNEL_FIELD_BWD, false, s);
+  if (copy_floats > 0 && (st = hip_check(gs::launch_copy_fold(fa, s), "fold gradient copies")) != GOSURF_OK)
+    return st;
   if ((st = hip_check(gs::launch_priv_reduce(fa, nb, counts, w.colsum_tmp, s), "level reduce")) != GOSURF_OK)
     return st;
   if (ray_grads &&

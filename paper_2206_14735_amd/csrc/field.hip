@@ -120,10 +120,15 @@ struct ScatterStage {
 //    writers compute their segments' destinations, so the atomic loop reads
 //    only LDS (po >= 0: this lane's level has its LDS copy at float offset po).
 // BF: the BF16 kernel (decoders in bf16), which keeps fewer atomics in flight.
-template <bool HAS_DZ, bool HAS_GV, bool BF>
+// 4. With gradient copies (cpb >= 0: this lane's level scatters into four
+//    x/y-parity copies), the writer of cell (i, j, k) uses copy (i & 1, j & 1),
+//    where the cell's four corners at one z are one aligned 64-byte unit
+//    [dy][dx][feature]: its four segments are two such units, one request each
+//    instead of about five for the segments of the single layout.
+template <bool HAS_DZ, bool HAS_GV, bool BF, bool COPIES>
 __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const ScatterStage& S, int lane, int q,
-                                        int j, const LevelSample& ls, long long go, int po, bool valid,
-                                        const float dz[4], const float a[4], const float gv[3]) {
+                                        int j, const LevelSample& ls, const LevelConst& lc, int po, int cpb,
+                                        bool valid, const float dz[4], const float a[4], const float gv[3]) {
   // an invalid lane's inputs are zeroed (and its weights kept finite), so
   // its 32 values are exact zeros
   const float fx = valid ? ls.f[0] : 0.f, fy = valid ? ls.f[1] : 0.f, fz = valid ? ls.f[2] : 0.f;
@@ -172,13 +177,22 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const S
     const int rank = __popcll(wm & ((1ull << lane) - 1ull));
     S.heads[rank] = lane;
     float* st = S.val + lane * 32;
+    int unit = 0, plane = 0;
+    if (COPIES && cpb >= 0) {
+      const int ci = ls.cell & 2047, cj = (ls.cell >> 11) & 2047, ck = ls.cell >> 22;
+      const int mx = (lc.n[0] >> 1) + 1, my = (lc.n[1] >> 1) + 1;
+      plane = mx * my * 16;
+      unit = cpb + ((ci & 1) + 2 * (cj & 1)) * (lc.n[2] * plane) + ck * plane + ((cj >> 1) * mx + (ci >> 1)) * 16;
+    }
 #pragma unroll
     for (int sg = 0; sg < 4; ++sg) {
       const int c0 = sg, c1 = 4 + sg;   // corners (0, by, bz) and (1, by, bz), sg = 2 by + bz
       *reinterpret_cast<float4*>(st + 8 * sg) = make_float4(val[c0][0], val[c0][1], val[c0][2], val[c0][3]);
       *reinterpret_cast<float4*>(st + 8 * sg + 4) = make_float4(val[c1][0], val[c1][1], val[c1][2], val[c1][3]);
       const long long row = ls.row + (long long)(sg >> 1) * ls.sy + (long long)(sg & 1) * ls.sz;
-      S.dst[4 * lane + sg] = po >= 0 ? ~(po + 4 * (int)(row - go)) : (int)row;
+      S.dst[4 * lane + sg] = po >= 0   ? ~(po + 4 * (int)(row - lc.off))
+                             : COPIES && cpb >= 0 ? unit + (sg & 1) * plane + (sg >> 1) * 8
+                                       : (int)row;
     }
   }
   wave_lds_fence();
@@ -199,6 +213,7 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const S
       const float v = S.val[h * 32 + 8 * sg + f];
       const int d = S.dst[4 * h + sg];
       if (d < 0) atomic_add_lds(priv + (~d) + f, v);
+      else if constexpr (COPIES) atomic_add_global(A.copies + d + f, v);   // every level not in LDS has copies
       else atomic_add_global(A.grad_grid + (long long)d * 4 + f, v);
     }
   }
@@ -237,9 +252,9 @@ constexpr int kFieldMaxBlocksBwd = 2048;   // rows of the decoder / level partia
 // One wave-tile: MODE 0 = 16 ray samples, MODE 1 = 8 smoothness pairs (lanes
 // j < 8 hold x, lanes j >= 8 hold x + eps of the same pair).  POSE (backward
 // only): also dL/dx of every ray sample, for camera pose refinement.
-template <int MODE, bool BWD, bool BF, bool POSE, class Smem>
+template <int MODE, bool BWD, bool BF, bool POSE, bool COPIES, class Smem>
 __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, int tile, int total, int lane, int q,
-                                           int j, const LevelConst& lc, int po, float* scrA, float* scrB,
+                                           int j, const LevelConst& lc, int po, int cpb, float* scrA, float* scrB,
                                            const ScatterStage& stage, float* priv,
                                            v4f (&aW1)[2], v4f (&aW2)[4], v4f (&aW3)[2], v4f (&aU1)[2], v4f& aS,
                                            float& smooth_acc) {
@@ -508,10 +523,10 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
       rows_to_lanes<1>(scrB, &qv, tY, q, j);
       outer_lanes<BF, 2, 1>(tX, tY, aW1);
       const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
-      scatter<true, true, BF>(A, priv, stage, lane, q, j, ls, lc.off, po, valid, dzl, al, gv);
+      scatter<true, true, BF, COPIES>(A, priv, stage, lane, q, j, ls, lc, po, cpb, valid, dzl, al, gv);
     } else {
       const float al[4] = {0, 0, 0, 0};
-      scatter<true, false, BF>(A, priv, stage, lane, q, j, ls, lc.off, po, valid, dzl, al, gv);
+      scatter<true, false, BF, COPIES>(A, priv, stage, lane, q, j, ls, lc, po, cpb, valid, dzl, al, gv);
     }
   } else {
     // smoothness pair: d|g(x) - g(x+eps)|^2 / dg at either point is
@@ -544,7 +559,7 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
     outer_lanes<BF, 2, 1>(tX, tY, aW1);
     const float al[4] = {ab[0], ab[1], ab[2], ab[3]};
     const float dzl[4] = {0, 0, 0, 0};
-    scatter<false, true, BF>(A, priv, stage, lane, q, j, ls, lc.off, po, pv, dzl, al, gv);
+    scatter<false, true, BF, COPIES>(A, priv, stage, lane, q, j, ls, lc, po, cpb, pv, dzl, al, gv);
   }
   }
 }
@@ -553,7 +568,7 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
 // overlap with the ray tiles of other waves.
 // At least two waves per SIMD: the backward kernels then fit 256 registers
 // without spilling, and a second wave hides the gather and atomic latency.
-template <bool BWD, bool BF, bool POSE>
+template <bool BWD, bool BF, bool POSE, bool COPIES>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void field_kernel(FieldArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   FieldSmem<BF, BWD>& sm = *reinterpret_cast<FieldSmem<BF, BWD>*>(smem_raw);
@@ -586,6 +601,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   // this lane's grid level (q) in registers; po >= 0 if the level is accumulated in LDS
   const LevelConst lc = level_const(A.g, q);
   const int po = ((uniform_i(A.priv_mask) >> q) & 1) ? pick_level(A.priv_off, q) : -1;
+  const int cpb = COPIES ? pick_level(A.copy_base, q) : -1;
   float* priv = reinterpret_cast<float*>(smem_raw + smem_bytes<BF, BWD>());
   if (BWD)
     for (int e = tid; e < A.priv_floats; e += kBlock) priv[e] = 0.f;
@@ -613,10 +629,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
 
   for (int tile = blockIdx.x * kWavesPerBlock + wave; tile < n_tiles; tile += gridDim.x * kWavesPerBlock) {
     if (tile < n_pair_tiles)
-      field_tile<1, BWD, BF, POSE>(A, sm, tile, total, lane, q, j, lc, po, scrA, scrB, stage, priv, aW1, aW2, aW3,
+      field_tile<1, BWD, BF, POSE, COPIES>(A, sm, tile, total, lane, q, j, lc, po, cpb, scrA, scrB, stage, priv, aW1, aW2, aW3,
                                    aU1, aS, smooth_acc);
     else
-      field_tile<0, BWD, BF, POSE>(A, sm, tile - n_pair_tiles, total, lane, q, j, lc, po, scrA, scrB, stage, priv,
+      field_tile<0, BWD, BF, POSE, COPIES>(A, sm, tile - n_pair_tiles, total, lane, q, j, lc, po, cpb, scrA, scrB, stage, priv,
                                    aW1, aW2, aW3, aU1, aS, smooth_acc);
   }
 
@@ -749,6 +765,68 @@ void plan_privatised_levels(FieldArgs& a, int counts[4]) {
 
 int priv_max_floats() { return kPrivMaxFloats; }
 
+// Copy layout of one level with (nx, ny, nz) vertices: four copies (px, py),
+// each [nz][my][mx][dy][dx][feature] with mx = nx / 2 + 1, my = ny / 2 + 1;
+// vertex (x, y, z) sits in copy (px, py) at pair (x - px) / 2, (y - py) / 2
+// with dx = (x - px) & 1, dy = (y - py) & 1 (for x >= px, y >= py).
+static long long copy_level_floats(int nx, int ny, int nz) {
+  return 4LL * nz * ((nx >> 1) + 1) * ((ny >> 1) + 1) * 16;
+}
+
+// Gradient copies for every level not accumulated in LDS (call after
+// plan_privatised_levels).  Returns the floats of all copies, or -1 where a
+// level is too large for the packed cell index or the 32-bit offsets.
+long long plan_copies(FieldArgs& a) {
+  long long n = 0;
+  for (int l = 0; l < 4; ++l) {
+    a.copy_base[l] = -1;
+    if ((a.priv_mask >> l) & 1) continue;
+    if (a.g.nx[l] > 2048 || a.g.ny[l] > 2048 || a.g.nz[l] > 512) return -1;
+    a.copy_base[l] = (int)n;
+    n += copy_level_floats(a.g.nx[l], a.g.ny[l], a.g.nz[l]);
+    if (n >= (1LL << 31) - 64) return -1;
+  }
+  return n;
+}
+
+// grad[level] += the level's four copies (one thread per vertex, fixed order).
+// A block covers 64 x 4 vertices of one z-slice: a 64-byte unit holds two
+// rows of the copy, so the rows that share units are read by one block (one
+// XCD's L2) instead of by blocks that the dispatcher spreads over the XCDs.
+__global__ __launch_bounds__(256) void copy_fold_kernel(const float* __restrict__ copies, int base, int nx, int ny,
+                                                        int nz, long long off, float* __restrict__ grad) {
+  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y, z = blockIdx.z;
+  if (x >= nx || y >= ny) return;
+  const int mx = (nx >> 1) + 1, my = (ny >> 1) + 1, plane = mx * my * 16, csize = nz * plane;
+  float4* gp = reinterpret_cast<float4*>(grad) + off + ((long long)z * ny + y) * nx + x;
+  float4 acc = *gp;
+#pragma unroll
+  for (int py = 0; py < 2; ++py)
+#pragma unroll
+    for (int px = 0; px < 2; ++px) {
+      if (x < px || y < py) continue;
+      const int ux = x - px, uy = y - py;
+      const float4 c = *reinterpret_cast<const float4*>(copies + base + (px + 2 * py) * csize + z * plane +
+                                                        ((uy >> 1) * mx + (ux >> 1)) * 16 + (uy & 1) * 8 +
+                                                        (ux & 1) * 4);
+      acc.x += c.x; acc.y += c.y; acc.z += c.z; acc.w += c.w;
+    }
+  *gp = acc;
+}
+
+hipError_t launch_copy_fold(const FieldArgs& a, hipStream_t st) {
+  for (int l = 0; l < 4; ++l) {
+    if (a.copy_base[l] < 0) continue;
+    hipLaunchKernelGGL(copy_fold_kernel, dim3((unsigned)((a.g.nx[l] + 63) / 64), (unsigned)((a.g.ny[l] + 3) / 4),
+                                              a.g.nz[l]),
+                       dim3(64, 4), 0, st, a.copies, a.copy_base[l], a.g.nx[l], a.g.ny[l], a.g.nz[l],
+                       (long long)a.g.off[l], a.grad_grid);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <bool BWD, bool BF>
 static size_t field_smem(const FieldArgs& a) {
   return (size_t)smem_bytes<BF, BWD>() + (BWD ? (size_t)a.priv_floats * sizeof(float) : 0);
@@ -756,7 +834,7 @@ static size_t field_smem(const FieldArgs& a) {
 
 // Blocks that are resident at once on the current device for this kernel and
 // LDS size (CUs x blocks per CU), queried once per (device, kernel, LDS size).
-template <bool BWD, bool BF, bool POSE>
+template <bool BWD, bool BF, bool POSE, bool COPIES>
 static int resident_blocks(size_t smem) {
   struct Entry { int dev; size_t smem; int blocks; };
   thread_local Entry cache[8];
@@ -765,7 +843,7 @@ static int resident_blocks(size_t smem) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   for (int i = 0; i < n_cached; ++i)
     if (cache[i].dev == dev && cache[i].smem == smem) return cache[i].blocks;
-  const void* fn = reinterpret_cast<const void*>(&field_kernel<BWD, BF, POSE>);
+  const void* fn = reinterpret_cast<const void*>(&field_kernel<BWD, BF, POSE, COPIES>);
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem) != hipSuccess) return 0;
   int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
@@ -784,13 +862,17 @@ int field_grid(const FieldArgs& a, bool bwd) {
   const int tiles = (a.total + 15) / 16 + (a.S + 7) / 8;
   int blocks = (tiles + kWavesPerBlock - 1) / kWavesPerBlock;
   int resident;
-  const bool pose = bwd && a.grad_x != nullptr;
-  if (pose) resident = bf ? resident_blocks<true, true, true>(field_smem<true, true>(a))
-                          : resident_blocks<true, false, true>(field_smem<true, false>(a));
-  else if (bwd) resident = bf ? resident_blocks<true, true, false>(field_smem<true, true>(a))
-                              : resident_blocks<true, false, false>(field_smem<true, false>(a));
-  else resident = bf ? resident_blocks<false, true, false>(field_smem<false, true>(a))
-                     : resident_blocks<false, false, false>(field_smem<false, false>(a));
+  const bool pose = bwd && a.grad_x != nullptr, copies = bwd && a.copies != nullptr;
+  if (!bwd) resident = bf ? resident_blocks<false, true, false, false>(field_smem<false, true>(a))
+                          : resident_blocks<false, false, false, false>(field_smem<false, false>(a));
+  else if (bf) resident = pose ? (copies ? resident_blocks<true, true, true, true>(field_smem<true, true>(a))
+                                         : resident_blocks<true, true, true, false>(field_smem<true, true>(a)))
+                               : (copies ? resident_blocks<true, true, false, true>(field_smem<true, true>(a))
+                                         : resident_blocks<true, true, false, false>(field_smem<true, true>(a)));
+  else resident = pose ? (copies ? resident_blocks<true, false, true, true>(field_smem<true, false>(a))
+                                 : resident_blocks<true, false, true, false>(field_smem<true, false>(a)))
+                       : (copies ? resident_blocks<true, false, false, true>(field_smem<true, false>(a))
+                                 : resident_blocks<true, false, false, false>(field_smem<true, false>(a)));
   if (resident <= 0) return 0;
   const int cap = bwd ? kFieldMaxBlocksBwd : kFieldMaxBlocksFwd;
   if (blocks > resident) blocks = resident;
@@ -798,23 +880,30 @@ int field_grid(const FieldArgs& a, bool bwd) {
   return blocks < 1 ? 1 : blocks;
 }
 
-template <bool BWD, bool BF, bool POSE>
+template <bool BWD, bool BF, bool POSE, bool COPIES>
 static hipError_t launch_field_t(const FieldArgs& a, int blocks, hipStream_t st) {
   const size_t smem = field_smem<BWD, BF>(a);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<BWD, BF, POSE>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&field_kernel<BWD, BF, POSE, COPIES>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((field_kernel<BWD, BF, POSE>), dim3(blocks), dim3(kBlock), smem, st, a);
+  hipLaunchKernelGGL((field_kernel<BWD, BF, POSE, COPIES>), dim3(blocks), dim3(kBlock), smem, st, a);
   return hipGetLastError();
+}
+
+template <bool BF>
+static hipError_t launch_field_bwd(const FieldArgs& a, int blocks, hipStream_t st) {
+  const bool pose = a.grad_x != nullptr, copies = a.copies != nullptr;
+  if (pose) return copies ? launch_field_t<true, BF, true, true>(a, blocks, st)
+                          : launch_field_t<true, BF, true, false>(a, blocks, st);
+  return copies ? launch_field_t<true, BF, false, true>(a, blocks, st)
+                : launch_field_t<true, BF, false, false>(a, blocks, st);
 }
 
 hipError_t launch_field(const FieldArgs& a, bool bwd, int blocks, hipStream_t st) {
   const bool bf = a.grid_bf16 != nullptr;
-  if (bwd && a.grad_x)
-    return bf ? launch_field_t<true, true, true>(a, blocks, st) : launch_field_t<true, false, true>(a, blocks, st);
-  if (bwd)
-    return bf ? launch_field_t<true, true, false>(a, blocks, st) : launch_field_t<true, false, false>(a, blocks, st);
-  return bf ? launch_field_t<false, true, false>(a, blocks, st) : launch_field_t<false, false, false>(a, blocks, st);
+  if (bwd) return bf ? launch_field_bwd<true>(a, blocks, st) : launch_field_bwd<false>(a, blocks, st);
+  return bf ? launch_field_t<false, true, false, false>(a, blocks, st)
+            : launch_field_t<false, false, false, false>(a, blocks, st);
 }
 
 }  // namespace gs

@@ -10,6 +10,7 @@ struct LevelSample {
   float f[3];
   long long row;   // corner 000
   int sy, sz;      // row strides of +y, +z corners
+  int cell;        // cell indices i | j << 11 | k << 22 (each below 2048 where gradient copies are used)
   float inv_v;
 };
 
@@ -62,6 +63,7 @@ __device__ __forceinline__ void locate(const Grid& g, const LevelConst& lc, floa
   ls.sy = lc.n[0];
   ls.sz = lc.n[0] * lc.n[1];
   ls.row = lc.off + ((long long)i0[2] * lc.n[1] + i0[1]) * lc.n[0] + i0[0];
+  ls.cell = i0[0] | (i0[1] << 11) | (i0[2] << 22);
   ls.inv_v = 1.f / v;
 }
 

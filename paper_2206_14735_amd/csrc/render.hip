@@ -656,8 +656,18 @@ hipError_t launch_nonfinite_check(const float* grid_grad, long long n_grid, cons
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void zero4_kernel(float4* __restrict__ a, long long n4) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n4; i += (long long)gridDim.x * 256)
+    a[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 hipError_t launch_zero(float* a, long long n, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3(stream_blocks(n)), dim3(256), 0, st, a, n);
+  if (n <= 0) return hipSuccess;
+  if (n % 4 == 0 && reinterpret_cast<uintptr_t>(a) % 16 == 0)
+    hipLaunchKernelGGL(zero4_kernel, dim3(stream_blocks(n / 4)), dim3(256), 0, st, reinterpret_cast<float4*>(a),
+                       n / 4);
+  else
+    hipLaunchKernelGGL(zero_kernel, dim3(stream_blocks(n)), dim3(256), 0, st, a, n);
   return hipGetLastError();
 }
 

@@ -42,7 +42,8 @@ class GosurfError(RuntimeError):
 class Model(C.Structure):
     _fields_ = [("p0", C.c_float * 3), ("p1", C.c_float * 3), ("voxel", C.c_float * LEVELS),
                 ("dims", (C.c_int32 * 3) * LEVELS), ("offset", C.c_int64 * LEVELS),
-                ("n_vertices", C.c_int64), ("precision", C.c_int32), ("colour_mode", C.c_int32)]
+                ("n_vertices", C.c_int64), ("precision", C.c_int32), ("colour_mode", C.c_int32),
+                ("grad_copies", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -199,9 +200,11 @@ def _stream(stream):
 
 
 # ---------------------------------------------------------------- descriptors
-def make_model(layout, precision=FP32, colour_mode=0):
+def make_model(layout, precision=FP32, colour_mode=0, grad_copies=False):
     """gosurf_model from a synth.GridLayout (levels coarsest first); colour_mode
-    COLOUR_DECODED (0) or COLOUR_GRID (1, the paper's colour path)."""
+    COLOUR_DECODED (0) or COLOUR_GRID (1, the paper's colour path);
+    grad_copies: the backward scatters the large levels into x/y-parity
+    gradient copies in the workspace (see gosurf_backward)."""
     if layout.n_levels != LEVELS:
         raise ValueError(f"the library implements {LEVELS}-level grids")
     m = Model()
@@ -216,6 +219,7 @@ def make_model(layout, precision=FP32, colour_mode=0):
     m.n_vertices = layout.n_vertices
     m.precision = precision
     m.colour_mode = colour_mode
+    m.grad_copies = 1 if grad_copies else 0
     return m
 
 
@@ -505,6 +509,8 @@ def gosurf_time_kernel(kernel, start=None, stop=None):
 
 def workspace_for(model, M, total, S, device="cuda"):
     n = gosurf_workspace_bytes(model, M, total, S)
+    if n == 0:
+        raise GosurfError("gosurf_workspace_bytes", 4, lib().gosurf_last_error().decode())
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 

@@ -16,11 +16,11 @@ class Reconstruction:
     def __init__(self, layout, frames, n_strat, n_near, M, S, span_mode, near, far, trunc=0.1,
                  delta_s=0.004, lambdas=(10.0, 1.0, 10.0, 1.0, 1.0, 1.0), alpha_fs=5.0,
                  lr_grid=1e-2, lr_mlp=1e-3, seed=0, precision=G.FP32, loss_scale=1.0,
-                 grid=None, mlp=None, device="cuda"):
+                 grid=None, mlp=None, device="cuda", grad_copies=False):
         import synth
         self.device = torch.device(device)
         self.layout = layout
-        self.model = G.make_model(layout, precision)
+        self.model = G.make_model(layout, precision, grad_copies=grad_copies)
         if grid is None or mlp is None:
             grid, mlp = synth.init_params(layout, seed=seed)
         self.grid = grid.to(self.device, torch.float32).contiguous()
@@ -86,7 +86,8 @@ class Reconstruction:
         if self.poses is not None:
             raise ValueError("pose refinement is not built for the colour-grid path")
         cg, cm = synth.init_colour(self.layout, seed=seed, grid_std=grid_std)
-        self.model = G.make_model(self.layout, self.model.precision, colour_mode=G.COLOUR_GRID)
+        self.model = G.make_model(self.layout, self.model.precision, colour_mode=G.COLOUR_GRID,
+                                  grad_copies=bool(self.model.grad_copies))
         self.cgrid = cg.to(self.device).contiguous()
         self.cmlp = cm.to(self.device).contiguous()
         self.cgrid_grad, self.cmlp_grad = torch.zeros_like(self.cgrid), torch.zeros_like(self.cmlp)

@@ -76,6 +76,33 @@ def test_workspace_bytes_grows_with_batch(lib):
     assert a % 256 == 0
 
 
+def test_workspace_bytes_with_gradient_copies(lib):
+    import synth
+    L = synth.configs.ROOM.layout()
+    a = G.gosurf_workspace_bytes(G.make_model(L), 1024, 65536, 4096)
+    b = G.gosurf_workspace_bytes(G.make_model(L, grad_copies=True), 1024, 65536, 4096)
+    # levels are kept on chip, coarsest first, while their vertices add up to at
+    # most 1024; each other level gets four copies of nz (nx/2 + 1)(ny/2 + 1)
+    # 64-byte units
+    on_chip, extra = 0, 0
+    for nx, ny, nz in L.dims:
+        if on_chip + nx * ny * nz <= 1024:
+            on_chip += nx * ny * nz
+        else:
+            extra += 4 * nz * (nx // 2 + 1) * (ny // 2 + 1) * 64
+    assert on_chip > 0 and extra > 0
+    assert b - a == (extra + 255) // 256 * 256
+    # more than 2048 vertices along x: no copies
+    big = synth.padded_layout((0.0, 0.0, 0.0), (50.0, 1.0, 1.0), (0.02, 0.06, 0.24, 0.96))
+    assert max(d[0] for d in big.dims) > 2048
+    assert G.gosurf_workspace_bytes(G.make_model(big), 64, 64, 0) > 0
+    assert G.gosurf_workspace_bytes(G.make_model(big, grad_copies=True), 64, 64, 0) == 0
+    m = G.make_model(L)
+    m.grad_copies = 2
+    assert G.gosurf_workspace_bytes(m, 64, 64, 0) == 0
+    assert b"grad_copies" in lib.gosurf_last_error()
+
+
 def test_batch_samples(lib):
     c = G.SampleCfg(6144, 64, 32, 1, 0.1, 1e9, 0.1, 16384, 0.004, 0, 0)
     assert G.gosurf_batch_samples(c) == 6144 * 96
