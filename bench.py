@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP32 vs BF16 + proposal comparison")
     ap.add_argument("--compare-seeds", type=int, default=3, help="seeds of the comparison")
+    ap.add_argument("--proposal-samples", type=int, default=None,
+                    help="samples in the predicted interval per confident ray (default: the workload's)")
+    ap.add_argument("--free-samples", type=int, default=None,
+                    help="samples on the free space before the interval per confident ray (default: the workload's)")
     ap.add_argument("--compare-phase1", type=int, default=600,
                     help="shared plain FP32 steps (65536 rays) before the two continuations")
     ap.add_argument("--compare-phase2", type=int, default=600, help="steps of each continuation (timed)")
@@ -276,8 +280,8 @@ def compare(a, G, synth, Reconstruction, torch):
     wp = synth.configs.ROOM_PROPOSAL
     lay = wp.layout()
     M, S = wp.M, wp.S
-    n_prop = wp.extra["proposal_samples"]
-    n_free = wp.extra["free_samples"]
+    n_prop = wp.extra["proposal_samples"] if a.proposal_samples is None else a.proposal_samples
+    n_free = wp.extra["free_samples"] if a.free_samples is None else a.free_samples
     depth_check = wp.extra["depth_check"]
     depth_extend = wp.extra["depth_extend"]
     thr = wp.extra["conf_threshold"]
@@ -390,7 +394,9 @@ def compare(a, G, synth, Reconstruction, torch):
             e = torch.cat(errs)
             out = {"depth_l1_mm": {"mean": round(1e3 * e.mean().item(), 3),
                                    "median": round(1e3 * e.median().item(), 3),
-                                   "p90": round(1e3 * torch.quantile(e, 0.9).item(), 3)},
+                                   "p90": round(1e3 * torch.quantile(e, 0.9).item(), 3),
+                                   "p99": round(1e3 * torch.quantile(e, 0.99).item(), 3),
+                                   "over_50mm": round((e > 0.05).float().mean().item(), 5)},
                    "samples_per_ray": round(sum(spr) / len(spr), 2)}
             if conf:
                 out["confident_fraction"] = round(sum(conf) / len(conf), 4)
