@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--compare-phase1", type=int, default=600,
                     help="shared plain FP32 steps (65536 rays) before the two continuations")
     ap.add_argument("--compare-phase2", type=int, default=600, help="steps of each continuation (timed)")
+    ap.add_argument("--sequential", type=int, default=0,
+                    help="also run sequential (online) mapping over this many frames of the room sequence")
+    ap.add_argument("--seq-iters", type=int, default=10, help="sequential mapping: steps after each new frame")
+    ap.add_argument("--seq-rays", type=int, default=4096, help="sequential mapping: rays per step")
     ap.add_argument("--mesh", type=float, default=0.0,
                     help="also extract the surface on a lattice of this spacing (m) after --mesh-train more steps")
     ap.add_argument("--mesh-train", type=int, default=10000,
@@ -188,6 +192,44 @@ def cpu_baseline(w, frames_cpu, grid, mlp, n_rays, reps=1):
                       f"{grid.numel() + mlp.numel()} parameters ({t_adam:.1f} s in all)"}
 
 
+def sequential_measure(a, G, synth, frames, torch):
+    """Online mapping over the first a.sequential frames of the room sequence
+    with the 3-level grid of the sequential mode (96, 24, 6 cm): frames/s of
+    the whole loop (a.seq_iters steps of a.seq_rays rays after each frame),
+    then the depth error of the resulting field on the received frames,
+    rendered with 64 + 32 samples against the noise-free depth."""
+    from paper_2206_14735_amd.train import Reconstruction, SequentialMapper
+    n = min(a.sequential, frames.depth.shape[0])
+    sm = SequentialMapper(frames, (0.0, 0.0, 0.0), (8.0, 6.0, 3.0), M=a.seq_rays, S=1024,
+                          iters_per_frame=a.seq_iters, seed=0)
+    sm.add_frame()                       # warm-up: first frame, kernels loaded
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n - 1):
+        sm.add_frame()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rec = sm.rec
+    seen = sm._frames(n)
+    ev = Reconstruction(sm.layout, seen, 64, 32, 16384, 0, G.SPAN_BOX, 0.1, 1e9, 0.1, seed=5, grid=rec.grid,
+                        mlp=rec.mlp)
+    errs = []
+    for k in range(4):
+        ev.it = 400_000 + k
+        ev.sample()
+        ev.forward()
+        ok = ev.batch.depth > 0
+        errs.append((ev.fwd.depth_hat[ok] - seen.depth_gt.reshape(-1)[ev.batch.pixel][ok]).abs())
+    e = torch.cat(errs)
+    n_par = rec.grid.numel() + rec.mlp.numel()
+    return {"frames": n, "frames_per_s": round((n - 1) / dt, 2), "ms_per_frame": round(1e3 * dt / (n - 1), 3),
+            "steps_per_frame": a.seq_iters, "rays_per_step": a.seq_rays, "smoothness_pairs": 1024,
+            "ms_per_step": round(1e3 * dt / ((n - 1) * a.seq_iters), 4),
+            "grid": "3 levels, 0.96 / 0.24 / 0.06 m", "params": n_par,
+            "depth_l1_mm_on_received_frames": {"mean": round(1e3 * e.mean().item(), 3),
+                                               "median": round(1e3 * e.median().item(), 3)}}
+
+
 def mesh_measure(a, G, rec, w, scene, frames, torch):
     """SDF lattice over the grid box and marching tetrahedra on it, timed with
     HIP events; then culling of unobserved surface and the reconstruction
@@ -228,25 +270,34 @@ def mesh_measure(a, G, rec, w, scene, frames, torch):
     cen = tris[pick].double().mean(1)
     err = scene.sdf(cen).abs() if kept else torch.zeros(1, device="cuda", dtype=torch.float64)
     # per lattice point: 4 levels x 8 corners x 16 B gathered, t and ray index in, 4 outputs out, phi copied
-    per_pt = 32 * CORNER_BYTES[w.precision] + 8.0 + 16.0 + 8.0
-    gbs = per_pt * n_pts / (sdf_ms * 1e-3) / 1e9
+    # Per lattice point the kernel runs the geometry decoder (16-32-32-16: 4096 FLOPs, the colour decoder
+    # is skipped) on 4 levels x 8 corners gathered from the caches (neighbouring points share corners),
+    # so its bound is the matrix cores; the compulsory HBM bytes are t and the ray index in, the 16-byte
+    # output and the phi copy (36 B per point) plus one read of the grid.
+    flops_pt = 4096.0
+    tfs = flops_pt * n_pts / (sdf_ms * 1e-3) / 1e12
+    comp_bytes = 36.0 * n_pts + 4.0 * rec.grid.numel()
+    gbs = comp_bytes / (sdf_ms * 1e-3) / 1e9
     t0 = time.perf_counter()
     tk = tris[:kept]
     seen = mesh_eval.visible(tk.mean(1), frames)
-    pred = mesh_eval.sample_triangles(tk[seen], 1e4, seed=0)
+    pred, pred_n = mesh_eval.sample_triangles(tk[seen], 1e4, seed=0, normals=True)
     gt = scene.surface_samples(1e4, seed=0).to("cuda")
     gt = gt[mesh_eval.visible(gt, frames)]
+    gt_n = scene.normals(gt)
     torch.cuda.synchronize()
     t_cull = time.perf_counter() - t0
-    m = mesh_eval.metrics(pred, gt, 0.05)
+    m = mesh_eval.metrics(pred, gt, 0.05, pred_normals=pred_n, gt_normals=gt_n)
     t_eval = time.perf_counter() - t0
     quality = {"culled_triangles_kept": int(seen.sum()), "points_per_cm2": 1,
                **{k: (round(1e3 * v, 3) if k in ("accuracy", "completion", "chamfer_l1") else v) for k, v in m.items()},
                "distance_unit": "mm", "threshold": "5 cm", "cull_s": round(t_cull, 2), "eval_s": round(t_eval, 2)}
     return {"spacing_m": h, "lattice": list(dims), "points": n_pts, "train_steps_before": a.mesh_train,
             "sdf_lattice_ms": round(sdf_ms, 3), "lattice_points_per_s": round(n_pts / (sdf_ms * 1e-3)),
-            "sdf_lattice_roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": per_pt},
+            "sdf_lattice_roofline": {"bound": "mfma", "achieved": round(tfs, 2), "peak": MFMA_PEAK_TFLOPS[w.precision],
+                                     "unit": "TFLOP/s", "frac": round(tfs / MFMA_PEAK_TFLOPS[w.precision], 4),
+                                     "flops_per_point": flops_pt,
+                                     "compulsory_hbm_gb_per_s": round(gbs, 1)},
             "marching_ms": round(mt_ms, 3), "cubes_per_s": round((nx - 1) * (ny - 1) * (nz - 1) / (mt_ms * 1e-3)),
             "triangles": n_tri, "triangle_capacity": cap,
             "unculled_centroid_sdf_mm": {"mean": round(1e3 * float(err.mean()), 3),
@@ -619,6 +670,12 @@ def main():
             raise SystemExit("--mesh needs a room workload (its analytic scene judges the accuracy)")
         mesh = mesh_measure(a, G, rec, w, scene, frames, torch)
         print(f"# mesh: {mesh}", file=sys.stderr, flush=True)
+    sequential = None
+    if a.sequential > 0:
+        if scene is None:
+            raise SystemExit("--sequential needs a room workload")
+        sequential = sequential_measure(a, G, synth, frames, torch)
+        print(f"# sequential: {sequential}", file=sys.stderr, flush=True)
     comparison = None
     if not a.no_compare:
         del rec
@@ -657,6 +714,8 @@ def main():
     }
     if mesh is not None:
         out["mesh"] = mesh
+    if sequential is not None:
+        out["sequential_mapping"] = sequential
     print(json.dumps(out), flush=True)
 
 

@@ -16,7 +16,12 @@ at 5 cm are computed between the clouds.  Readings used here:
   uniform barycentric coordinates;
 * accuracy = mean distance from predicted to ground-truth points,
   completion = the reverse, Chamfer-L1 = their mean, precision / recall =
-  the fractions within the threshold, F = 2 P R / (P + R).
+  the fractions within the threshold, F = 2 P R / (P + R);
+* normal consistency (named by the paper, not defined there): each point
+  carries a unit normal (a predicted point its triangle's, a ground-truth
+  point the scene's), and NC is the mean, over both directions, of
+  |n . n'| with n' the normal of the nearest point of the other cloud
+  (orientation-free, 1 for matching surfaces).
 
 This is evaluation, not part of an optimisation step; it runs as torch
 operations on whatever device the inputs live on.
@@ -63,8 +68,9 @@ def triangle_areas(tris):
     return 0.5 * torch.linalg.norm(torch.linalg.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0]), dim=1)
 
 
-def sample_triangles(tris, density, seed=0):
-    """Points on triangles [T, 3, 3], `density` per square metre on average: [N, 3] float64."""
+def sample_triangles(tris, density, seed=0, normals=False):
+    """Points on triangles [T, 3, 3], `density` per square metre on average: [N, 3] float64
+    (with normals=True also each point's unit triangle normal, [N, 3])."""
     g = torch.Generator(device=tris.device).manual_seed(seed)
     a = triangle_areas(tris)
     n = torch.floor(a * density + torch.rand(a.shape, generator=g, device=tris.device, dtype=torch.float64)).long()
@@ -73,19 +79,32 @@ def sample_triangles(tris, density, seed=0):
     r2 = torch.rand(idx.shape[0], 1, generator=g, device=tris.device, dtype=torch.float64)
     s = torch.sqrt(r1)
     t = tris[idx].to(torch.float64)
-    return (1 - s) * t[:, 0] + s * (1 - r2) * t[:, 1] + s * r2 * t[:, 2]
+    p = (1 - s) * t[:, 0] + s * (1 - r2) * t[:, 1] + s * r2 * t[:, 2]
+    if not normals:
+        return p
+    nrm = torch.linalg.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    return p, nrm / nrm.norm(dim=1, keepdim=True).clamp(min=1e-300)
 
 
-def metrics(pred, gt, threshold=0.05):
-    """Accuracy, completion, Chamfer-L1 (metres), precision, recall, F-score between point clouds."""
+def metrics(pred, gt, threshold=0.05, pred_normals=None, gt_normals=None):
+    """Accuracy, completion, Chamfer-L1 (metres), precision, recall, F-score between point clouds,
+    and normal consistency when both clouds come with unit normals."""
     from scipy.spatial import cKDTree
-    pred = np.asarray(pred.cpu() if torch.is_tensor(pred) else pred, dtype=np.float64)
-    gt = np.asarray(gt.cpu() if torch.is_tensor(gt) else gt, dtype=np.float64)
-    d_pred, _ = cKDTree(gt).query(pred, workers=-1)
-    d_gt, _ = cKDTree(pred).query(gt, workers=-1)
+
+    def host(x):
+        return np.asarray(x.cpu() if torch.is_tensor(x) else x, dtype=np.float64)
+    pred, gt = host(pred), host(gt)
+    d_pred, i_pred = cKDTree(gt).query(pred, workers=-1)
+    d_gt, i_gt = cKDTree(pred).query(gt, workers=-1)
     acc, comp = float(d_pred.mean()), float(d_gt.mean())
     prec, rec = float(np.mean(d_pred < threshold)), float(np.mean(d_gt < threshold))
     f = 2 * prec * rec / (prec + rec) if prec + rec > 0 else 0.0
-    return {"accuracy": acc, "completion": comp, "chamfer_l1": 0.5 * (acc + comp), "precision": prec,
-            "recall": rec, "f_score": f, "threshold": threshold, "n_pred": int(pred.shape[0]),
-            "n_gt": int(gt.shape[0])}
+    out = {"accuracy": acc, "completion": comp, "chamfer_l1": 0.5 * (acc + comp), "precision": prec,
+           "recall": rec, "f_score": f, "threshold": threshold, "n_pred": int(pred.shape[0]),
+           "n_gt": int(gt.shape[0])}
+    if pred_normals is not None and gt_normals is not None:
+        npd, ngt = host(pred_normals), host(gt_normals)
+        nc_acc = np.abs(np.sum(npd * ngt[i_pred], axis=1)).mean()
+        nc_comp = np.abs(np.sum(ngt * npd[i_gt], axis=1)).mean()
+        out["normal_consistency"] = float(0.5 * (nc_acc + nc_comp))
+    return out

@@ -47,6 +47,7 @@ class Reconstruction:
         self.importance = None
         self.poses = None
         self.cgrid = None
+        self.frozen_rows = 0   # leading grid rows that Adam leaves alone (their gradient is dropped)
         self.it = 0
 
     @classmethod
@@ -130,9 +131,13 @@ class Reconstruction:
                                self.pose_grad)
 
     def adam(self):
-        G.gosurf_adam_step(self.it + 1, self.grid, self.grid_grad, self.grid_m, self.grid_v, self.mlp,
-                           self.mlp_grad, self.mlp_m, self.mlp_v, self.lr_grid, self.lr_mlp,
-                           inv_loss_scale=1.0 / self.loss_scale, grid_bf16=self.grid_bf16)
+        f = self.frozen_rows
+        if f:
+            self.grid_grad[:f].zero_()
+        G.gosurf_adam_step(self.it + 1, self.grid[f:], self.grid_grad[f:], self.grid_m[f:], self.grid_v[f:],
+                           self.mlp, self.mlp_grad, self.mlp_m, self.mlp_v, self.lr_grid, self.lr_mlp,
+                           inv_loss_scale=1.0 / self.loss_scale,
+                           grid_bf16=None if self.grid_bf16 is None else self.grid_bf16[f:])
         if self.cgrid is not None:
             # the colour grid with the grids' rate, its decoder with the decoders'
             G.gosurf_adam_step(self.it + 1, self.cgrid.view(-1), self.cgrid_grad.view(-1), self.cgrid_m.view(-1),
@@ -184,3 +189,43 @@ class Reconstruction:
     def losses(self):
         v = self.fwd.losses.tolist()
         return dict(zip(G.LOSS_NAMES, v))
+
+
+class SequentialMapper:
+    """Online mapping (supplementary, sequential mapping experiments): frames
+    arrive one at a time, and after each arrival the field takes
+    `iters_per_frame` steps on rays drawn uniformly from the frames received
+    so far (or from the last `window` of them).  The grid is the 3-level one
+    of that mode, 96, 24 and 6 cm (synth.sequential_layout): its placeholder
+    level 0 starts at 0 and Adam leaves it there, so the decoder sees 12
+    features and the first layer's columns for the placeholder get no
+    gradient.  Losses, decoders and their learning rates are the batch
+    mode's."""
+
+    def __init__(self, frames, bounds_min, bounds_max, M=4096, S=1024, iters_per_frame=5, window=0,
+                 n_strat=64, n_near=32, near=0.1, far=1e9, trunc=0.1, seed=0, device="cuda"):
+        import synth
+        self.layout = synth.sequential_layout(bounds_min, bounds_max)
+        grid, mlp = synth.init_params(self.layout, seed=seed)
+        n0 = self.layout.dims[0][0] * self.layout.dims[0][1] * self.layout.dims[0][2]
+        grid[:n0] = 0.0
+        self.all = frames.to(device)
+        self.iters, self.window = iters_per_frame, window
+        self.t = 0   # frames received
+        self.rec = Reconstruction(self.layout, self._frames(1), n_strat, n_near, M, S, G.SPAN_BOX, near, far, trunc,
+                                  seed=seed, grid=grid, mlp=mlp, device=device)
+        self.rec.frozen_rows = n0
+
+    def _frames(self, t):
+        import synth
+        f = self.all
+        a = max(0, t - self.window) if self.window else 0
+        return synth.Frames(f.rgb[a:t], f.depth[a:t], f.c2w[a:t], f.fx, f.fy, f.cx, f.cy,
+                            None if f.depth_gt is None else f.depth_gt[a:t])
+
+    def add_frame(self):
+        """Receive the next frame and take the steps that follow it."""
+        self.t += 1
+        self.rec.frames = self._frames(self.t)
+        for _ in range(self.iters):
+            self.rec.step()

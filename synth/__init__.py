@@ -10,7 +10,7 @@ any of the code under test.
 
 from .scenes import SphereScene, RoomScene  # noqa: F401
 from .frames import Frames, render_frames, sphere_frames, room_frames  # noqa: F401
-from .layout import GridLayout, padded_layout  # noqa: F401
+from .layout import GridLayout, padded_layout, sequential_layout  # noqa: F401
 from .params import (init_params, init_proposal, init_colour, MLP_SIZES, mlp_slices, MLP_NUMEL,  # noqa: F401
                      PROPOSAL_NUMEL, COLOUR_MLP_NUMEL)
 from . import params  # noqa: F401

@@ -58,3 +58,14 @@ def padded_layout(bounds_min, bounds_max, voxels, feat=4):
             raise ValueError("every voxel size must divide the coarsest one")
         dims.append(tuple(int(round(e / v)) + 1 for e in ext))
     return GridLayout(tuple(p0), tuple(p1), vox, dims, feat=feat)
+
+
+def sequential_layout(bounds_min, bounds_max, voxels=(0.96, 0.24, 0.06), feat=4):
+    """The 3-level grid of the sequential-mapping mode (96, 24 and 6 cm) in a
+    4-level table: level 0 is a placeholder of 2 x 2 x 2 vertices whose one
+    cell spans the whole box.  With its features held at 0 it adds nothing to
+    the decoder input, and the decoder's first-layer columns for it get a zero
+    gradient, so the model is the 3-level one."""
+    base = padded_layout(bounds_min, bounds_max, voxels, feat)
+    ext = max(b - a for a, b in zip(base.p0, base.p1))
+    return GridLayout(base.p0, base.p1, [ext] + list(base.voxels), [(2, 2, 2)] + list(base.dims), feat=feat)

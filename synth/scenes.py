@@ -162,6 +162,14 @@ class RoomScene:
             d = torch.minimum(d, (p - c.to(p)).norm(dim=-1) - r)
         return d
 
+    def normals(self, p, h=1e-6):
+        """Unit normals of the scene surface at points p [N, 3] (float64): the
+        normalised central-difference gradient of the analytic SDF."""
+        p = p.to(torch.float64)
+        g = torch.stack([self.sdf(p + h * e) - self.sdf(p - h * e)
+                         for e in torch.eye(3, dtype=torch.float64, device=p.device)], -1)
+        return g / g.norm(dim=-1, keepdim=True).clamp(min=1e-300)
+
     def _albedo(self, p, obj):
         s = self.noise_step
         u = (p / s).clamp(min=0)

@@ -63,3 +63,35 @@ def test_room_surface_samples_lie_on_the_surface():
     p = sc.surface_samples(2000.0, seed=1)
     assert p.shape[0] > 0.8 * 2000 * 150
     assert torch.all(sc.sdf(p).abs() < 1e-6)
+
+
+def test_normal_consistency():
+    """1 for matching surfaces whatever the normals' orientation, |cos| of the
+    angle between two planes, and the triangle normals of a sampled mesh."""
+    rng = np.random.default_rng(4)
+    g = np.column_stack([rng.uniform(0, 1, 20000), rng.uniform(0, 1, 20000), np.zeros(20000)])
+    up = np.tile([0.0, 0.0, 1.0], (g.shape[0], 1))
+    assert E.metrics(g, g, pred_normals=up, gt_normals=up)["normal_consistency"] == 1.0
+    assert E.metrics(g, g, pred_normals=-up, gt_normals=up)["normal_consistency"] == 1.0
+    side = np.tile([1.0, 0.0, 0.0], (g.shape[0], 1))
+    assert E.metrics(g, g, pred_normals=side, gt_normals=up)["normal_consistency"] == 0.0
+    a = 0.3
+    tilt = np.tile([np.sin(a), 0.0, np.cos(a)], (g.shape[0], 1))
+    assert E.metrics(g, g, pred_normals=tilt, gt_normals=up)["normal_consistency"] == pytest.approx(np.cos(a))
+    assert "normal_consistency" not in E.metrics(g, g)
+    tris = torch.tensor([[[0, 0, 0], [1, 0, 0], [0, 1, 0]], [[1, 0, 0], [0, 1, 0], [1, 1, 0]]], dtype=torch.float64)
+    p, n = E.sample_triangles(tris, 5000.0, seed=1, normals=True)
+    assert p.shape == n.shape and torch.allclose(n.abs(), torch.tensor([0.0, 0.0, 1.0], dtype=torch.float64))
+
+
+def test_room_normals_are_the_faces_normals():
+    sc = synth.scenes.RoomScene(0)
+    floor = torch.tensor([[2.0, 3.0, 0.0], [5.5, 1.2, 0.0]], dtype=torch.float64)
+    wall = torch.tensor([[0.0, 3.0, 1.0]], dtype=torch.float64)
+    # the SDF grows into the room: +z at the floor, +x at the wall x = 0
+    assert torch.allclose(sc.normals(floor), torch.tensor([0.0, 0.0, 1.0], dtype=torch.float64).expand(2, 3),
+                          atol=1e-6)
+    assert torch.allclose(sc.normals(wall), torch.tensor([[1.0, 0.0, 0.0]], dtype=torch.float64), atol=1e-6)
+    p = sc.surface_samples(200.0, seed=2)
+    n = sc.normals(p)
+    assert torch.allclose(n.norm(dim=1), torch.ones(p.shape[0], dtype=torch.float64))
