@@ -39,12 +39,12 @@ pytestmark = pytest.mark.gpu
 TRAIN_STEPS = 500
 
 # relative L2 against the FP64 oracle, and depth errors in millimetres
-# About twice the largest error measured on MI355X over three trainings and
+# About twice the largest error measured on MI355X over four trainings and
 # three subsets each (relative L2 against the FP64 oracle; depth in mm).
 BOUNDS = {"phi": 5e-3, "colour": 3e-3, "c_hat": 2.5e-3, "d_hat": 1e-3, "depth_mm_median": 1.0,
           "depth_mm_p90": 2.0,
           "total": 3e-2, "grad_grid_0": 0.8, "grad_grid_1": 0.8, "grad_grid_2": 0.8, "grad_grid_3": 0.8,
-          "q_total": 1.2e-2, "q_grad_grid_0": 0.6, "q_grad_grid_1": 0.6, "q_grad_grid_2": 0.6, "q_grad_grid_3": 0.6}
+          "q_total": 3e-2, "q_grad_grid_0": 0.6, "q_grad_grid_1": 0.6, "q_grad_grid_2": 0.6, "q_grad_grid_3": 0.6}
 # The decoder gradient is the smallest residual (every sample feeds it): its
 # relative L2 error reached 0.83 against the masters and 0.69 against the
 # rounded masters, so it is bounded by the angle instead (1 - cos at twice the
