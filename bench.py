@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--compare-seeds", type=int, default=3, help="seeds of the comparison")
     ap.add_argument("--proposal-samples", type=int, default=None,
                     help="samples in the predicted interval per confident ray (default: the workload's)")
+    ap.add_argument("--depth-edge", type=float, default=0.0,
+                    help="proposal rays at a depth discontinuity larger than this (m) fall back to plain samples")
     ap.add_argument("--free-samples", type=int, default=None,
                     help="samples on the free space before the interval per confident ray (default: the workload's)")
     ap.add_argument("--compare-phase1", type=int, default=600,
@@ -430,7 +432,7 @@ def compare(a, G, synth, Reconstruction, torch):
             """Rendered depth against the noise-free depth of the held-out frames, on rays with observed depth."""
             evaluator.grid, evaluator.mlp = grid, mlp
             evaluator.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr, n_free=n_free,
-                                   depth_check=depth_check, depth_extend=depth_extend)
+                                   depth_check=depth_check, depth_extend=depth_extend, depth_edge=a.depth_edge)
             errs, spr, conf, net_conf = [], [], [], []
             for k in range(n_batches):
                 evaluator.it = 300_000 + k
@@ -459,7 +461,7 @@ def compare(a, G, synth, Reconstruction, torch):
             rec = new_rec(bf16, 3 + seed, base)
             if prop is not None:
                 rec.use_proposal(prop, n_proposal=n_prop, conf_threshold=thr, n_free=n_free, depth_check=depth_check,
-                                 depth_extend=depth_extend)
+                                 depth_extend=depth_extend, depth_edge=a.depth_edge)
             t0 = time.time()
             ms, per_call, spr = run(rec, a.compare_phase2)
             r = {"ms_per_step": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2), "per_call_ms": per_call,
@@ -488,7 +490,8 @@ def compare(a, G, synth, Reconstruction, torch):
     return {
         "workload": f"{wp.name}: {M} rays per step, plain 64+32 vs proposal {n_prop} in the interval + "
                     f"{n_free} on the free space before it per confident ray (confidence >= {thr}"
-                    f"{f' and the observed depth within {depth_extend} m of the interval (stretched to it)' if depth_check else ''}, else plain "
+                    f"{f' and the observed depth within {depth_extend} m of the interval (stretched to it)' if depth_check else ''}"
+                    f"{f' and no depth step above {a.depth_edge} m to a neighbouring pixel' if a.depth_edge > 0 else ''}, else plain "
                     f"64+32), {S} smoothness pairs, {T} frames {wp.W}x{wp.H} of which every 50th is held out "
                     f"for the depth error; per seed {a.compare_phase1} shared plain steps, then "
                     f"{a.compare_phase2} steps of each; proposal trained for 12000 steps on "

@@ -175,6 +175,10 @@ typedef struct {
                               depth_extend of it, and falls back to plain samples otherwise
                               (needs conf_threshold > 0) */
   float depth_extend;      /* metres, >= 0 */
+  float depth_edge;        /* with depth_check, metres (0: off): a confident ray whose pixel has a
+                              4-neighbour in its frame with valid depth differing from D by more
+                              than depth_edge (a depth discontinuity, e.g. a silhouette) falls back
+                              to plain samples (needs out->pixel) */
 } gosurf_sample_cfg;
 
 /* A ray batch.  Written by gosurf_sample_rays, read by forward/backward.

@@ -6,6 +6,15 @@ namespace gs {
 
 constexpr int kChunks = GOSURF_MAX_SAMPLES_PER_RAY / 64;
 
+// Depth-edge test of the proposal's segment pass: the frames' depth images
+// [T][H][W], each ray's pixel, the threshold (metres; 0 = off).
+struct EdgeCheck {
+  const float* depth;
+  int H, W;
+  const long long* pixel;
+  float edge;
+};
+
 struct FieldArgs {
   Grid g;
   const float* grid;

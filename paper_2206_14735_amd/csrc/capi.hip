@@ -35,8 +35,8 @@ hipError_t launch_sample_rays_only(const SampleArgs& a, hipStream_t st);
 hipError_t launch_sample_gen_only(const SampleArgs& a, hipStream_t st);
 hipError_t launch_proposal(const PropArgs& a, bool train, int blocks, hipStream_t st);
 hipError_t launch_proposal_targets(const TargetArgs& a, hipStream_t st);
-hipError_t launch_proposal_seg(float* prop3, const float* depth, int depth_check, float extend, int M, float thr,
-                               int n_prop, int n_plain, int* seg, int* block_total, hipStream_t st);
+hipError_t launch_proposal_seg(float* prop3, const float* depth, int depth_check, float extend, const EdgeCheck& ec,
+                               int M, float thr, int n_prop, int n_plain, int* seg, int* block_total, hipStream_t st);
 int proposal_blocks(int M);
 int proposal_numel();
 hipError_t launch_colsum(const float* part, int rows, int cols, float* tmp, float* add_dst, int n_add,
@@ -289,6 +289,10 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
       return fail(GOSURF_ERR_VALUE, "the depth check needs conf_threshold > 0");
     if (c->depth_check && !(c->depth_extend >= 0.f && std::isfinite(c->depth_extend)))
       return fail(GOSURF_ERR_VALUE, "depth_extend must be finite and >= 0");
+    if (!(c->depth_edge >= 0.f && std::isfinite(c->depth_edge)))
+      return fail(GOSURF_ERR_VALUE, "depth_edge must be finite and >= 0");
+    if (c->depth_edge > 0.f && !c->depth_check) return fail(GOSURF_ERR_VALUE, "depth_edge needs depth_check");
+    if (c->depth_edge > 0.f && !out->pixel) return fail(GOSURF_ERR_NULL, "depth_edge needs out.pixel");
   }
   if (out->M != c->M || out->total != total || out->S != c->S)
     return fail(GOSURF_ERR_SHAPE, "out sizes (M=%d total=%d S=%d) do not match cfg (M=%d total=%lld S=%d)",
@@ -323,7 +327,9 @@ gosurf_status gosurf_sample_rays(const gosurf_model* model, const gosurf_frames*
   pa.span_mode = c->span_mode; pa.near_t = c->near_t; pa.far_t = c->far_t; pa.out3 = out->prop;
   if ((st = hip_check(gs::launch_proposal(pa, false, gs::proposal_blocks(c->M), s), "proposal")) != GOSURF_OK)
     return st;
-  if ((st = hip_check(gs::launch_proposal_seg(out->prop, out->depth, c->depth_check, c->depth_extend, c->M,
+  gs::EdgeCheck ec{fr->depth, fr->H, fr->W, reinterpret_cast<const long long*>(out->pixel),
+                   c->depth_check ? c->depth_edge : 0.f};
+  if ((st = hip_check(gs::launch_proposal_seg(out->prop, out->depth, c->depth_check, c->depth_extend, ec, c->M,
                                               c->conf_threshold,
                                               c->n_free + c->n_proposal,
                                               c->n_strat + c->n_near, out->seg, out->ray_of, s),

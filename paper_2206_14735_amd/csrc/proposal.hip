@@ -335,16 +335,40 @@ __global__ __launch_bounds__(256) void proposal_targets_kernel(TargetArgs A) {
 // its confidence reaches thr, else n_plain.  With depth_check, a confident ray
 // with an observed depth D > 0 outside [near, far] gets its interval extended
 // to D in prop3 if D lies within `extend` of it, and is rejected otherwise: its
-// confidence is negated in prop3 (thr > 0), which the sample generator reads.  Block b scans rays [8192 b, 8192 (b + 1)): lengths are read
+// confidence is negated in prop3 (thr > 0), which the sample generator reads.
+// With edge > 0 (and depth_check) a confident ray whose pixel has a
+// 4-neighbour in its frame with valid depth differing from D by more than
+// edge is rejected the same way: at a depth discontinuity the interval
+// around D would leave the grazed surface in front of it unsampled.
+// Block b scans rays [8192 b, 8192 (b + 1)): lengths are read
 // coalesced into LDS, each thread sums 8 consecutive rays, the 1024 partial
 // sums are scanned in LDS and the chunk-local offsets written out coalesced
 // with the chunk total in block_total[b]; a second pass adds the totals of
 // the preceding chunks.
 constexpr int kSegChunk = 8192;
+
+// true if a 4-neighbour of pixel p (frame-major index into [T][H][W]) has a
+// valid depth (> 0) that differs from D by more than ec.edge
+__device__ __forceinline__ bool at_depth_edge(const EdgeCheck& ec, long long p, float D) {
+  const long long hw = (long long)ec.H * ec.W;
+  const long long f = p / hw;
+  const int rem = (int)(p - f * hw), y = rem / ec.W, x = rem - (rem / ec.W) * ec.W;
+  const float* img = ec.depth + f * hw;
+  const int nx[4] = {x - 1, x + 1, x, x}, ny[4] = {y, y, y - 1, y + 1};
+  bool edge = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (nx[i] < 0 || nx[i] >= ec.W || ny[i] < 0 || ny[i] >= ec.H) continue;
+    const float Dn = img[(long long)ny[i] * ec.W + nx[i]];
+    if (Dn > 0.f && fabsf(Dn - D) > ec.edge) edge = true;
+  }
+  return edge;
+}
 __global__ __launch_bounds__(1024) void proposal_seg_local_kernel(float* __restrict__ prop3,
                                                                   const float* __restrict__ depth, int depth_check,
-                                                                  float extend, int M, float thr, int n_prop, int n_plain,
-                                                                  int* __restrict__ seg, int* __restrict__ block_total) {
+                                                                  float extend, EdgeCheck ec, int M, float thr,
+                                                                  int n_prop, int n_plain, int* __restrict__ seg,
+                                                                  int* __restrict__ block_total) {
   __shared__ int len[kSegChunk];
   __shared__ int part[1024];
   const int tid = threadIdx.x;
@@ -357,6 +381,10 @@ __global__ __launch_bounds__(1024) void proposal_seg_local_kernel(float* __restr
       const size_t k = (size_t)(c0 + m);
       const float conf = prop3[3 * k + 2];
       bool acc = conf >= thr;
+      if (acc && depth_check && ec.edge > 0.f && depth[k] > 0.f && at_depth_edge(ec, ec.pixel[k], depth[k])) {
+        acc = false;
+        prop3[3 * k + 2] = -conf;
+      }
       if (acc && depth_check) {
         const float D = depth[k], nr = prop3[3 * k], fr = prop3[3 * k + 1];
         if (D > 0.f && !(nr <= D && D <= fr)) {
@@ -440,12 +468,11 @@ hipError_t launch_proposal_targets(const TargetArgs& a, hipStream_t st) {
 
 // block_total: scratch of ceil(M / 8192) ints (the batch's ray_of, which the
 // sample generator overwrites afterwards)
-hipError_t launch_proposal_seg(float* prop3, const float* depth, int depth_check, float extend, int M, float thr,
-                               int n_prop, int n_plain, int* seg, int* block_total, hipStream_t st) {
+hipError_t launch_proposal_seg(float* prop3, const float* depth, int depth_check, float extend, const EdgeCheck& ec,
+                               int M, float thr, int n_prop, int n_plain, int* seg, int* block_total, hipStream_t st) {
   const int nb = (M + kSegChunk - 1) / kSegChunk;
-  hipLaunchKernelGGL(proposal_seg_local_kernel, dim3(nb), dim3(1024), 0, st, prop3, depth, depth_check, extend, M,
-                     thr,
-                     n_prop, n_plain, seg, block_total);
+  hipLaunchKernelGGL(proposal_seg_local_kernel, dim3(nb), dim3(1024), 0, st, prop3, depth, depth_check, extend, ec,
+                     M, thr, n_prop, n_plain, seg, block_total);
   hipLaunchKernelGGL(proposal_seg_add_kernel, dim3(nb), dim3(1024), 0, st, M, seg, block_total);
   return hipGetLastError();
 }

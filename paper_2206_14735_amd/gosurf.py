@@ -63,7 +63,7 @@ class SampleCfg(C.Structure):
                 ("delta_s", C.c_float), ("seed", C.c_uint64), ("step", C.c_uint32),
                 ("proposal", C.c_void_p), ("grid", C.c_void_p), ("n_proposal", C.c_int32),
                 ("conf_threshold", C.c_float), ("n_free", C.c_int32), ("depth_check", C.c_int32),
-                ("depth_extend", C.c_float)]
+                ("depth_extend", C.c_float), ("depth_edge", C.c_float)]
 
 
 class RayBatchC(C.Structure):
@@ -441,7 +441,7 @@ def gosurf_adam_step_checked(step, grid, grid_grad, grid_m, grid_v, mlp, mlp_gra
 
 
 def set_proposal(cfg, proposal, grid, n_proposal=24, conf_threshold=0.5, n_free=0, depth_check=False,
-                 depth_extend=0.0):
+                 depth_extend=0.0, depth_edge=0.0):
     """Enable (or, with proposal=None, disable) proposal-driven sampling in cfg.
     The tensors must stay alive while cfg is used."""
     cfg.proposal = None if proposal is None else _ptr(proposal, F32).value
@@ -451,6 +451,7 @@ def set_proposal(cfg, proposal, grid, n_proposal=24, conf_threshold=0.5, n_free=
     cfg.n_free = n_free
     cfg.depth_check = int(bool(depth_check))
     cfg.depth_extend = float(depth_extend)
+    cfg.depth_edge = float(depth_edge)
     return cfg
 
 

@@ -176,10 +176,11 @@ class Reconstruction:
         self.ws = G.workspace_for(self.model, M, self.total, S, dev)
 
     def use_proposal(self, proposal, n_proposal=24, conf_threshold=0.5, n_free=0, depth_check=False,
-                     depth_extend=0.0):
+                     depth_extend=0.0, depth_edge=0.0):
         """Sample with the learned proposal from now on (None: plain sampling)."""
         self.proposal = proposal
-        G.set_proposal(self.cfg, proposal, self.grid, n_proposal, conf_threshold, n_free, depth_check, depth_extend)
+        G.set_proposal(self.cfg, proposal, self.grid, n_proposal, conf_threshold, n_free, depth_check, depth_extend,
+                       depth_edge)
         self.total = G.gosurf_batch_samples(self.cfg)
         M, S = self.cfg.M, self.cfg.S
         self.batch = G.RayBatch.empty(M, self.total, S, self.device, proposal=proposal is not None)

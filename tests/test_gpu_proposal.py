@@ -95,9 +95,26 @@ def _uniforms(m, step, stream, n, seed):
     return uniform01(w.reshape(-1))[:n]
 
 
-@pytest.mark.parametrize("n_free,depth_check,extend", [(0, False, 0.0), (5, False, 0.0), (5, True, 0.0),
-                                                       (0, True, 0.3)])
-def test_proposal_driven_sampling(n_free, depth_check, extend):
+def _depth_edges(depth, pix, D, edge):
+    """Host restatement of the depth-edge rule: a 4-neighbour of the ray's
+    pixel with valid depth differing from D by more than `edge`."""
+    T, H, W = depth.shape
+    f, rem = np.divmod(pix, H * W)
+    y, x = np.divmod(rem, W)
+    out = np.zeros(len(pix), dtype=bool)
+    for dx, dy in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        xn, yn = x + dx, y + dy
+        ok = (xn >= 0) & (xn < W) & (yn >= 0) & (yn < H)
+        dn = np.zeros(len(pix), dtype=np.float32)
+        dn[ok] = depth[f[ok], yn[ok], xn[ok]]
+        out |= ok & (dn > 0) & (np.abs(dn - D) > edge)
+    return out
+
+
+@pytest.mark.parametrize("n_free,depth_check,extend,edge", [(0, False, 0.0, 0.0), (5, False, 0.0, 0.0),
+                                                            (5, True, 0.0, 0.0), (0, True, 0.3, 0.0),
+                                                            (0, True, 0.3, 0.02)])
+def test_proposal_driven_sampling(n_free, depth_check, extend, edge):
     G = _G()
     L, fr, b, grid, prop = _room(M=8, seed=7)
     M = 500
@@ -105,7 +122,7 @@ def test_proposal_driven_sampling(n_free, depth_check, extend):
     cfg = G.SampleCfg(M, 16, 8, G.SPAN_BOX, 0.1, 1e9, 0.1, 0, 0.004, 99, 3)
     gd, pd = grid.cuda(), prop.cuda()
     G.set_proposal(cfg, pd, gd, n_proposal=12, conf_threshold=0.5, n_free=n_free, depth_check=depth_check,
-                   depth_extend=extend)
+                   depth_extend=extend, depth_edge=edge)
     batch = G.gosurf_sample_rays(model, fr.to("cuda"), cfg)
     torch.cuda.synchronize()
     p3 = batch.prop.cpu().numpy()
@@ -121,12 +138,18 @@ def test_proposal_driven_sampling(n_free, depth_check, extend):
         # a confident ray whose observed depth lies outside [near, far] by at
         # most `extend` has its interval stretched to reach it; further out it
         # is rejected (confidence negated)
-        conf0 = raw[:, 2] >= 0.5
+        # with `edge`, a confident ray at a depth discontinuity of its frame is
+        # rejected first
+        at_edge = np.zeros(M, dtype=bool)
+        if edge > 0:
+            at_edge = (raw[:, 2] >= 0.5) & (D > 0) & _depth_edges(fr.depth.numpy(), batch.pixel.cpu().numpy(), D, edge)
+            assert at_edge.sum() > 0
+        conf0 = (raw[:, 2] >= 0.5) & ~at_edge
         inside = (raw[:, 0] <= D) & (D <= raw[:, 1])
         near_miss = conf0 & (D > 0) & ~inside & (raw[:, 0] - extend <= D) & (D <= raw[:, 1] + extend)
         far_miss = conf0 & (D > 0) & ~inside & ~near_miss
         rej = p3[:, 2] <= -0.5
-        assert far_miss.sum() > 0 and np.array_equal(rej, far_miss)
+        assert far_miss.sum() > 0 and np.array_equal(rej, far_miss | at_edge)
         assert np.array_equal(p3[near_miss, 0], np.minimum(raw[near_miss, 0], D[near_miss]))
         assert np.array_equal(p3[near_miss, 1], np.maximum(raw[near_miss, 1], D[near_miss]))
         assert np.array_equal(p3[~near_miss, :2], raw[~near_miss, :2])
