@@ -98,11 +98,11 @@ __device__ __forceinline__ void run_step(float (&val)[8][4], int segid, int j) {
     for (int k = 0; k < 4; ++k) val[c][k] = fmaf(dpp_f<CTRL>(val[c][k]), take, val[c][k]);
 }
 
-// Per-wave LDS staging of the scatter: 64 lanes x 32 floats, the head list
-// and the destination of each head lane's four segments.
+// Per-wave LDS staging of the scatter, indexed by the writer's rank among the
+// wave's writers (lane order), so that job k (writer k / 4, segment k % 4)
+// finds its 8 floats at val[8 k] and its destination at dst[k].
 struct ScatterStage {
-  float* val;   // [64][32]: per lane, 4 segments (by, bz) of 8 floats (bx, feature)
-  int* heads;   // [64] lane ids of the writing lanes, in lane order
+  float* val;   // [64][32]: per writer, 4 segments (by, bz) of 8 floats (bx, feature)
   int* dst;     // [64][4]: vertex row of the segment's x = 0 corner, or, for a
                 // level accumulated in LDS, ~(float offset in the block's copy)
 };
@@ -175,8 +175,7 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const S
   const int nw = __popcll(wm);
   if (writer) {
     const int rank = __popcll(wm & ((1ull << lane) - 1ull));
-    S.heads[rank] = lane;
-    float* st = S.val + lane * 32;
+    float* st = S.val + rank * 32;
     int unit = 0, plane = 0;
     if (COPIES && cpb >= 0) {
       const int ci = ls.cell & 2047, cj = (ls.cell >> 11) & 2047, ck = ls.cell >> 22;
@@ -190,16 +189,26 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const S
       *reinterpret_cast<float4*>(st + 8 * sg) = make_float4(val[c0][0], val[c0][1], val[c0][2], val[c0][3]);
       *reinterpret_cast<float4*>(st + 8 * sg + 4) = make_float4(val[c1][0], val[c1][1], val[c1][2], val[c1][3]);
       const long long row = ls.row + (long long)(sg >> 1) * ls.sy + (long long)(sg & 1) * ls.sz;
-      S.dst[4 * lane + sg] = po >= 0   ? ~(po + 4 * (int)(row - lc.off))
+      S.dst[4 * rank + sg] = po >= 0   ? ~(po + 4 * (int)(row - lc.off))
                              : COPIES && cpb >= 0 ? unit + (sg & 1) * plane + (sg >> 1) * 8
                                        : (int)row;
     }
   }
   wave_lds_fence();
+  // Eight lanes per job, eight jobs per atomic instruction.  The next
+  // instruction's values are read from LDS before the wait below, so the LDS
+  // latency overlaps the memory system's.
   const int jobs = 4 * nw;
   const int f = lane & 7;
+  int k = lane >> 3;
+  float v = 0.f;
+  int d = 0;
+  if (k < jobs) { v = S.val[8 * k + f]; d = S.dst[k]; }
   for (int base = 0; base < jobs; base += 8) {
-    const int k = base + (lane >> 3);
+    const int kn = k + 8;
+    float vn = 0.f;
+    int dn = 0;
+    if (kn < jobs) { vn = S.val[8 * kn + f]; dn = S.dst[kn]; }
     // At most two (FP32) or one (BF16) atomic instructions of this wave in
     // flight: issued back to back, a tile's atomics queue in the memory system
     // ahead of the other waves' gathers.  Measured on MI355X, backward kernel
@@ -209,13 +218,13 @@ __device__ __forceinline__ void scatter(const FieldArgs& A, float* priv, const S
     if constexpr (BF) wait_vmem_at_most<0>();
     else wait_vmem_at_most<1>();
     if (k < jobs) {
-      const int h = S.heads[k >> 2], sg = k & 3;
-      const float v = S.val[h * 32 + 8 * sg + f];
-      const int d = S.dst[4 * h + sg];
       if (d < 0) atomic_add_lds(priv + (~d) + f, v);
       else if constexpr (COPIES) atomic_add_global(A.copies + d + f, v);   // every level not in LDS has copies
       else atomic_add_global(A.grad_grid + (long long)d * 4 + f, v);
     }
+    k = kn;
+    v = vn;
+    d = dn;
   }
   wave_lds_fence();
 }
@@ -235,7 +244,6 @@ struct FieldSmem {
   float bias[32 + 32 + 16 + 32 + 16];   // b1, b2, b3, c1, c2(pad 16)
   float w3row0[32];
   float scr[kWavesPerBlock][BWD ? 2048 : 1];   // operand transposes, then scatter staging
-  int heads[kWavesPerBlock][BWD ? 64 : 1];
   int dst[kWavesPerBlock][BWD ? 256 : 1];
 };
 constexpr int kRedFloats = kWavesPerBlock * kMlpNumel;
@@ -597,7 +605,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   }
   float* scrA = BWD ? sm.scr[wave] : nullptr;
   float* scrB = BWD ? sm.scr[wave] + 32 * RSR : nullptr;
-  const ScatterStage stage{scrA, BWD ? sm.heads[wave] : nullptr, BWD ? sm.dst[wave] : nullptr};
+  const ScatterStage stage{scrA, BWD ? sm.dst[wave] : nullptr};
   // this lane's grid level (q) in registers; po >= 0 if the level is accumulated in LDS
   const LevelConst lc = level_const(A.g, q);
   const int po = ((uniform_i(A.priv_mask) >> q) & 1) ? pick_level(A.priv_off, q) : -1;
