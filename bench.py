@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--compare-seeds", type=int, default=3, help="seeds of the comparison")
     ap.add_argument("--proposal-samples", type=int, default=None,
                     help="samples in the predicted interval per confident ray (default: the workload's)")
+    ap.add_argument("--depth-midpoint", action="store_true",
+                    help="comparison: render depth with each weight at its interval's midpoint (unbiased) in both arms")
     ap.add_argument("--depth-edge", type=float, default=0.0,
                     help="proposal rays at a depth discontinuity larger than this (m) fall back to plain samples")
     ap.add_argument("--free-samples", type=int, default=None,
@@ -359,6 +361,7 @@ def compare(a, G, synth, Reconstruction, torch):
                              precision=G.BF16 if bf16 else G.FP32, loss_scale=wp.loss_scale if bf16 else 1.0,
                              grid=None if src is None else src.grid.clone(),
                              mlp=None if src is None else src.mlp.clone())
+        rec.loss_cfg.depth_midpoint = 1 if a.depth_midpoint else 0
         if src is not None:
             for n in ("grid_m", "grid_v", "mlp_m", "mlp_v"):
                 getattr(rec, n).copy_(getattr(src, n))
@@ -427,19 +430,53 @@ def compare(a, G, synth, Reconstruction, torch):
               f"(loss {ploss:.4f})", file=sys.stderr, flush=True)
         evaluator = Reconstruction(lay, held, 64, 32, M, 0, span, wp.near, wp.far, wp.trunc, seed=11 + 100 * seed,
                                    grid=base.grid, mlp=base.mlp)
+        evaluator.loss_cfg.depth_midpoint = 1 if a.depth_midpoint else 0
+
+        def surface_depth(grid, mlp, b, n1=256, n2=64):
+            """Depth of the learned surface along each ray of batch b (sampler-free): the first + to -
+            sign change of phi on n1 even samples over the ray's span, then on n2 even samples inside
+            that bracket, linearly interpolated.  NaN where phi does not cross zero."""
+            Mb = b.M
+            seg = b.seg.long()
+            lo, hi = b.t[seg[:-1]], b.t[seg[1:] - 1]
+            t = lo[:, None] + (hi - lo)[:, None] * torch.linspace(0, 1, n1, device="cuda")[None]
+            lc = evaluator.loss_cfg
+            for n, last in ((n1, False), (n2, True)):
+                sb = G.RayBatch(b.o, b.r, b.rgb, b.depth, t.reshape(-1).contiguous(),
+                                (torch.arange(Mb + 1, device="cuda", dtype=torch.int32) * n),
+                                torch.arange(Mb, device="cuda", dtype=torch.int32).repeat_interleave(n),
+                                torch.zeros(0, 3, device="cuda"), torch.zeros(0, 3, device="cuda"))
+                ws = G.workspace_for(evaluator.model, Mb, Mb * n, 0)
+                fo = G.gosurf_forward(evaluator.model, grid, mlp, sb, lc, ws)
+                phi = fo.sample_values(Mb * n)[0].view(Mb, n)
+                cross = (phi[:, :-1] > 0) & (phi[:, 1:] <= 0)
+                has = cross.any(1)
+                k = cross.float().argmax(1)
+                r_ = torch.arange(Mb, device="cuda")
+                t0, t1 = t[r_, k], t[r_, k + 1]
+                p0, p1 = phi[r_, k], phi[r_, k + 1]
+                if not last:
+                    t = t0[:, None] + (t1 - t0)[:, None] * torch.linspace(0, 1, n2, device="cuda")[None]
+                    found = has
+            d = t0 + (t1 - t0) * p0 / (p0 - p1)
+            return torch.where(found & has, d, torch.full_like(d, float("nan")))
 
         def depth_error(grid, mlp, proposal=None, n_batches=4):
-            """Rendered depth against the noise-free depth of the held-out frames, on rays with observed depth."""
+            """Rendered depth against the noise-free depth of the held-out frames, on rays with observed depth
+            (and, for the plain render, the depth of the learned surface along the same rays)."""
             evaluator.grid, evaluator.mlp = grid, mlp
             evaluator.use_proposal(proposal, n_proposal=n_prop, conf_threshold=thr, n_free=n_free,
                                    depth_check=depth_check, depth_extend=depth_extend, depth_edge=a.depth_edge)
-            errs, spr, conf, net_conf = [], [], [], []
+            errs, spr, conf, net_conf, serrs = [], [], [], [], []
             for k in range(n_batches):
                 evaluator.it = 300_000 + k
                 evaluator.sample()
                 evaluator.forward()
                 ok = evaluator.batch.depth > 0
                 errs.append((evaluator.fwd.depth_hat[ok] - dgt[evaluator.batch.pixel][ok]).abs())
+                if proposal is None:
+                    sd = surface_depth(grid, mlp, evaluator.batch)
+                    serrs.append((sd[ok] - dgt[evaluator.batch.pixel][ok]).abs())
                 spr.append(evaluator.batch.n_samples() / M)
                 if proposal is not None:
                     conf.append((evaluator.batch.prop[:, 2] >= thr).float().mean().item())
@@ -451,6 +488,15 @@ def compare(a, G, synth, Reconstruction, torch):
                                    "p99": round(1e3 * torch.quantile(e, 0.99).item(), 3),
                                    "over_50mm": round((e > 0.05).float().mean().item(), 5)},
                    "samples_per_ray": round(sum(spr) / len(spr), 2)}
+            if serrs:
+                se = torch.cat(serrs)
+                miss = torch.isnan(se)
+                sv = se[~miss]
+                out["surface_depth_l1_mm"] = {"mean": round(1e3 * sv.mean().item(), 3),
+                                              "median": round(1e3 * sv.median().item(), 3),
+                                              "p90": round(1e3 * torch.quantile(sv, 0.9).item(), 3),
+                                              "over_50mm": round((sv > 0.05).float().mean().item(), 5),
+                                              "no_crossing": round(miss.float().mean().item(), 5)}
             if conf:
                 out["confident_fraction"] = round(sum(conf) / len(conf), 4)
                 out["network_confident_fraction"] = round(sum(net_conf) / len(net_conf), 4)
@@ -478,6 +524,8 @@ def compare(a, G, synth, Reconstruction, torch):
         fp, fb = p["field"]["depth_l1_mm"], b["field"]["depth_l1_mm"]
         res["iterations_speedup"] = round(p["ms_per_step"] / b["ms_per_step"], 3)
         res["field_depth_l1_gap_mm"] = {k: round(fb[k] - fp[k], 3) for k in ("mean", "median", "p90")}
+        sp, sb_ = p["field"]["surface_depth_l1_mm"], b["field"]["surface_depth_l1_mm"]
+        res["surface_depth_l1_gap_mm"] = {k: round(sb_[k] - sp[k], 3) for k in ("mean", "median", "p90")}
         res["n_logged"] = n_logged
         return res
 
@@ -492,7 +540,8 @@ def compare(a, G, synth, Reconstruction, torch):
                     f"{n_free} on the free space before it per confident ray (confidence >= {thr}"
                     f"{f' and the observed depth within {depth_extend} m of the interval (stretched to it)' if depth_check else ''}"
                     f"{f' and no depth step above {a.depth_edge} m to a neighbouring pixel' if a.depth_edge > 0 else ''}, else plain "
-                    f"64+32), {S} smoothness pairs, {T} frames {wp.W}x{wp.H} of which every 50th is held out "
+                    f"64+32){'; depth rendered at interval midpoints in both arms' if a.depth_midpoint else ''}, "
+                    f"{S} smoothness pairs, {T} frames {wp.W}x{wp.H} of which every 50th is held out "
                     f"for the depth error; per seed {a.compare_phase1} shared plain steps, then "
                     f"{a.compare_phase2} steps of each; proposal trained for 12000 steps on "
                     f"{seeds[0]['n_logged']} logged rays; {a.compare_seeds} seeds",
@@ -501,6 +550,8 @@ def compare(a, G, synth, Reconstruction, torch):
         "iterations_speedup": summary(lambda r: r["iterations_speedup"]),
         "field_depth_l1_gap_mm": {k: summary(lambda r, k=k: r["field_depth_l1_gap_mm"][k])
                                   for k in ("mean", "median", "p90")},
+        "surface_depth_l1_gap_mm": {k: summary(lambda r, k=k: r["surface_depth_l1_gap_mm"][k])
+                                    for k in ("mean", "median", "p90")},
         "held_out_depth_l1_mm": {
             "plain_field": summary(lambda r: r["plain_fp32"]["field"]["depth_l1_mm"]["mean"]),
             "proposal_trained_field": summary(lambda r: r["bf16_proposal"]["field"]["depth_l1_mm"]["mean"]),

@@ -211,6 +211,9 @@ typedef struct {
   float lambda[6];      /* weights of rgb, depth, sdf, free-space, Eikonal, smoothness */
   float trunc;          /* truncation t: S_tr = {|D - d| <= t}, S_fs = {D - d > t} */
   float alpha_fs;       /* exponent of the free-space term (5) */
+  int32_t depth_midpoint; /* 0: d_hat = sum w_i t_i (Eq. volume_rendering; w_i belongs to the interval
+                             [t_i, t_i+1], so a sharp surface renders about half a spacing short);
+                             1: d_hat = sum w_i (t_i + t_i+1) / 2 (unbiased for any spacing) */
 } gosurf_loss_cfg;
 
 /* Forward outputs.  losses[] = {L_rgb, L_d, L_sdf, L_fs, L_eik, L_smooth,

@@ -8,7 +8,11 @@ the weight w_i = T_i alpha_i, and the expected colour and depth are
 sum_i w_i c_i and sum_i w_i d_i.
 
 Readings: the last sample has no successor, so alpha_N = 0 and its depth is
-never attributed; a sample outside the grid box has no SDF, so the opacities
+never attributed; alpha_i belongs to the interval [d_i, d_{i+1}], and the
+equation attributes its weight to d_i, so a sharp surface renders short by
+up to one spacing (half on average).  As an option (midpoint) the weight is
+attributed to (d_i + d_{i+1}) / 2 instead, which is unbiased for any
+spacing; a sample outside the grid box has no SDF, so the opacities
 of the two intervals touching it are 0; alpha is evaluated through
 log Phi_s to stay finite (1 - Phi_s(a)/Phi_s(b) = -expm1(log Phi_s(a) -
 log Phi_s(b))), and its clamp at 0 passes no gradient at exactly 0.
@@ -34,9 +38,10 @@ def weights(alpha):
     return T * alpha
 
 
-def render(phi, col, t, valid, s):
+def render(phi, col, t, valid, s, midpoint=False):
     """Returns w [R, N], c_hat [R, 3], d_hat [R], wsum [R]."""
     w = weights(alphas(phi, valid, s))
     c_hat = (w[..., None] * col).sum(1)
-    d_hat = (w * t).sum(1)
+    d = torch.cat([0.5 * (t[:, :-1] + t[:, 1:]), t[:, -1:]], 1) if midpoint else t
+    d_hat = (w * d).sum(1)
     return w, c_hat, d_hat, w.sum(1)

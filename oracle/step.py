@@ -43,6 +43,7 @@ class LossCfg:
     lambdas: tuple = (10.0, 1.0, 10.0, 1.0, 1.0, 1.0)   # rgb, depth, sdf, fs, eik, smooth
     trunc: float = 0.1
     alpha_fs: float = 5.0
+    depth_midpoint: bool = False    # d_hat from interval midpoints (see oracle.render)
 
 
 def _pad(batch):
@@ -134,7 +135,7 @@ def evaluate(grid, mlp, layout, batch, cfg=LossCfg(), want_grads=True, dtype=tor
         t32[ray_of, slot] = batch.t
         vmask = torch.from_numpy(valid)
         phi_p, col_p, t_p, g_p = pad(phi), pad(col), pad(t), pad(gphi)
-        w, c_hat, d_hat, wsum = R.render(phi_p, col_p, t_p, vmask, s)
+        w, c_hat, d_hat, wsum = R.render(phi_p, col_p, t_p, vmask, s, cfg.depth_midpoint)
         s_tr, s_fs = O.subsets(batch.depth, t32, valid, cfg.trunc)
         b = depth[:, None] - t_p
 

@@ -94,6 +94,7 @@ struct RenderArgs {
   const float* eik;     // [total] or null
   float trunc, alpha_fs;
   float lam[6];
+  int depth_mid;        // d_hat attributes w_i to (t_i + t_i+1) / 2 instead of t_i
   // forward outputs
   float* rgb_hat;
   float* depth_hat;

@@ -208,6 +208,8 @@ gosurf_status check_loss(const gosurf_loss_cfg* l) {
       return fail(GOSURF_ERR_VALUE, "lambda[%d] must be finite and >= 0", k);
   if (!(l->trunc > 0.f) || !std::isfinite(l->trunc)) return fail(GOSURF_ERR_VALUE, "trunc must be > 0");
   if (!std::isfinite(l->alpha_fs)) return fail(GOSURF_ERR_VALUE, "alpha_fs must be finite");
+  if (l->depth_midpoint != 0 && l->depth_midpoint != 1)
+    return fail(GOSURF_ERR_VALUE, "depth_midpoint %d is not 0 or 1", l->depth_midpoint);
   return GOSURF_OK;
 }
 
@@ -401,7 +403,7 @@ gosurf_status forward_launch(const gosurf_model* model, const gosurf_params* par
   gs::RenderArgs ra{};
   ra.g = g; ra.o = b->o; ra.r = b->r; ra.rgb = b->rgb; ra.depth = b->depth; ra.t = b->t; ra.seg = b->seg;
   ra.M = b->M; ra.total = b->total; ra.mlp = params->mlp; ra.out4 = out->saved; ra.eik = need_gx ? eik : nullptr;
-  ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs;
+  ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs; ra.depth_mid = loss->depth_midpoint;
   for (int k = 0; k < 6; ++k) ra.lam[k] = loss->lambda[k];
   ra.rgb_hat = out->rgb_hat; ra.depth_hat = out->depth_hat; ra.wsum = out->wsum; ra.weights = out->weights;
   ra.ray_partial = out->ray_terms ? out->ray_terms : w.ray_partial;
@@ -511,7 +513,7 @@ gosurf_status gosurf_backward(const gosurf_model* model, const gosurf_params* pa
   gs::RenderArgs ra{};
   ra.g = g; ra.o = b->o; ra.r = b->r; ra.rgb = b->rgb; ra.depth = b->depth; ra.t = b->t; ra.seg = b->seg;
   ra.M = b->M; ra.total = b->total; ra.mlp = params->mlp; ra.out4 = fwd->saved; ra.eik = nullptr;
-  ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs;
+  ra.trunc = loss->trunc; ra.alpha_fs = loss->alpha_fs; ra.depth_mid = loss->depth_midpoint;
   for (int k = 0; k < 6; ++k) ra.lam[k] = loss->lambda[k];
   ra.n_depth_rays = fwd->losses + 7;
   ra.loss_scale = loss_scale; ra.seed4 = w.seed4; ra.posw = w.posw; ra.ray_dv = w.ray_dv;

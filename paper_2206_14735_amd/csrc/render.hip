@@ -16,6 +16,7 @@ struct RayState {
   float o[3], r[3];     // ray origin and direction
   float D, I[3];
   float phi[kChunks], tt[kChunks], col[kChunks][3];
+  float da[kChunks];    // depth attributed to each sample in d_hat (its t, or the interval midpoint)
   bool valid[kChunks];
   float alpha[kChunks], T[kChunks], w[kChunks];
   float c_hat[3], d_hat, wsum;
@@ -58,16 +59,19 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
   const int nch = (R.n + 63) >> 6;   // chunks holding samples (wave-uniform)
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
+    R.da[c] = R.tt[c];
     if (c >= nch) {
       R.alpha[c] = 0.f;
       continue;
     }
     float nphi = __shfl_down(R.phi[c], 1, 64);
+    float ntt = __shfl_down(R.tt[c], 1, 64);
     int nval = __shfl_down((int)R.valid[c], 1, 64);
     if (c + 1 < kChunks) {
       const float p0 = __shfl(R.phi[c + 1], 0, 64);
+      const float t0 = __shfl(R.tt[c + 1], 0, 64);
       const int v0 = __shfl((int)R.valid[c + 1], 0, 64);
-      if (lane == 63) { nphi = p0; nval = v0; }
+      if (lane == 63) { nphi = p0; ntt = t0; nval = v0; }
     } else if (lane == 63) {
       nval = 0;
     }
@@ -75,6 +79,9 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
     float a = 0.f;
     if (R.valid[c] && nval && k + 1 < R.n && nphi < R.phi[c]) {
       a = sigmoidf_(-R.s * nphi) * -expm1f(R.s * (nphi - R.phi[c]));
+      // alpha_k belongs to the interval [t_k, t_k+1]; the midpoint variant
+      // attributes its weight to the interval's centre
+      if (A.depth_mid) R.da[c] = 0.5f * (R.tt[c] + ntt);
     }
     R.alpha[c] = a;
   }
@@ -105,7 +112,7 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
     cr += R.w[c] * R.col[c][0];
     cg += R.w[c] * R.col[c][1];
     cbl += R.w[c] * R.col[c][2];
-    dd += R.w[c] * R.tt[c];
+    dd += R.w[c] * R.da[c];
     ws += R.w[c];
   }
   R.c_hat[0] = wave_sum_dpp(cr);
@@ -195,7 +202,7 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
   float g[kChunks], Q[kChunks];
 #pragma unroll
   for (int c = 0; c < kChunks; ++c)
-    g[c] = gc[0] * R.col[c][0] + gc[1] * R.col[c][1] + gc[2] * R.col[c][2] + gd * R.tt[c];
+    g[c] = gc[0] * R.col[c][0] + gc[1] * R.col[c][1] + gc[2] * R.col[c][2] + gd * R.da[c];
   float carry = 0.f;   // Q just past the current chunk
 #pragma unroll
   for (int c = kChunks - 1; c >= 0; --c) {

@@ -74,7 +74,8 @@ class RayBatchC(C.Structure):
 
 
 class LossCfg(C.Structure):
-    _fields_ = [("lambda_", C.c_float * 6), ("trunc", C.c_float), ("alpha_fs", C.c_float)]
+    _fields_ = [("lambda_", C.c_float * 6), ("trunc", C.c_float), ("alpha_fs", C.c_float),
+                ("depth_midpoint", C.c_int32)]
 
 
 class FwdOutC(C.Structure):
@@ -223,12 +224,15 @@ def make_model(layout, precision=FP32, colour_mode=0, grad_copies=False):
     return m
 
 
-def make_loss_cfg(lambdas=(10.0, 1.0, 10.0, 1.0, 1.0, 1.0), trunc=0.1, alpha_fs=5.0):
+def make_loss_cfg(lambdas=(10.0, 1.0, 10.0, 1.0, 1.0, 1.0), trunc=0.1, alpha_fs=5.0, depth_midpoint=False):
+    """depth_midpoint: d_hat attributes each weight to its interval's midpoint (unbiased for any
+    spacing) instead of the interval's first sample (the paper's sum w_i t_i)."""
     c = LossCfg()
     for k in range(6):
         c.lambda_[k] = lambdas[k]
     c.trunc = trunc
     c.alpha_fs = alpha_fs
+    c.depth_midpoint = 1 if depth_midpoint else 0
     return c
 
 

@@ -109,7 +109,7 @@ def room_case(M=256, S=512, n_strat=64, n_near=32, frames=4, H=96, W=128, seed=3
     return L, fr, b, grid, mlp
 
 
-def oracle_weights_of(phi, col, L, b, v):
+def oracle_weights_of(phi, col, L, b, v, midpoint=False):
     """The oracle's rendering weights evaluated on given per-sample SDF and
     colour values (float64), isolating the render stage from decoder rounding."""
     import math
@@ -127,7 +127,7 @@ def oracle_weights_of(phi, col, L, b, v):
     co[ray_of, slot] = col
     s = torch.tensor(math.exp(10.0 * float(v)), dtype=torch.float64)
     w, c_hat, d_hat, ws = OR.render(torch.from_numpy(ph), torch.from_numpy(co), torch.from_numpy(tt),
-                                    torch.from_numpy(valid), s)
+                                    torch.from_numpy(valid), s, midpoint)
     return w.numpy()[ray_of, slot], c_hat.numpy(), d_hat.numpy()
 
 

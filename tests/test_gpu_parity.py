@@ -19,11 +19,11 @@ def _G():
     return G
 
 
-def run_device(L, b, grid, mlp, lambdas=LAMBDAS, loss_scale=1.0, trunc=0.1, grad_copies=False):
+def run_device(L, b, grid, mlp, lambdas=LAMBDAS, loss_scale=1.0, trunc=0.1, grad_copies=False, midpoint=False):
     G = _G()
     model = G.make_model(L, grad_copies=grad_copies)
     db = G.RayBatch.from_host(b)
-    lc = G.make_loss_cfg(lambdas, trunc)
+    lc = G.make_loss_cfg(lambdas, trunc, depth_midpoint=midpoint)
     ws = G.workspace_for(model, db.M, db.total, db.S)
     g = grid.cuda().contiguous()
     m = mlp.cuda().contiguous()
@@ -41,9 +41,9 @@ def run_device(L, b, grid, mlp, lambdas=LAMBDAS, loss_scale=1.0, trunc=0.1, grad
                 grad_grid=(gg / loss_scale).cpu().numpy(), grad_mlp=(gm / loss_scale).cpu().numpy())
 
 
-def oracle_pair(grid, mlp, L, b, lambdas=LAMBDAS, trunc=0.1):
+def oracle_pair(grid, mlp, L, b, lambdas=LAMBDAS, trunc=0.1, midpoint=False):
     """The oracle in float64 (the reference) and the same definition in float32."""
-    cfg = ostep.LossCfg(lambdas=lambdas, trunc=trunc)
+    cfg = ostep.LossCfg(lambdas=lambdas, trunc=trunc, depth_midpoint=midpoint)
     return (ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, cfg),
             ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, cfg, dtype=torch.float32))
 
@@ -52,7 +52,8 @@ def _np(x):
     return x.double().numpy() if isinstance(x, torch.Tensor) else np.asarray(x, dtype=np.float64)
 
 
-def compare(dev, ref, ref32, grads=True, fwd_tol=FWD_TOL, grad_tol=GRAD_TOL, case=None, lambdas=LAMBDAS):
+def compare(dev, ref, ref32, grads=True, fwd_tol=FWD_TOL, grad_tol=GRAD_TOL, case=None, lambdas=LAMBDAS,
+            midpoint=False):
     """Every forward value, the per-sample d(phi)/dx at the samples and the
     smoothness points, the eight loss slots and both gradients, each against
     the float64 oracle at the stated tolerance (forward 1e-5, gradients 1e-4),
@@ -77,7 +78,7 @@ def compare(dev, ref, ref32, grads=True, fwd_tol=FWD_TOL, grad_tol=GRAD_TOL, cas
     # the render stage alone, on the device's own SDF values
     if case is not None:
         L, b, mlp = case
-        w_ref, c_ref, d_ref = oracle_weights_of(dev["phi"], dev["col"], L, b, mlp[-1])
+        w_ref, c_ref, d_ref = oracle_weights_of(dev["phi"], dev["col"], L, b, mlp[-1], midpoint)
         check_close("weights (render stage)", dev["w"], w_ref, fwd_tol, entry_tol=fwd_tol)
         check_close("d_hat (render stage)", dev["d_hat"], d_ref, fwd_tol, entry_tol=fwd_tol)
     names = ["rgb", "depth", "sdf", "fs", "eik", "smooth"]
@@ -141,6 +142,19 @@ def test_room_ragged_batch_matches_oracle():
     L, fr, b, grid, mlp = room_case(M=203, S=301, n_strat=61, n_near=30)
     b = _clear(grid, mlp, L, b)
     compare(run_device(L, b, grid, mlp), *oracle_pair(grid, mlp, L, b), case=(L, b, mlp))
+
+
+@pytest.mark.parametrize("case", ["sphere", "room_ragged"])
+def test_depth_midpoint_matches_oracle(case):
+    """d_hat with each weight attributed to its interval's midpoint (the
+    unbiased variant of the depth rendering), forward and all gradients."""
+    if case == "sphere":
+        L, fr, b, grid, mlp = sphere_case(grid_std=0.3)
+    else:
+        L, fr, b, grid, mlp = room_case(M=203, S=301, n_strat=61, n_near=30)
+    b = _clear(grid, mlp, L, b)
+    compare(run_device(L, b, grid, mlp, midpoint=True), *oracle_pair(grid, mlp, L, b, midpoint=True),
+            case=(L, b, mlp), midpoint=True)
 
 
 def test_loss_scale_and_disabled_terms():

@@ -230,6 +230,28 @@ def test_rendered_depth_left_endpoint_bias():
     assert abs(float(ws[0]) - 1) < 1e-9
 
 
+def test_rendered_depth_midpoint_is_unbiased():
+    # the same sharp plane with the midpoint attribution: d_hat is the centre
+    # of the interval holding D*, so over D* spread evenly across intervals the
+    # mean error vanishes while the left-endpoint attribution's is -spacing/2
+    t = torch.linspace(0.5, 2.5, 41, dtype=torch.float64)[None]
+    h = float(t[0, 1] - t[0, 0])
+    valid = torch.ones_like(t, dtype=torch.bool)
+    errs_mid, errs_left = [], []
+    for k in range(200):
+        Dstar = 1.0 + (k + 0.5) * h / 200 * 10        # 10 intervals, evenly covered
+        _, _, d_mid, _ = R.render(Dstar - t, torch.zeros(1, 41, 3, dtype=torch.float64), t, valid,
+                                  torch.tensor(1e5, dtype=torch.float64), midpoint=True)
+        _, _, d_left, _ = R.render(Dstar - t, torch.zeros(1, 41, 3, dtype=torch.float64), t, valid,
+                                   torch.tensor(1e5, dtype=torch.float64))
+        i = int(((t[0] <= Dstar).sum()) - 1)
+        assert abs(float(d_mid[0]) - 0.5 * float(t[0, i] + t[0, i + 1])) < 1e-9
+        errs_mid.append(float(d_mid[0]) - Dstar)
+        errs_left.append(float(d_left[0]) - Dstar)
+    assert abs(np.mean(errs_mid)) < 1e-3 * h
+    assert abs(np.mean(errs_left) + h / 2) < 1e-3 * h
+
+
 def test_empty_ray_gets_no_weight():
     t = torch.linspace(0.1, 3.0, 64)[None]
     phi = 0.2 + t  # SDF increasing along the ray: no surface
