@@ -18,6 +18,17 @@
 
 namespace gs {
 
+// One step of the segmented sum inside a 16-lane group: lanes of the same run
+// add the partial of the lane D to their right (a multiply by 0 or 1, folded
+// into one v_fmac_f32 with a DPP source; the values are finite).
+template <int CTRL, int D>
+__device__ __forceinline__ void merge_step(float (&val)[12], int segid, int j) {
+  const int so = dpp_i<CTRL>(segid);
+  const float take = (j + D < 16) && so == segid ? 1.f : 0.f;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) val[c] = fmaf(dpp_f<CTRL>(val[c]), take, val[c]);
+}
+
 // packed V1[32][9] e1[32] V2[32][32] e2[32] V3[3][32] e3[3]
 constexpr int oV1 = 0, oE1 = 288, oV2 = 320, oE2 = 1344, oV3 = 1376, oE3 = 1472, kColourNumel = 1475;
 static_assert(kColourNumel == GOSURF_COLOUR_MLP_NUMEL, "colour decoder layout");
@@ -185,12 +196,28 @@ __device__ __forceinline__ void colour_tile(const ColourArgs& A, const ColourSme
     for (int k = 0; k < 4; ++k) g[k] = __shfl(din[k], j, 64);
     g[4] = __shfl(din[0], 16 + j, 64);
     g[5] = __shfl(din[1], 16 + j, 64);
-    if (valid) {
+    // Consecutive samples of a ray often share the finest cell: a segmented
+    // sum over the 16 lanes of the group (DPP row shifts) merges each run of
+    // equal cells into its first lane, which alone writes its two corners.
+    float val[12];
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) val[6 * cc + k] = valid ? wc[cc] * g[k] : 0.f;
+    const int key = valid ? (int)row0 : -1 - j;   // an invalid lane is a run of its own
+    const bool head = (j == 0) || key != dpp_i<kRowShr1>(key);
+    const unsigned grp = (unsigned)(__ballot(head) >> (16 * q)) & 0xffffu;
+    const int segid = __popc(grp & ((2u << j) - 1u));
+    merge_step<kRowShl1, 1>(val, segid, j);
+    merge_step<kRowShl2, 2>(val, segid, j);
+    merge_step<kRowShl4, 4>(val, segid, j);
+    merge_step<kRowShl8, 8>(val, segid, j);
+    if (head && valid) {
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc) {
         float* dst = A.grad_cgrid + 8 * crow[cc];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) atomic_add_global(dst + k, wc[cc] * g[k]);
+        for (int k = 0; k < 6; ++k) atomic_add_global(dst + k, val[6 * cc + k]);
       }
     }
   }
