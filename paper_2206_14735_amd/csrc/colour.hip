@@ -212,14 +212,32 @@ __device__ __forceinline__ void colour_tile(const ColourArgs& A, const ColourSme
     merge_step<kRowShl2, 2>(val, segid, j);
     merge_step<kRowShl4, 4>(val, segid, j);
     merge_step<kRowShl8, 8>(val, segid, j);
-    if (head && valid) {
+    // The writers stage their two corners by rank in the wave's scratch (8
+    // floats per corner, 6 used), then 8 lanes write one corner: the 6
+    // features of a vertex lie in one aligned 32-byte row, so each corner is
+    // one request of an atomic instruction instead of six.
+    const bool writer = head && valid;
+    const unsigned long long wm = __ballot(writer);
+    const int nw = __popcll(wm);
+    int* dsti = reinterpret_cast<int*>(scrA + 1024);   // [128] rows, after the [128][8] values
+    wave_lds_fence();   // the transposes' reads of the scratch are complete
+    if (writer) {
+      const int rank = __popcll(wm & ((1ull << lane) - 1ull));
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc) {
-        float* dst = A.grad_cgrid + 8 * crow[cc];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) atomic_add_global(dst + k, val[6 * cc + k]);
+        for (int k = 0; k < 6; ++k) scrA[16 * rank + 8 * cc + k] = val[6 * cc + k];
+        dsti[2 * rank + cc] = (int)crow[cc];
       }
     }
+    wave_lds_fence();
+    const int jobs = 2 * nw, f = lane & 7;
+    for (int base = 0; base < jobs; base += 8) {
+      const int k = base + (lane >> 3);
+      wait_vmem_at_most<1>();   // as in the field kernel's scatter: a bounded number in flight
+      if (k < jobs && f < 6) atomic_add_global(A.grad_cgrid + 8 * (long long)dsti[k] + f, scrA[8 * k + f]);
+    }
+    wave_lds_fence();   // the next tile reuses the scratch
   }
 }
 
