@@ -674,7 +674,9 @@ def main():
                               "field_kernel<backward> (gosurf_backward: samples and smoothness pairs)"),
         "field_fwd": roofline("field_fwd", field_bytes("field_fwd"), kern["field_fwd"],
                               "field_kernel<forward> (gosurf_forward: samples and smoothness pairs)"),
-        "adam": roofline("adam", BYTES_PER_PARAM_ADAM * n_par, kern["adam"], "adam_kernel (gosurf_adam_step)"),
+        # the timed launch is the step's first Adam call: the geometry grid and the decoders
+        "adam": roofline("adam", BYTES_PER_PARAM_ADAM * (rec.grid.numel() + rec.mlp.numel()), kern["adam"],
+                         "adam_kernel (gosurf_adam_step)"),
     }
     eikonal = w.lambdas[4] > 0
 
