@@ -44,6 +44,9 @@ struct FieldArgs {
   float* grad_grid;       // [V][4]
   float* mlp_partial;     // [gridDim.x][kMlpNumel]
   int need_gx;            // ray mode: compute grad phi for the Eikonal term
+  const float* depth;     // forward, optional: [M] observed depth per ray; with it, wave-tiles
+                          // with no sample in S_fs = {D - t > trunc} skip grad phi
+  float trunc;
   float* grad_x;          // backward, optional: [total][4] dL/dx of each sample (x, y, z, 0)
   int colour;             // ray mode: 1 = colour from the geometry decoder's features; 0 = no colour
                           // here (the paper's colour path runs in its own kernel)

@@ -382,6 +382,7 @@ gosurf_status forward_launch(const gosurf_model* model, const gosurf_params* par
   fa.o = b->o; fa.r = b->r; fa.t = b->t; fa.ray_of = b->ray_of; fa.total = b->total;
   fa.xs = b->xs; fa.eps = b->eps; fa.S = b->S; fa.seg_end = b->seg + b->M;
   fa.out4 = out->saved; fa.eik = eik; fa.smooth_partial = w.smooth_partial; fa.need_gx = need_gx;
+  fa.depth = b->depth; fa.trunc = loss->trunc;   // residuals are needed only in S_fs
   fa.grad_phi = out->grad_phi; fa.pair_terms = out->pair_terms;
   fa.colour = model->colour_mode == GOSURF_COLOUR_DECODED;
   if (loss->lambda[5] == 0.f) fa.S = 0;   // the smoothness pairs are skipped

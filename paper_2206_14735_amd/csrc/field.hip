@@ -266,13 +266,13 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
                                            const ScatterStage& stage, float* priv,
                                            v4f (&aW1)[2], v4f (&aW2)[4], v4f (&aW3)[2], v4f (&aU1)[2], v4f& aS,
                                            float& smooth_acc) {
-  const bool need_g = (MODE == 1) || A.need_gx || POSE;
   // ---------------- sample position
   int item;
   float px, py, pz;
   bool live;
   float4 seed_in = make_float4(0.f, 0.f, 0.f, 0.f);   // backward: dL/dphi, dL/dc of the sample
   float ew_in = 0.f;                                   // backward: its Eikonal weight
+  float b_fs = 0.f;                                    // forward: D - t of the sample (-1 without depth)
   if (MODE == 0) {
     item = tile * 16 + j;
     live = item < total;
@@ -289,6 +289,10 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
         px = mad_norm(tt, A.r[3 * ray + 0], A.o[3 * ray + 0]);
         py = mad_norm(tt, A.r[3 * ray + 1], A.o[3 * ray + 1]);
         pz = mad_norm(tt, A.r[3 * ray + 2], A.o[3 * ray + 2]);
+        if (A.depth) {
+          const float D = A.depth[ray];
+          b_fs = D > 0.f ? D - tt : -1.f;
+        }
       }
     }
   } else {
@@ -308,6 +312,18 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
     }
   }
   const bool valid = live && inside_box(A.g, px, py, pz);
+  // d(phi)/dx is needed at smoothness points, for pose refinement, and for
+  // the Eikonal term, which only samples of S_fs = {D - t > trunc} (decided in
+  // float32 as the render decides it) carry.  A wave-tile with no such sample
+  // skips the gradient of the interpolation and the decoders' d(phi)/dz,
+  // which contribute exactly zero there.
+  bool need_g = (MODE == 1) || POSE;
+  if (MODE == 0 && !POSE && A.need_gx) {
+    bool lane_fs;
+    if constexpr (BWD) lane_fs = valid && ew_in != 0.f;
+    else lane_fs = A.grad_phi != nullptr || A.depth == nullptr || (valid && b_fs > A.trunc);
+    need_g = __ballot(lane_fs) != 0ull;
+  }
   LevelSample ls;
   locate(A.g, lc, px, py, pz, ls);
   float zl[4], G[4][3];
@@ -373,8 +389,9 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
       if (q == 0 && live) {
         *reinterpret_cast<float4*>(A.out4 + 4 * (size_t)item) = make_float4(ob[0], cb[0], cb[1], cb[2]);
         if (A.need_gx) {
+          // (a tile that skipped d(phi)/dx holds no S_fs sample: its residuals are not read)
           const float n = sqrtf(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
-          A.eik[item] = (1.f - n) * (1.f - n);
+          A.eik[item] = need_g ? (1.f - n) * (1.f - n) : 0.f;
           if (A.grad_phi) {
             float* gp = A.grad_phi + 3 * (size_t)item;
             gp[0] = gx[0]; gp[1] = gx[1]; gp[2] = gx[2];
@@ -508,7 +525,7 @@ __device__ __forceinline__ void field_tile(const FieldArgs& A, const Smem& sm, i
     colsum_into(tX[1], 1, aS, j);
 
     const float dzl[4] = {dz[0], dz[1], dz[2], dz[3]};
-    if (A.need_gx) {
+    if (need_g && A.need_gx) {
       // second-order terms of the Eikonal residual
       v4f qv;
 #pragma unroll

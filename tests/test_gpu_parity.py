@@ -406,3 +406,32 @@ def test_gradient_copies_equal_the_single_buffer(precision):
     for x in (g1, g2):
         assert np.linalg.norm(x - g0) <= 1e-6 * np.linalg.norm(g0)
         assert np.all(np.abs(x - g0) <= 1e-5 * np.abs(g0).max())
+
+
+def test_tiles_without_free_space_samples_skip_the_gradient():
+    """A forward wave-tile (16 samples) with no sample in S_fs = {D - t > trunc}
+    skips d(phi)/dx, which only the Eikonal term over S_fs reads: the losses
+    and the residuals of the S_fs samples are bit for bit those of a forward
+    that computes d(phi)/dx at every sample (which asking for it forces)."""
+    from oracle import grid as OG
+    G = _G()
+    L, fr, b, grid, mlp = room_case(M=203, S=301, n_strat=61, n_near=30)
+    model = G.make_model(L)
+    db = G.RayBatch.from_host(b)
+    lc = G.make_loss_cfg(LAMBDAS, 0.1)
+    ws = G.workspace_for(model, db.M, db.total, db.S)
+    g, m = grid.cuda().contiguous(), mlp.cuda().contiguous()
+    full = G.gosurf_forward(model, g, m, db, lc, ws, grad_phi=True)
+    skip = G.gosurf_forward(model, g, m, db, lc, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(full.losses, skip.losses)
+    seg = np.asarray(b.seg)
+    ray = np.repeat(np.arange(len(seg) - 1), np.diff(seg))
+    inside = OG.inside_box_fp32(b.o[ray], b.t, b.r[ray], L.p0, L.p1)
+    D = np.asarray(b.depth, dtype=np.float32)[ray]
+    fs = inside & (D > 0) & ((D - np.asarray(b.t, dtype=np.float32)) > np.float32(0.1))
+    tiles_without = int(np.sum([not fs[k:k + 16].any() for k in range(0, len(fs), 16)]))
+    assert tiles_without > 0 and fs.any()
+    e_full = full.saved[4 * db.total:].cpu().numpy()
+    e_skip = skip.saved[4 * db.total:].cpu().numpy()
+    assert np.array_equal(e_full[fs], e_skip[fs])
