@@ -30,8 +30,8 @@ FP32_MFMA_TFLOPS = 157.3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="room")
     ap.add_argument("--frames", type=int, default=None, help="override the number of frames")
     ap.add_argument("--poses", action="store_true",
