@@ -299,3 +299,28 @@ def test_checked_adam_rejects_missing_or_misaligned_flag(lib):
     assert lib.gosurf_adam_step_checked(C.byref(c), C.byref(s), 18, None) == 3
     c.step = 0                                          # the Adam checks come first
     assert lib.gosurf_adam_step_checked(C.byref(c), C.byref(s), 16, None) == 4
+
+
+def test_binding_raises_when_the_library_is_missing(monkeypatch, tmp_path):
+    # no fallback: a missing library is an error, not a silent CPU path
+    monkeypatch.setattr(G, "_lib", None)
+    monkeypatch.setattr(G, "LIB_PATH", str(tmp_path / "libgosurf.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        G.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        G.gosurf_workspace_bytes(G.make_model(_room_layout()), 16, 16 * 96, 0)
+
+
+def test_binding_rejects_host_and_strided_tensors():
+    import torch
+    with pytest.raises(ValueError, match="GPU"):
+        G._ptr(torch.zeros(8))
+    with pytest.raises(ValueError, match="contiguous"):
+        G._ptr(torch.zeros(4, 4).t())
+    with pytest.raises(TypeError):
+        G._ptr(torch.zeros(8, dtype=torch.float64), torch.float32)
+
+
+def _room_layout():
+    import synth
+    return synth.configs.ROOM.layout()
