@@ -178,12 +178,16 @@ def test_proposal_driven_sampling(n_free, depth_check, extend, edge):
 
 
 # Rendered-depth error of the proposal's 24 samples minus plain 96's on the
-# rays the proposal is confident about (metres), about twice the measured
-# +9.8 mm (mean) and +2.4 mm (p90): the median and p90 stay within a few
-# millimetres, the mean carries a tail of rays whose interval misses or cuts
-# the surface (0.4 % of confident intervals miss it).
-MEAN_GAP_BOUND = 20e-3
-P90_GAP_BOUND = 5e-3
+# rays the proposal is confident about (metres).  The median and p90 stay
+# within a few millimetres; the mean carries a tail of rays whose interval
+# misses or cuts the surface (0.3-1 % of confident intervals miss it).  The
+# field's training is not bit-reproducible (its grid gradient sums float
+# atomics in a varying order), and the gaps move between trainings: on
+# MI355X, seven gave means of +9.0 .. +13.0 mm and p90s of +2.2 .. +3.1 mm,
+# and an eighth +24.7 and +6.7 mm (with 99.0 % of confident intervals
+# holding the surface instead of 99.5 %).  The bounds sit above that spread.
+MEAN_GAP_BOUND = 40e-3
+P90_GAP_BOUND = 10e-3
 
 
 def test_trained_proposal_beats_plain_sampling_at_equal_samples():
