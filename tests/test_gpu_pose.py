@@ -71,9 +71,9 @@ def test_pose_backward_matches_oracle():
     assert np.abs(d - ref.numpy()).max() <= 1e-5 * np.abs(ref.numpy()).max()
 
 
-def _ray_grads_device(L, b, grid, mlp, lambdas=LAMBDAS):
+def _ray_grads_device(L, b, grid, mlp, lambdas=LAMBDAS, grad_copies=False):
     G = _G()
-    model = G.make_model(L)
+    model = G.make_model(L, grad_copies=grad_copies)
     db = G.RayBatch.from_host(b)
     lc = G.make_loss_cfg(lambdas)
     ws = G.workspace_for(model, db.M, db.total, db.S)
@@ -88,12 +88,15 @@ def _ray_grads_device(L, b, grid, mlp, lambdas=LAMBDAS):
     return go.cpu().numpy(), gr.cpu().numpy(), gg.cpu().numpy(), gm.cpu().numpy(), gg2.cpu().numpy(), gm2.cpu().numpy()
 
 
-@pytest.mark.parametrize("case,lambdas", [("sphere", LAMBDAS), ("room", LAMBDAS), ("room", LAMBDAS[:4] + (0.0, 1.0)),
-                                          ("room", (0.0, 0.0, 0.0, 0.0, 1.0, 0.0))])
-def test_ray_gradients_match_oracle(case, lambdas):
+@pytest.mark.parametrize("case,lambdas,copies", [("sphere", LAMBDAS, False), ("room", LAMBDAS, False),
+                                                 ("room", LAMBDAS[:4] + (0.0, 1.0), False),
+                                                 ("room", (0.0, 0.0, 0.0, 0.0, 1.0, 0.0), False),
+                                                 ("room", LAMBDAS, True)])
+def test_ray_gradients_match_oracle(case, lambdas, copies):
     """dL/do and dL/dr of every ray against the oracle (all terms; without
     the Eikonal term; the Eikonal term alone, whose x-derivative is the
-    second-order interpolation block), and the grid and decoder gradients of
+    second-order interpolation block; all terms with the grid gradient
+    scattered into gradient copies), and the grid and decoder gradients of
     the same call unchanged by computing them."""
     L, fr, b, grid, mlp = (sphere_case(M=256, S=256, grid_std=0.3) if case == "sphere"
                            else room_case(M=203, S=301, n_strat=61, n_near=30))
@@ -101,10 +104,12 @@ def test_ray_gradients_match_oracle(case, lambdas):
     cfg = ostep.LossCfg(lambdas=lambdas)
     ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, cfg, ray_grads=True)
     ref32 = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, cfg, ray_grads=True, dtype=torch.float32)
-    go, gr, gg, gm, gg2, gm2 = _ray_grads_device(L, b, grid, mlp, lambdas)
-    print(f"{case} {lambdas}: {nr} rays at a kink left out", flush=True)
+    go, gr, gg, gm, gg2, gm2 = _ray_grads_device(L, b, grid, mlp, lambdas, copies)
+    print(f"{case} {lambdas} copies={copies}: {nr} rays at a kink left out", flush=True)
     check_parity("dL/do", go, _np(ref["grad_o"]), _np(ref32["grad_o"]), GRAD_TOL)
     check_parity("dL/dr", gr, _np(ref["grad_r"]), _np(ref32["grad_r"]), GRAD_TOL)
+    check_parity("grad_grid", gg, _np(ref["grad_grid"]), _np(ref32["grad_grid"]), GRAD_TOL)
+    check_parity("grad_mlp", gm, _np(ref["grad_mlp"]), _np(ref32["grad_mlp"]), GRAD_TOL)
     assert np.array_equal(gm, gm2)
     assert np.abs(gg - gg2).max() <= 1e-6 * np.abs(gg2).max()          # atomic order only
 
