@@ -24,9 +24,9 @@ def _np(x):
     return x.double().numpy() if isinstance(x, torch.Tensor) else np.asarray(x, dtype=np.float64)
 
 
-def _device(L, b, grid, mlp, cg, cm, lambdas=LAMBDAS, static=False):
+def _device(L, b, grid, mlp, cg, cm, lambdas=LAMBDAS, static=False, grad_copies=False):
     G = _G()
-    model = G.make_model(L, colour_mode=G.COLOUR_GRID)
+    model = G.make_model(L, colour_mode=G.COLOUR_GRID, grad_copies=grad_copies)
     db = G.RayBatch.from_host(b)
     lc = G.make_loss_cfg(lambdas)
     ws = G.workspace_for(model, db.M, db.total, db.S)
@@ -49,8 +49,10 @@ def _device(L, b, grid, mlp, cg, cm, lambdas=LAMBDAS, static=False):
     return res
 
 
-@pytest.mark.parametrize("case", ["sphere", "room"])
-def test_colour_grid_path_matches_oracle(case):
+@pytest.mark.parametrize("case,copies", [("sphere", False), ("room", False), ("room", True)])
+def test_colour_grid_path_matches_oracle(case, copies):
+    """The colour-grid path against the oracle (with copies: the geometry
+    grid's gradient scattered into gradient copies)."""
     if case == "sphere":
         L, fr, b, grid, mlp = sphere_case(M=512, S=512, grid_std=0.3)
     else:
@@ -61,7 +63,7 @@ def test_colour_grid_path_matches_oracle(case):
     kw = dict(colour_grid=cg.numpy(), colour_mlp=cm.numpy())
     ref = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, **kw)
     r32 = ostep.evaluate(grid.numpy(), mlp.numpy(), L, b, dtype=torch.float32, **kw)
-    dev = _device(L, b, grid, mlp, cg, cm, static=True)
+    dev = _device(L, b, grid, mlp, cg, cm, static=True, grad_copies=copies)
     v = ref["valid"].numpy()
     check_parity("phi", dev["phi"][v], _np(ref["phi"])[v], _np(r32["phi"])[v], FWD_TOL)
     check_parity("colour", dev["col"][v], _np(ref["col"])[v], _np(r32["col"])[v], FWD_TOL)
