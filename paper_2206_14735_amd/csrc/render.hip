@@ -1,14 +1,125 @@
 // Per-ray volume rendering, loss terms and their backward seeds.
 //
 // One wave owns one ray: lane k holds samples k, k+64, k+128, k+192, so every
-// per-sample array is read coalesced.  The transmittance is an exclusive
+// per-sample array is read coalesced; two neighbouring rays of at most 32
+// samples share a wave, one half each.  The transmittance is an exclusive
 // product scan over the ray and the backward recurrence of the opacities is a
-// suffix scan of affine maps, both with cross-lane shuffles.
+// suffix scan of affine maps, both on DPP row shifts and row broadcasts.
 #include "args.h"
 
 namespace gs {
 
 
+
+// Cross-lane steps of the per-ray scans, on DPP row shifts and readlane.  A
+// ray occupies a segment of W lanes: a whole wave (W = 64), or one half of it
+// (W = 32, two rays of at most 32 samples per wave).  sl is the lane's index
+// in its segment.
+
+// lane sl reads lane sl + 1 of its segment (the last lane reads 0)
+template <int W>
+__device__ __forceinline__ float seg_next(float v, int sl) {
+  const float x = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));  // wave_shl:1
+  return (W == 32 && sl == 31) ? 0.f : x;
+}
+template <int W>
+__device__ __forceinline__ int seg_next_i(int v, int sl) {
+  const int x = __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true);
+  return (W == 32 && sl == 31) ? 0 : x;
+}
+// lane sl reads lane sl - 1 of its segment (the first lane reads 0)
+template <int W>
+__device__ __forceinline__ float seg_prev(float v, int sl) {
+  const float x = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));  // wave_shr:1
+  return (W == 32 && sl == 0) ? 0.f : x;
+}
+__device__ __forceinline__ float lane_at(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+// the value of the segment's first / last lane
+template <int W>
+__device__ __forceinline__ float seg_first(float v, int lane) {
+  if constexpr (W == 64) return lane_at(v, 0);
+  else return lane < 32 ? lane_at(v, 0) : lane_at(v, 32);
+}
+template <int W>
+__device__ __forceinline__ float seg_last(float v, int lane) {
+  if constexpr (W == 64) return lane_at(v, 63);
+  else return lane < 32 ? lane_at(v, 31) : lane_at(v, 63);
+}
+
+// Inclusive scan over the segment (op: sum or product): inside each row of
+// 16 lanes by row shifts (lanes without a source keep their value), then the
+// row totals carried on by row broadcasts (lane 15 into row 1 and lane 47
+// into row 3; for W = 64, then lane 31 into rows 2 and 3).  Rows that a
+// broadcast does not write take the identity.
+template <int CTRL, int D, bool PROD>
+__device__ __forceinline__ float scan_step(float v, int lane) {
+  const float u = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+  if ((lane & 15) < D) return v;
+  return PROD ? v * u : v + u;
+}
+template <int W, bool PROD>
+__device__ __forceinline__ float seg_scan(float v, int lane) {
+  constexpr float id = PROD ? 1.f : 0.f;
+  v = scan_step<0x111, 1, PROD>(v, lane);   // row_shr:1
+  v = scan_step<0x112, 2, PROD>(v, lane);   // row_shr:2
+  v = scan_step<0x114, 4, PROD>(v, lane);   // row_shr:4
+  v = scan_step<0x118, 8, PROD>(v, lane);   // row_shr:8
+  const float b15 =
+      __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(id), __float_as_int(v), 0x142, 0xA, 0xF, false));
+  v = PROD ? v * b15 : v + b15;
+  if constexpr (W == 64) {
+    const float b31 =
+        __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(id), __float_as_int(v), 0x143, 0xC, 0xF, false));
+    v = PROD ? v * b31 : v + b31;
+  }
+  return v;
+}
+// the segment's sum, in every lane of the segment
+template <int W>
+__device__ __forceinline__ float seg_sum(float v, int lane) {
+  return seg_last<W>(seg_scan<W, false>(v, lane), lane);
+}
+
+// Suffix composition of the affine maps x -> b_j + a_j x over lanes j..end
+// of the segment: on return lane j holds the maps of lanes j..end composed
+// (the map of lane j applied last).  Inside each row by row shifts towards
+// lower lanes; the later rows of the segment are composed from their first
+// lanes and applied.
+template <int CTRL, int D>
+__device__ __forceinline__ void affine_step(float& a, float& b, int lane) {
+  const float a2 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), CTRL, 0xF, 0xF, true));
+  const float b2 = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(b), CTRL, 0xF, 0xF, true));
+  if ((lane & 15) + D < 16) {
+    b = b + a * b2;
+    a = a * a2;
+  }
+}
+template <int W>
+__device__ __forceinline__ void seg_affine_suffix(float& a, float& b, int lane) {
+  affine_step<0x101, 1>(a, b, lane);   // row_shl:1
+  affine_step<0x102, 2>(a, b, lane);   // row_shl:2
+  affine_step<0x104, 4>(a, b, lane);   // row_shl:4
+  affine_step<0x108, 8>(a, b, lane);   // row_shl:8
+  const int row = lane >> 4;
+  float ca = 1.f, cb = 0.f;   // the maps of the segment's later rows: x -> cb + ca x
+  if constexpr (W == 64) {
+    const float a1 = lane_at(a, 16), b1 = lane_at(b, 16);
+    const float a2 = lane_at(a, 32), b2 = lane_at(b, 32);
+    const float a3 = lane_at(a, 48), b3 = lane_at(b, 48);
+    if (row < 3) { ca = a3; cb = b3; }
+    if (row < 2) { cb = b2 + a2 * cb; ca = a2 * ca; }
+    if (row < 1) { cb = b1 + a1 * cb; ca = a1 * ca; }
+  } else {
+    const float a1 = lane_at(a, 16), b1 = lane_at(b, 16);
+    const float a3 = lane_at(a, 48), b3 = lane_at(b, 48);
+    if (row == 0) { ca = a1; cb = b1; }
+    if (row == 2) { ca = a3; cb = b3; }
+  }
+  b = b + a * cb;
+  a = a * ca;
+}
 
 struct RayState {
   int n, s0;
@@ -22,7 +133,15 @@ struct RayState {
   float c_hat[3], d_hat, wsum;
 };
 
+// Chunks of W samples per ray: 4 of 64 (up to GOSURF_MAX_SAMPLES_PER_RAY
+// samples) for a whole wave, 1 of 32 for a half.
+template <int W>
+constexpr int seg_chunks() { return W == 64 ? kChunks : 1; }
+
+template <int W>
 __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane, RayState& R) {
+  constexpr int NC = seg_chunks<W>();
+  const int sl = lane & (W - 1);
   // offsets clamped to the batch's capacity (the segment array lives on the
   // device and is not validated by the host)
   R.s0 = min(max(A.seg[m], 0), A.total);
@@ -36,10 +155,15 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
   R.I[0] = A.rgb[3 * m]; R.I[1] = A.rgb[3 * m + 1]; R.I[2] = A.rgb[3 * m + 2];
 #pragma unroll
   for (int c = 0; c < kChunks; ++c) {
-    const int k = 64 * c + lane;
     R.valid[c] = false;
     R.phi[c] = 0.f; R.tt[c] = 0.f;
     R.col[c][0] = R.col[c][1] = R.col[c][2] = 0.f;
+    R.alpha[c] = R.T[c] = R.w[c] = 0.f;
+    R.da[c] = 0.f;
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int k = W * c + sl;
     if (k < R.n) {
       const int sidx = R.s0 + k;
       const float tt = A.t[sidx];
@@ -52,30 +176,26 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
       }
     }
   }
-  // opacities: alpha_k uses sample k+1 (next lane, or lane 0 of the next chunk).
+  // opacities: alpha_k uses sample k+1 (next lane, or the first lane of the next chunk).
   // 1 - Phi(b)/Phi(a) = Phi(-b) * (1 - e^{-(a - b)}) with a = s phi_k, b = s phi_{k+1}:
   // no difference of nearly equal logarithms, so small opacities keep their
-  // relative accuracy.
-  const int nch = (R.n + 63) >> 6;   // chunks holding samples (wave-uniform)
+  // relative accuracy.  With W = 64 the chunks past the ray's end are skipped
+  // (nch is wave-uniform); with W = 32 there is one chunk.
+  const int nch = W == 64 ? (R.n + 63) >> 6 : 1;
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
+  for (int c = 0; c < NC; ++c) {
     R.da[c] = R.tt[c];
-    if (c >= nch) {
-      R.alpha[c] = 0.f;
-      continue;
-    }
-    float nphi = __shfl_down(R.phi[c], 1, 64);
-    float ntt = __shfl_down(R.tt[c], 1, 64);
-    int nval = __shfl_down((int)R.valid[c], 1, 64);
-    if (c + 1 < kChunks) {
-      const float p0 = __shfl(R.phi[c + 1], 0, 64);
-      const float t0 = __shfl(R.tt[c + 1], 0, 64);
-      const int v0 = __shfl((int)R.valid[c + 1], 0, 64);
+    if (c >= nch) continue;
+    float nphi = seg_next<W>(R.phi[c], sl);
+    float ntt = seg_next<W>(R.tt[c], sl);
+    int nval = seg_next_i<W>((int)R.valid[c], sl);
+    if (c + 1 < NC && c + 1 < nch) {
+      const float p0 = lane_at(R.phi[c + 1], 0);
+      const float t0 = lane_at(R.tt[c + 1], 0);
+      const int v0 = __builtin_amdgcn_readlane((int)R.valid[c + 1], 0);
       if (lane == 63) { nphi = p0; ntt = t0; nval = v0; }
-    } else if (lane == 63) {
-      nval = 0;
     }
-    const int k = 64 * c + lane;
+    const int k = W * c + sl;
     float a = 0.f;
     if (R.valid[c] && nval && k + 1 < R.n && nphi < R.phi[c]) {
       a = sigmoidf_(-R.s * nphi) * -expm1f(R.s * (nphi - R.phi[c]));
@@ -86,53 +206,47 @@ __device__ __forceinline__ void ray_forward(const RenderArgs& A, int m, int lane
     R.alpha[c] = a;
   }
   // transmittance: exclusive product of (1 - alpha)
-  // (one store per chunk of T and w, so that they stay in registers)
   float carry = 1.f;
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
+  for (int c = 0; c < NC; ++c) {
     float Tc = 0.f;
     if (c < nch) {
-      float v = 1.f - R.alpha[c];
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const float u = __shfl_up(v, d, 64);
-        if (lane >= d) v *= u;
-      }
-      float ex = __shfl_up(v, 1, 64);
-      if (lane == 0) ex = 1.f;
+      const float v = seg_scan<W, true>(1.f - R.alpha[c], lane);
+      float ex = seg_prev<W>(v, sl);
+      if (sl == 0) ex = 1.f;
       Tc = carry * ex;
-      carry *= __shfl(v, 63, 64);
+      if (c + 1 < NC) carry *= lane_at(v, 63);
     }
     R.T[c] = Tc;
     R.w[c] = Tc * R.alpha[c];
   }
   float cr = 0.f, cg = 0.f, cbl = 0.f, dd = 0.f, ws = 0.f;
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
+  for (int c = 0; c < NC; ++c) {
     cr += R.w[c] * R.col[c][0];
     cg += R.w[c] * R.col[c][1];
     cbl += R.w[c] * R.col[c][2];
     dd += R.w[c] * R.da[c];
     ws += R.w[c];
   }
-  R.c_hat[0] = wave_sum_dpp(cr);
-  R.c_hat[1] = wave_sum_dpp(cg);
-  R.c_hat[2] = wave_sum_dpp(cbl);
-  R.d_hat = wave_sum_dpp(dd);
-  R.wsum = wave_sum_dpp(ws);
+  R.c_hat[0] = seg_sum<W>(cr, lane);
+  R.c_hat[1] = seg_sum<W>(cg, lane);
+  R.c_hat[2] = seg_sum<W>(cbl, lane);
+  R.d_hat = seg_sum<W>(dd, lane);
+  R.wsum = seg_sum<W>(ws, lane);
 }
 
-__global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs A) {
-  const int lane = threadIdx.x & 63;
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (m >= A.M) return;
+template <int W>
+__device__ __forceinline__ void render_fwd_ray(const RenderArgs& A, int m, int lane) {
+  constexpr int NC = seg_chunks<W>();
+  const int sl = lane & (W - 1);
   RayState R;
-  ray_forward(A, m, lane, R);
+  ray_forward<W>(A, m, lane, R);
   const bool has_d = R.D > 0.f;
   float sdf = 0.f, fs = 0.f, ek = 0.f, ntr = 0.f, nfs = 0.f;
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
-    const int k = 64 * c + lane;
+  for (int c = 0; c < NC; ++c) {
+    const int k = W * c + sl;
     if (A.weights && k < R.n) A.weights[R.s0 + k] = R.w[c];
     if (!(R.valid[c] && has_d)) continue;
     const float b = R.D - R.tt[c];
@@ -147,12 +261,12 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs A) {
     }
   }
   // a ray ends at its GOSURF_MAX_SAMPLES_PER_RAY-th sample: later samples are
-  // not rendered and get weight 0
-  if (A.weights)
+  // not rendered and get weight 0 (a half-wave ray holds at most 32)
+  if (W == 64 && A.weights)
     for (int k = kChunks * 64 + lane; k < R.n; k += 64) A.weights[R.s0 + k] = 0.f;
-  sdf = wave_sum_dpp(sdf); fs = wave_sum_dpp(fs); ek = wave_sum_dpp(ek);
-  ntr = wave_sum_dpp(ntr); nfs = wave_sum_dpp(nfs);
-  if (lane == 0) {
+  sdf = seg_sum<W>(sdf, lane); fs = seg_sum<W>(fs, lane); ek = seg_sum<W>(ek, lane);
+  ntr = seg_sum<W>(ntr, lane); nfs = seg_sum<W>(nfs, lane);
+  if (sl == 0) {
     A.rgb_hat[3 * m] = R.c_hat[0];
     A.rgb_hat[3 * m + 1] = R.c_hat[1];
     A.rgb_hat[3 * m + 2] = R.c_hat[2];
@@ -170,12 +284,12 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs A) {
   }
 }
 
-__global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
-  const int lane = threadIdx.x & 63;
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (m >= A.M) return;
+template <int W>
+__device__ __forceinline__ void render_bwd_ray(const RenderArgs& A, int m, int lane) {
+  constexpr int NC = seg_chunks<W>();
+  const int sl = lane & (W - 1);
   RayState R;
-  ray_forward(A, m, lane, R);
+  ray_forward<W>(A, m, lane, R);
   const bool has_d = R.D > 0.f;
   const float invM = 1.f / (float)A.M;
   const float nd = *A.n_depth_rays;
@@ -188,69 +302,63 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
   // subset sizes
   float ntr = 0.f, nfs = 0.f;
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
+  for (int c = 0; c < NC; ++c) {
     if (!(R.valid[c] && has_d)) continue;
     const float b = R.D - R.tt[c];
     if (fabsf(b) <= A.trunc) ntr += 1.f;
     else if (b > A.trunc) nfs += 1.f;
   }
-  ntr = wave_sum_dpp(ntr);
-  nfs = wave_sum_dpp(nfs);
-  const int nch = (R.n + 63) >> 6;   // chunks holding samples (wave-uniform)
+  ntr = seg_sum<W>(ntr, lane);
+  nfs = seg_sum<W>(nfs, lane);
+  const int nch = W == 64 ? (R.n + 63) >> 6 : 1;   // chunks holding samples (uniform over the segment's wave)
 
   // dL/dw_k and the suffix recurrence Q_i = g_i alpha_i + (1 - alpha_i) Q_{i+1}
   float g[kChunks], Q[kChunks];
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c)
+  for (int c = 0; c < NC; ++c)
     g[c] = gc[0] * R.col[c][0] + gc[1] * R.col[c][1] + gc[2] * R.col[c][2] + gd * R.da[c];
   float carry = 0.f;   // Q just past the current chunk
 #pragma unroll
-  for (int c = kChunks - 1; c >= 0; --c) {
+  for (int c = NC - 1; c >= 0; --c) {
     if (c >= nch) {
       Q[c] = 0.f;
       continue;
     }
     float a = 1.f - R.alpha[c], b = g[c] * R.alpha[c];
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const float a2 = __shfl_down(a, d, 64), b2 = __shfl_down(b, d, 64);
-      if (lane + d < 64) { b = b + a * b2; a = a * a2; }
-    }
+    seg_affine_suffix<W>(a, b, lane);
     Q[c] = b + a * carry;
-    carry = __shfl(Q[c], 0, 64);
+    carry = seg_first<W>(Q[c], lane);
   }
   float dv_acc = 0.f;
   float dalpha[kChunks], act_next[kChunks];
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
+  for (int c = 0; c < NC; ++c) {
     if (c >= nch) {
       dalpha[c] = 0.f;
       continue;
     }
     // R_k = Q_{k+1}
-    float Rk = __shfl_down(Q[c], 1, 64);
-    if (c + 1 < kChunks) {
-      const float q0 = __shfl(Q[c + 1], 0, 64);
+    float Rk = seg_next<W>(Q[c], sl);
+    if (c + 1 < NC && c + 1 < nch) {
+      const float q0 = lane_at(Q[c + 1], 0);
       if (lane == 63) Rk = q0;
-    } else if (lane == 63) {
-      Rk = 0.f;
     }
     dalpha[c] = R.alpha[c] > 0.f ? R.T[c] * (g[c] - Rk) : 0.f;
   }
   const float s = R.s;
 #pragma unroll
-  for (int c = 0; c < kChunks; ++c) {
+  for (int c = 0; c < NC; ++c) {
     if (c >= nch) {
       act_next[c] = 0.f;
       continue;
     }
-    const int k = 64 * c + lane;
+    const int k = W * c + sl;
     // this interval's derivative factors (active only when alpha > 0)
     const float om = 1.f - R.alpha[c];
     const float q_here = sigmoidf_(-s * R.phi[c]);           // 1 - Phi_s(phi_k)
-    float nphi = __shfl_down(R.phi[c], 1, 64);
-    if (c + 1 < kChunks) {
-      const float p0 = __shfl(R.phi[c + 1], 0, 64);
+    float nphi = seg_next<W>(R.phi[c], sl);
+    if (c + 1 < NC && c + 1 < nch) {
+      const float p0 = lane_at(R.phi[c + 1], 0);
       if (lane == 63) nphi = p0;
     }
     const float q_next = sigmoidf_(-s * nphi);
@@ -260,12 +368,10 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
     const float d_next = -dalpha[c] * s * ratio * q_next;     // d alpha_k / d phi_{k+1}
     dv_acc += dalpha[c] * ratio * (R.phi[c] * q_here - nphi * q_next);
     // contribution of interval k-1 to phi_k
-    float from_prev = __shfl_up(d_next, 1, 64);
+    float from_prev = seg_prev<W>(d_next, sl);
     if (c > 0) {
-      const float p63 = __shfl(act_next[c - 1], 63, 64);
+      const float p63 = lane_at(act_next[c - 1], 63);
       if (lane == 0) from_prev = p63;
-    } else if (lane == 0) {
-      from_prev = 0.f;
     }
     act_next[c] = d_next;
     float dphi = d_self + from_prev;
@@ -302,15 +408,50 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
   // samples past the per-ray cap are not rendered: zero seeds and a position
   // outside the box, so that the field backward neither gathers nor scatters
   // for them (instead of reading what an earlier call left in the workspace)
-  for (int k = kChunks * 64 + lane; k < R.n; k += 64) {
-    const size_t sidx = R.s0 + k;
-    *reinterpret_cast<float4*>(A.seed4 + 4 * sidx) = make_float4(0.f, 0.f, 0.f, 0.f);
-    *reinterpret_cast<float4*>(A.posw + 4 * sidx) =
-        make_float4(A.g.p0[0] - 1.f, A.g.p0[1] - 1.f, A.g.p0[2] - 1.f, 0.f);
-  }
-  dv_acc = wave_sum_dpp(dv_acc);
+  if (W == 64)
+    for (int k = kChunks * 64 + lane; k < R.n; k += 64) {
+      const size_t sidx = R.s0 + k;
+      *reinterpret_cast<float4*>(A.seed4 + 4 * sidx) = make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4*>(A.posw + 4 * sidx) =
+          make_float4(A.g.p0[0] - 1.f, A.g.p0[1] - 1.f, A.g.p0[2] - 1.f, 0.f);
+    }
+  dv_acc = seg_sum<W>(dv_acc, lane);
   // d s / d v = 10 s
-  if (lane == 0) A.ray_dv[m] = dv_acc * 10.f * s * sc;
+  if (sl == 0) A.ray_dv[m] = dv_acc * 10.f * s * sc;
+}
+
+// One wave per ray, except that two neighbouring rays (2i, 2i + 1) of at most
+// 32 samples each share the wave of ray 2i, one half each, and the wave of
+// ray 2i + 1 ends at once: a wave's time is mostly memory latency, which the
+// two rays then share.  Both waves take the decision from the same offsets.
+__device__ __forceinline__ int ray_len(const RenderArgs& A, int m) {
+  const int s0 = min(max(A.seg[m], 0), A.total);
+  return max(min(A.seg[m + 1], A.total) - s0, 0);
+}
+__device__ __forceinline__ bool short_pair(const RenderArgs& A, int pm) {
+  return pm + 1 < A.M && ray_len(A, pm) <= 32 && ray_len(A, pm + 1) <= 32;
+}
+
+__global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int m = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (m >= A.M) return;
+  if (short_pair(A, m & ~1)) {
+    if ((m & 1) == 0) render_fwd_ray<32>(A, m + (lane >> 5), lane);
+    return;
+  }
+  render_fwd_ray<64>(A, m, lane);
+}
+
+__global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int m = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (m >= A.M) return;
+  if (short_pair(A, m & ~1)) {
+    if ((m & 1) == 0) render_bwd_ray<32>(A, m + (lane >> 5), lane);
+    return;
+  }
+  render_bwd_ray<64>(A, m, lane);
 }
 
 // ---------------------------------------------------------------- reductions (fixed order)

@@ -6,7 +6,7 @@ import torch
 import synth
 from oracle import sampler as osampler, step as ostep
 from tests.helpers import (FWD_TOL, GRAD_TOL, check_close, check_parity, clear_of_kinks, f32_layout,
-                           oracle_weights_of, room_case, sphere_case)
+                           oracle_weights_of, room_case, sphere_case, subset_batch)
 
 pytestmark = pytest.mark.gpu
 
@@ -142,6 +142,48 @@ def test_room_ragged_batch_matches_oracle():
     L, fr, b, grid, mlp = room_case(M=203, S=301, n_strat=61, n_near=30)
     b = _clear(grid, mlp, L, b)
     compare(run_device(L, b, grid, mlp), *oracle_pair(grid, mlp, L, b), case=(L, b, mlp))
+
+
+def _short_rays(b, seed=11):
+    """b with each ray cut to a window of its samples around the observed
+    depth, of a length drawn from a mix of short and long ones (0 to 91
+    samples, most at most 32).  The render kernels give two neighbouring rays
+    of at most 32 samples one wave (a half each) and other rays a wave each."""
+    from oracle import step as OS
+    rng = np.random.default_rng(seed)
+    seg, t = np.asarray(b.seg), np.asarray(b.t)
+    M = len(seg) - 1
+    short = np.array([0, 1, 2, 3, 7, 16, 24, 31, 32])
+    long_ = np.array([33, 40, 63, 64, 65, 91])
+    lens = np.where(rng.random(M) < 0.8, rng.choice(short, M), rng.choice(long_, M))
+    ts = []
+    for m in range(M):
+        tr = t[seg[m]:seg[m + 1]]
+        k = min(int(lens[m]), len(tr))
+        c = int(np.searchsorted(tr, b.depth[m])) if b.depth[m] > 0 else len(tr) // 2
+        a = min(max(c - k // 2, 0), len(tr) - k)
+        ts.append(tr[a:a + k])
+    n = np.array([len(x) for x in ts])
+    b2 = OS.Batch(b.o, b.r, b.rgb, b.depth, np.concatenate(ts).astype(np.float32),
+                  np.concatenate([[0], np.cumsum(n)]).astype(np.int32), b.xs, b.eps)
+    return b2, n
+
+
+@pytest.mark.parametrize("midpoint", [False, True])
+def test_short_rays_match_oracle(midpoint):
+    """Rays of 0 to 91 samples in a random order (203 rays, an odd count):
+    pairs of short rays rendered in one wave and the other rays one per wave,
+    forward and gradients against the oracle."""
+    L, fr, b, grid, mlp = room_case(M=203, S=301, n_strat=61, n_near=30)
+    b, n = _short_rays(b)
+    b = _clear(grid, mlp, L, b)
+    if (len(b.seg) - 1) % 2 == 0:   # keep the count odd: the last ray has no partner
+        b = subset_batch(b, np.arange(len(b.seg) - 2), np.arange(len(b.xs)))
+    n = np.diff(np.asarray(b.seg))
+    pairs = (n[0:-1:2] <= 32) & (n[1::2] <= 32)
+    assert pairs.sum() > 10 and (~pairs).sum() > 10 and len(n) % 2 == 1 and (n == 0).any()
+    compare(run_device(L, b, grid, mlp, midpoint=midpoint), *oracle_pair(grid, mlp, L, b, midpoint=midpoint),
+            case=(L, b, mlp), midpoint=midpoint)
 
 
 @pytest.mark.parametrize("case", ["sphere", "room_ragged"])
