@@ -111,15 +111,22 @@ def _depth_edges(depth, pix, D, edge):
     return out
 
 
-@pytest.mark.parametrize("n_free,depth_check,extend,edge", [(0, False, 0.0, 0.0), (5, False, 0.0, 0.0),
-                                                            (5, True, 0.0, 0.0), (0, True, 0.3, 0.0),
-                                                            (0, True, 0.3, 0.02)])
-def test_proposal_driven_sampling(n_free, depth_check, extend, edge):
+@pytest.mark.parametrize("n_free,depth_check,extend,edge,plain_n", [(0, False, 0.0, 0.0, (16, 8)),
+                                                                    (5, False, 0.0, 0.0, (16, 8)),
+                                                                    (5, True, 0.0, 0.0, (16, 8)),
+                                                                    (0, True, 0.3, 0.0, (16, 8)),
+                                                                    (0, True, 0.3, 0.02, (16, 8)),
+                                                                    (5, False, 0.0, 0.0, (40, 16))])
+def test_proposal_driven_sampling(n_free, depth_check, extend, edge, plain_n):
+    """Proposal-driven samples against the oracle.  Plain rays of 24 samples
+    and confident rays share waves two by two; with 40 + 16 plain samples a
+    plain ray takes a wave of its own (and so does its neighbour)."""
     G = _G()
     L, fr, b, grid, prop = _room(M=8, seed=7)
     M = 500
+    ns_, nn_ = plain_n
     model = G.make_model(L)
-    cfg = G.SampleCfg(M, 16, 8, G.SPAN_BOX, 0.1, 1e9, 0.1, 0, 0.004, 99, 3)
+    cfg = G.SampleCfg(M, ns_, nn_, G.SPAN_BOX, 0.1, 1e9, 0.1, 0, 0.004, 99, 3)
     gd, pd = grid.cuda(), prop.cuda()
     G.set_proposal(cfg, pd, gd, n_proposal=12, conf_threshold=0.5, n_free=n_free, depth_check=depth_check,
                    depth_extend=extend, depth_edge=edge)
@@ -157,11 +164,12 @@ def test_proposal_driven_sampling(n_free, depth_check, extend, edge):
             assert near_miss.sum() > 0
     else:
         assert np.array_equal(p3, raw)
-    lens = np.where(conf_ok, n_free + 12, 24)
+    n_plain = ns_ + nn_
+    lens = np.where(conf_ok, n_free + 12, n_plain)
     assert np.array_equal(np.diff(seg), lens) and seg[0] == 0
     # plain rays: identical to the plain sampler's rays; confident rays: n_free
     # stratified on [t_lo, near] (near-depth stream), then 12 in [near, far]
-    plain, _, _ = osampler.sample_batch(fr, L, M, 16, 8, "aabb", 0.1, 1e9, 0.1, 0, 0.004, seed=99, step=3)
+    plain, _, _ = osampler.sample_batch(fr, L, M, ns_, nn_, "aabb", 0.1, 1e9, 0.1, 0, 0.004, seed=99, step=3)
     o, r = batch.o.cpu().numpy().astype(np.float64), batch.r.cpu().numpy().astype(np.float64)
     t_lo, _ = OP.ray_span(o, r, L, "aabb", 0.1, 1e9)
     for m in range(M):
@@ -173,7 +181,7 @@ def test_proposal_driven_sampling(n_free, depth_check, extend, edge):
             assert np.allclose(tt, ref, rtol=4e-6, atol=2e-6), m
             assert np.all(np.diff(tt) >= 0)
         else:
-            assert np.allclose(tt, plain.t[24 * m:24 * (m + 1)], rtol=4e-6, atol=1e-6)
+            assert np.allclose(tt, plain.t[n_plain * m:n_plain * (m + 1)], rtol=4e-6, atol=1e-6)
     assert np.array_equal(batch.ray_of.cpu().numpy()[:seg[-1]], np.repeat(np.arange(M), lens))
 
 
