@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void colour_kernel(ColourArgs A) {
   float* scr = reinterpret_cast<float*>(smem_raw + sizeof(ColourSmem));
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
-  for (int e = tid; e < CV_END * 64; e += 256) sm.tab[e] = colour_table_value(A.cmlp, e >> 6, e & 63);
+  fill_batched<256>(sm.tab, CV_END * 64, tid, [&](int e) { return colour_table_value(A.cmlp, e >> 6, e & 63); });
   if (tid < 32) {
     sm.bias[tid] = A.cmlp[oE1 + tid];
     sm.bias[32 + tid] = A.cmlp[oE2 + tid];

@@ -160,6 +160,26 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Fills tab[0 .. n) with value(e), a value loaded from global memory, in
+// batches of 8 entries per thread: each thread then waits for 8 loads in
+// flight at once instead of one after another (block of NT threads).
+template <int NT, class F>
+__device__ __forceinline__ void fill_batched(float* tab, int n, int tid, F value) {
+  for (int e0 = tid; e0 < n; e0 += 8 * NT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT;
+      v[u] = e < n ? value(e) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NT;
+      if (e < n) tab[e] = v[u];
+    }
+  }
+}
+
 // Sum over the 64 lanes of a wave with every lane active, in a fixed order:
 // prefix sums inside each row of 16 lanes by DPP row shifts, then the row
 // totals carried on by row broadcasts (lane 15 into row 1 and lane 47 into

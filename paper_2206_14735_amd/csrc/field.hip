@@ -601,14 +601,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
 
   if constexpr (BF) {
-    for (int e = tid; e < (T_END / 4) * 64; e += kBlock) {
-      const int slot = e >> 6, l = e & 63;
-      const uint32_t lo = f2bf2(table_value(A.mlp, 4 * slot + 0, l), table_value(A.mlp, 4 * slot + 1, l));
-      const uint32_t hi = f2bf2(table_value(A.mlp, 4 * slot + 2, l), table_value(A.mlp, 4 * slot + 3, l));
-      sm.tabbf[e] = make_uint2(lo, hi);
+    // two entries (8 loads) per thread and pass, loaded before either is stored
+    for (int e0 = tid; e0 < (T_END / 4) * 64; e0 += 2 * kBlock) {
+      float v[2][4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = e0 + u * kBlock, slot = e >> 6, l = e & 63;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[u][c] = e < (T_END / 4) * 64 ? table_value(A.mlp, 4 * slot + c, l) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = e0 + u * kBlock;
+        if (e < (T_END / 4) * 64) sm.tabbf[e] = make_uint2(f2bf2(v[u][0], v[u][1]), f2bf2(v[u][2], v[u][3]));
+      }
     }
   } else {
-    for (int e = tid; e < T_END * 64; e += kBlock) sm.tab[e] = table_value(A.mlp, e >> 6, e & 63);
+    fill_batched<kBlock>(sm.tab, T_END * 64, tid, [&](int e) { return table_value(A.mlp, e >> 6, e & 63); });
   }
   if (tid < 32) {
     sm.bias[tid] = A.mlp[oB1 + tid];

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void proposal_kernel(PropArgs A) {
   PropSmem<TRAIN>& sm = *reinterpret_cast<PropSmem<TRAIN>*>(smem_raw);
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63, q = lane >> 4, j = lane & 15;
-  for (int e = tid; e < PT_END * 64; e += kBlock) sm.tab[e] = prop_table_value(A.prop, e >> 6, e & 63);
+  fill_batched<kBlock>(sm.tab, PT_END * 64, tid, [&](int e) { return prop_table_value(A.prop, e >> 6, e & 63); });
   if (tid < 64) {
     sm.bias[tid] = A.prop[pQ1 + tid];
     sm.bias[64 + tid] = A.prop[pQ2 + tid];
