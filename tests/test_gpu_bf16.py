@@ -1,8 +1,8 @@
 """BF16 precision variant: decoders on bf16 MFMA (fp32 accumulation), grid reads
 from a bf16 mirror of the fp32 masters, loss scale 2^10; rendering, losses,
 gradient accumulation and Adam in fp32.  Its error against the FP64 oracle
-(evaluated on the fp32 masters) is measured and bounded here; the measured
-values are recorded in gpurun_out/bf16_errors.json when run on the GPU."""
+(evaluated on the fp32 masters) is measured and bounded here, and the
+measured values are printed."""
 import json
 
 import numpy as np
