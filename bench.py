@@ -563,8 +563,8 @@ def compare(a, G, synth, Reconstruction, torch):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the multi-GPU sharding is a design "
-              f"described in DESIGN.md and is not run here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}): the step's sharding over several GPUs "
+              f"is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
 

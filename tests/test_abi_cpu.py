@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -324,3 +325,10 @@ def test_binding_rejects_host_and_strided_tensors():
 def _room_layout():
     import synth
     return synth.configs.ROOM.layout()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: any other count exits with a message before touching a device
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
